@@ -1,0 +1,109 @@
+"""Tier B oracle: the closed-shell working equations (Appendix B), any size.
+
+Literal transcription, in FP64 numpy on full (unpacked) N x N orbital pairs,
+of the restricted closed-shell equations: the factor of two of spin
+integration is written into W, W~, Delta h and the zero-body term, and gamma is
+the per-spin one-body density (here a real symmetric N x N matrix; for a
+closed-shell determinant the projector onto the occupied orbitals).
+
+Grid sums are implicit in the paper (Einstein convention over the grid index i
+in eq. tcmf:2el); the permutation operator P^{(pq)}_{(rs)} there is read as
+f(pq, rs) + f(rs, pq).
+
+Orbital-subset restriction: Delta U[pq, rs] only involves grid intermediates
+of pairs inside {p, q, r, s} and the occupied orbitals, so calling ``closed_shell``
+with phi restricted to S = occ + any other orbitals returns the exact S-blocks
+of V2 and h1 and the exact E0.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .jastrow import grad1, grad1_basis
+
+
+def grid_K(xyz, w, phi, jas, rows, grad=None):
+    """V_r^s(i) for the grid rows ``rows`` (a slice), [3][len][N][N]:
+    sum_j w_j phi_r(j) grad_1 u(r_i, r_j) phi_s(j)."""
+    d = grad1(xyz[rows], xyz, jas) if grad is None else grad(xyz[rows], xyz)
+    N = phi.shape[0]
+    rho_j = ((phi * w)[:, None, :] * phi[None, :, :]).reshape(N * N, -1)   # [rs][j]
+    K = np.einsum("xij,aj->xia", d, rho_j, optimize=True)
+    return K.reshape(3, -1, N, N)
+
+
+def intermediates(rho, K, gamma):
+    """eq. tcmf:inter (closed shell) for a block of grid points.
+
+    rho [i][r][s], K [3][i][r][s] (V in the paper), gamma [N][N].
+    Returns A [i][r][s] and B [3][i][r][s]."""
+    W = 2.0 * np.einsum("xitu,tu->xi", K, gamma)                  # W = 2 V_t^u g^t_u
+    X = np.einsum("xits,tu->xius", K, gamma)                       # X_u^s = V_t^s g^t_u
+    Zt = np.einsum("xiru,xius->irs", K, X)                         # Z~ = V_r^u . X_u^s
+    Vt = np.einsum("xi,xirs->irs", W, K)                           # V~ = W . V
+    A = Vt - Zt
+    Wt = 2.0 * np.einsum("itu,tu->i", rho, gamma)                  # W~ = 2 rho_t^u g^t_u
+    Y = np.einsum("xiru,tu->xirt", K, gamma)                       # Y_r^t = V_r^u g^t_u
+    Z = (np.einsum("iru,xius->xirs", rho, X)
+         + np.einsum("xirt,its->xirs", Y, rho))                    # Z = rho X + Y rho
+    B = 0.5 * Wt[None, :, None, None] * K - Z
+    return A, B
+
+
+def closed_shell(xyz, w, phi, gamma, jas, block=512, grad=None, return_f=False):
+    """V2 [N]^4 (V2[p,q,r,s] = Delta U_{pr}^{qs}), h1 [N][N] and E0.
+
+    ``gamma`` may be an (N x N) matrix or an index array of occupied orbitals."""
+    N, Ng = phi.shape
+    gamma = _as_gamma(gamma, N)
+    f = np.zeros((N * N, N * N))
+    for i0 in range(0, Ng, block):
+        rows = slice(i0, min(Ng, i0 + block))
+        K = grid_K(xyz, w, phi, jas, rows, grad)
+        rho = w[rows, None, None] * phi[:, rows].T[:, :, None] * phi[:, rows].T[:, None, :]
+        A, B = intermediates(rho, K, gamma)
+        nb = rho.shape[0]
+        # f(pq, rs) = sum_i rho_pq(i) A_rs(i) + V_pq(i) . B_rs(i)
+        f += rho.reshape(nb, -1).T @ A.reshape(nb, -1)
+        for x in range(3):
+            f += K[x].reshape(nb, -1).T @ B[x].reshape(nb, -1)
+    # eq. tcmf:2el: Delta U_pr^qs = -(f(pq, rs) + f(rs, pq))
+    V2 = -(f + f.T).reshape(N, N, N, N)
+    h1 = one_body_from_V2(V2, gamma)
+    E0 = zero_body_from_h1(h1, gamma)
+    if return_f:
+        return V2, h1, E0, f.reshape(N, N, N, N)
+    return V2, h1, E0
+
+
+def one_body_from_V2(V2, gamma):
+    """Appendix B: Delta h_p^q = -1/2 (2 Delta U_pr^qs g^r_s - Delta U_pr^sq g^r_s),
+    with Delta U_pr^qs = V2[p,q,r,s] and Delta U_pr^sq = V2[p,s,r,q]."""
+    return -0.5 * (2.0 * np.einsum("pqrs,rs->pq", V2, gamma)
+                   - np.einsum("psrq,rs->pq", V2, gamma))
+
+
+def zero_body_from_h1(h1, gamma):
+    """Appendix B: <Psi0|L|Psi0> = -(2/3) Delta h_p^q g^p_q."""
+    return -(2.0 / 3.0) * float(np.einsum("pq,pq->", h1, gamma))
+
+
+def _as_gamma(gamma, N):
+    g = np.asarray(gamma)
+    if g.ndim == 2:
+        return g.astype(np.float64)
+    G = np.zeros((N, N))
+    for k in g:
+        G[int(k), int(k)] = 1.0
+    return G
+
+
+def subset(phi, occ, extra):
+    """Orbital subset S = occ + extra (in that order) and occ's positions in S."""
+    S = [int(k) for k in occ] + [int(k) for k in extra if int(k) not in set(map(int, occ))]
+    return np.array(S), np.arange(len(occ))
+
+
+def basis_grad(k):
+    """Gradient generator for the k-th power basis function, for grid_K(grad=...)."""
+    return lambda xa, xb: grad1_basis(xa, xb, k)

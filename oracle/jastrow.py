@@ -1,0 +1,65 @@
+"""Electron-electron Jastrow u(r12) and its first-argument gradient (oracle).
+
+The three-body integrals contain grad_1 u(r1, r2) (Theory, definition of L);
+for u depending only on r12 = |r1 - r2| this is u'(r12) (r1 - r2)/r12.
+At coincident points (r12 == 0 exactly) the paper is silent; the gradient of
+an isotropic function is taken as zero there (it is bounded by max u').
+
+Supported forms (parameters are plain Python values):
+* Pade:  u = r / (2 (1 + b r)),        u' = 1 / (2 (1 + b r)^2)
+* power: u = sum_k c_k t^k, t = r/(1+r), u' = sum_k k c_k t^(k-1) / (1 + r)^2
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def u_of_r(r, kind: str, b: float = 1.0, coef=()):
+    r = np.asarray(r, dtype=np.float64)
+    if kind == "pade":
+        return r / (2.0 * (1.0 + b * r))
+    if kind == "power":
+        t = r / (1.0 + r)
+        return sum(c * t ** (k + 1) for k, c in enumerate(coef))
+    raise ValueError(kind)
+
+
+def du_dr(r, kind: str, b: float = 1.0, coef=()):
+    r = np.asarray(r, dtype=np.float64)
+    if kind == "pade":
+        return 1.0 / (2.0 * (1.0 + b * r) ** 2)
+    if kind == "power":
+        t = r / (1.0 + r)
+        s = sum((k + 1) * c * t ** k for k, c in enumerate(coef))
+        return s / (1.0 + r) ** 2
+    raise ValueError(kind)
+
+
+def basis_du_dr(r, k: int):
+    """d/dr of the k-th power basis function t^k (k >= 1): k t^(k-1)/(1+r)^2."""
+    r = np.asarray(r, dtype=np.float64)
+    t = r / (1.0 + r)
+    return k * t ** (k - 1) / (1.0 + r) ** 2
+
+
+def grad1(xa: np.ndarray, xb: np.ndarray, jas) -> np.ndarray:
+    """grad_1 u(r_a, r_b) for all pairs: array [3][len(xa)][len(xb)].
+
+    ``jas`` has attributes kind, b, coef.  Zero where r_a == r_b exactly.
+    """
+    d = xa[:, None, :] - xb[None, :, :]            # [na][nb][3]
+    r = np.sqrt(np.sum(d * d, axis=2))
+    up = du_dr(r, jas.kind, jas.b, jas.coef)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        f = np.where(r > 0.0, up / np.where(r > 0.0, r, 1.0), 0.0)
+    return np.moveaxis(d * f[:, :, None], 2, 0)
+
+
+def grad1_basis(xa: np.ndarray, xb: np.ndarray, k: int) -> np.ndarray:
+    """grad_1 of the k-th power basis function, [3][na][nb], zero at r == 0."""
+    d = xa[:, None, :] - xb[None, :, :]
+    r = np.sqrt(np.sum(d * d, axis=2))
+    up = basis_du_dr(r, k)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        f = np.where(r > 0.0, up / np.where(r > 0.0, r, 1.0), 0.0)
+    return np.moveaxis(d * f[:, :, None], 2, 0)
