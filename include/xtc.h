@@ -1,0 +1,164 @@
+/*
+ * xtc.h -- C ABI of libxtc: the xTC folding of the transcorrelated three-body
+ * operator into effective zero-, one- and two-body terms, on one MI355X.
+ *
+ * What is computed (Christlmaier et al., "xTC: An efficient treatment of
+ * three-body interactions in transcorrelated methods"):
+ *
+ *   grid intermediate (Theory, definition under eq. Ldecomp)
+ *     K^x_pq(g) = sum_g' w_g' d^x(g,g') phi_p(g') phi_q(g'),
+ *     d^x(g,g') = (r_g - r_g')_x u'(|r_g - r_g'|) / |r_g - r_g'|  (0 at r_g == r_g')
+ *   closed-shell intermediates and two-body correction (Appendix B, eq. tcmf:2el,
+ *   eq. tcmf:inter)    V2[p][q][r][s] = Delta U_pr^qs
+ *   one-body correction (Appendix B)  h1[p][q] = Delta h_p^q
+ *   zero-body term (Appendix B)       E0 = <Psi0|L|Psi0> = -(2/3) sum_k h1[k][k]
+ *
+ * Conventions shared by every entry point
+ *   - Orbitals are real.  p,q,r,s in [0,N).  A pair index P = pair(p,q), p <= q,
+ *     enumerates the upper triangle row by row:
+ *       pair(p,q) = p*N - p*(p-1)/2 + (q-p),   Npair = N(N+1)/2.
+ *     Pair-indexed device arrays have a padded leading dimension
+ *     ldP = xtc_pair_ld(N) >= Npair (a multiple of 128); columns [Npair, ldP)
+ *     are written as zero and otherwise ignored.
+ *   - All array pointers are DEVICE pointers owned by the caller unless marked
+ *     HOST.  The library never allocates, frees or retains caller memory.
+ *   - Scratch memory is a caller-provided device workspace of at least
+ *     xtc_workspace_size() bytes (256-byte aligned).  Between xtc_prepare and
+ *     the last call of a pass it carries state (the prepared operands and the
+ *     FP64 accumulators of the two- and one-body terms); do not share one
+ *     workspace between passes that overlap in time.
+ *   - Every call is asynchronous and stream-ordered on `stream` (a hipStream_t
+ *     passed as void*, NULL = the default stream).  It returns after host-side
+ *     validation and kernel launch; no call synchronises the host.
+ *   - On any non-OK status nothing has been launched and no output or
+ *     workspace byte has been written, except XTC_E_HIP which reports a failed
+ *     launch (earlier kernels of the same call may have run).  The message of
+ *     the last failure on the calling thread is returned by xtc_last_error().
+ *   - NaN and Inf in the inputs are not checked; they propagate.
+ */
+#ifndef XTC_H
+#define XTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    XTC_OK = 0,
+    XTC_E_ARG = -1,          /* invalid argument (see each call)                      */
+    XTC_E_WORKSPACE = -2,    /* workspace NULL, misaligned or smaller than required   */
+    XTC_E_HIP = -3,          /* a HIP runtime call or kernel launch failed            */
+    XTC_E_UNSUPPORTED = -4   /* valid but unsupported combination                     */
+} xtc_status;
+
+/* Arithmetic of the two bulk contractions (K build and two-body assembly).
+ * XTC_FP64   : FP64 MFMA throughout.
+ * XTC_FP32   : FP32 MFMA products, FP32 accumulation within blocks of grid
+ *              points, FP64 accumulation across blocks.
+ * XTC_BF16X3 : operands split a = a0 + a1 (a0 = bf16(a), a1 = bf16(a - a0));
+ *              products a0 b0 + a0 b1 + a1 b0 on BF16 MFMA, FP32 accumulation
+ *              within blocks, FP64 across blocks.
+ * XTC_BF16X6 : three-way split a = a0 + a1 + a2; the six products of total
+ *              order <= 2 (a0b0, a0b1, a1b0, a0b2, a1b1, a2b0).
+ * In every form the occupied-occupied block of K, the intermediates and the
+ * one- and zero-body reductions are computed in FP64. */
+typedef enum { XTC_FP64 = 0, XTC_FP32 = 1, XTC_BF16X3 = 2, XTC_BF16X6 = 3 } xtc_prec;
+
+/* flags of the contraction calls */
+enum {
+    XTC_RESET = 1,       /* zero the accumulator before adding this chunk           */
+    XTC_FINALIZE = 2     /* after adding this chunk, write the outputs              */
+};
+
+/* Electron-electron Jastrow u(r12) (paper: Theory, Jastrow factorisation; the
+ * build uses electron-electron forms only).  Passed by value; no lifetime.
+ *   kind 0 (Pade) : u = r / (2 (1 + b r)),                 b >= 0, finite
+ *   kind 1 (power): u = sum_{k=1..ncoef} coef[k-1] t^k,    t = r/(1+r), 1 <= ncoef <= 16 */
+typedef struct {
+    int32_t kind;
+    int32_t ncoef;
+    double b;
+    double coef[16];
+} xtc_jastrow;
+
+/* The problem: orbitals on a weighted grid and the occupied orbitals of a
+ * closed-shell determinant (gamma = projector onto occ, per spin; the factor
+ * two of spin integration is in the equations, Appendix B).
+ *   xyz [Ng][3] bohr, w [Ng], phi [N][Ng] (orthonormal under w: not checked),
+ *   occ [nocc] HOST int32, distinct, in [0,N). */
+typedef struct {
+    int32_t N;
+    int32_t Ng;
+    int32_t nocc;
+    int32_t reserved;        /* must be 0 */
+    const double *xyz;
+    const double *w;
+    const double *phi;
+    const int32_t *occ;      /* HOST */
+} xtc_problem;
+
+/* Padded leading dimension of pair-indexed arrays: Npair rounded up to 128. */
+int32_t xtc_pair_ld(int32_t N);
+
+/* Bytes of workspace needed for problem `pb` with contraction arithmetic
+ * `prec` and grid chunks of at most `chunk_rows` rows (1 <= chunk_rows <= Ng).
+ * Returns 0 for invalid arguments (message in xtc_last_error()). */
+size_t xtc_workspace_size(const xtc_problem *pb, int32_t prec, int32_t chunk_rows);
+
+/* Prepare a pass: tabulate the weighted pair densities rho_pq(g) = w_g phi_p phi_q
+ * (eq. tcmf:inter) and grid positions in the workspace, in FP64 and in the
+ * operand format of `prec`, copy occ to the device and zero the accumulators.
+ * Must precede the other calls of a pass; reads xyz, w, phi, occ. */
+xtc_status xtc_prepare(const xtc_problem *pb, int32_t prec, int32_t chunk_rows,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Build the grid intermediate (Theory, definition of V under eq. Ldecomp) for
+ * output rows g in [g0, g1):
+ *   K[x][g-g0][P] = sum_{g'=0}^{Ng-1} w_g' d^x(g,g') phi_p(g') phi_q(g'),  x = 0,1,2
+ * K: device [3][g1-g0][ldP] FP64 (columns >= Npair written as 0).
+ * The gradient is taken with respect to the first argument of u (the
+ * electron sitting on grid point g).  In the reduced forms the occupied-
+ * occupied pairs are recomputed in FP64.
+ * Errors: XTC_E_ARG for !(0 <= g0 < g1 <= Ng), g1-g0 > chunk_rows of the
+ * workspace, bad Jastrow, NULL K. */
+xtc_status xtc_build_K(const xtc_problem *pb, const xtc_jastrow *jas,
+                       int32_t g0, int32_t g1, int32_t prec, double *K,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Two-body correction (Appendix B / eq. tcmf:2el).  From K of rows [g0,g1)
+ * (as written by xtc_build_K) form the closed-shell intermediates A, B
+ * (eq. tcmf:inter) and add
+ *   M[P][R] += sum_{g in [g0,g1)} rho_P(g) A_R(g) + K_P(g) . B_R(g)
+ * into the FP64 accumulator in the workspace.  With XTC_FINALIZE, write
+ *   V2[p][q][r][s] = Delta U_pr^qs = -(M[pair(p,q)][pair(r,s)] + M[pair(r,s)][pair(p,q)])
+ * to V2 (device [N][N][N][N] FP64, chemist order (pq|rs)); the eight index
+ * symmetries hold bitwise.  V2 may be NULL unless XTC_FINALIZE is set. */
+xtc_status xtc_contract_2body(const xtc_problem *pb, const double *K,
+                              int32_t g0, int32_t g1, int32_t prec, int32_t flags,
+                              double *V2, void *ws, size_t ws_bytes, void *stream);
+
+/* One- and zero-body corrections (Appendix B), as an FP64 grid reduction.
+ * Substituting eq. tcmf:2el into the one-body equation of Appendix B gives,
+ * per grid point, with k over occ, rb = sum_k rho_kk, kb = sum_k K_kk,
+ * a = sum_k A_kk, b = sum_k B_kk:
+ *   h1[p][q] += rho_pq a + K_pq.b + rb A_pq + kb.B_pq
+ *              - 1/2 sum_k (rho_pk A_kq + K_pk.B_kq + rho_qk A_kp + K_qk.B_kp)
+ * With XTC_FINALIZE, write h1 (device [N][N] FP64, symmetric bitwise) and
+ * E0 = -(2/3) sum_k h1[k][k] (device, one FP64).  The reduction is always
+ * FP64; `prec` names the arithmetic the workspace was prepared for.
+ * h1 and E0 may be NULL unless XTC_FINALIZE is set. */
+xtc_status xtc_contract_1body_0body(const xtc_problem *pb, const double *K,
+                                    int32_t g0, int32_t g1, int32_t prec, int32_t flags,
+                                    double *h1, double *E0,
+                                    void *ws, size_t ws_bytes, void *stream);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char *xtc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XTC_H */

@@ -1,0 +1,369 @@
+// libxtc: C ABI (include/xtc.h) over the gfx950 kernels.
+//
+// Host side only validates, lays out the caller's workspace and launches.
+// Workspace layout (all offsets 256-byte aligned), for ldP = xtc_pair_ld(N)
+// and ngp = Ng rounded up to 128:
+//   pos    [ngp] x 4 doubles          grid positions (x, y, z, 0)
+//   rho    [ngp][ldP] doubles         weighted pair densities, zero padded
+//   lp     reduced-precision operands of the K build (prec != FP64)
+//   M      [ldP][ldP] doubles         FP64 accumulator of the two-body term
+//   h1acc  [ldP] doubles              FP64 accumulator of the one-body term
+//   T1     [kT1Split][ldP] doubles    per-split partials (one-body, term 1)
+//   E      [kESplit][N][N] doubles    per-split partials (one-body, exchange)
+//   S      [cap][8] doubles           per-point scalars of the current chunk
+//   D      [4][cap][ldP] doubles      A, Bx, By, Bz of the current chunk
+// The chunk capacity `cap` is the largest multiple of 4 rows that fits in the
+// bytes the caller passes, so every call with the same ws_bytes agrees on it.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/xtc.h"
+#include "kernels_build_k.h"
+#include "kernels_contract.h"
+#include "kernels_prepare.h"
+
+using namespace xtc;
+
+namespace {
+
+thread_local std::string g_err;
+
+xtc_status fail(xtc_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+xtc_status fail(xtc_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+constexpr int kT1Split = 64;
+constexpr int kESplitMax = 256;
+constexpr size_t kAlign = 256;
+constexpr int kMaxN = 256;
+constexpr size_t kLdsMax = 160 * 1024;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int pair_ld(int N) {
+    const long npair = (long)N * (N + 1) / 2;
+    return (int)((npair + kPairTile - 1) / kPairTile * kPairTile);
+}
+
+struct Layout {
+    int N, Ng, nocc, ldP, ngp, Npair;
+    size_t pos, rho, lp, M, h1acc, T1, E, S, D;
+    size_t fixed;        // bytes before S
+    size_t per_row;      // bytes per chunk row (S + D)
+    int cap;             // chunk rows that fit (multiple of 4)
+};
+
+size_t lp_bytes(int prec, int ngp, int ldP) {
+    switch (prec) {
+        case XTC_FP64: return 0;
+        default: return 0;   // reduced-precision operand formats are added with their kernels
+    }
+}
+
+Layout make_layout(const xtc_problem* pb, int prec) {
+    Layout L{};
+    L.N = pb->N;
+    L.Ng = pb->Ng;
+    L.nocc = pb->nocc;
+    L.ldP = pair_ld(pb->N);
+    L.Npair = pb->N * (pb->N + 1) / 2;
+    L.ngp = (int)align_up((size_t)pb->Ng, kGridPad);
+    size_t off = 0;
+    L.pos = off;   off = align_up(off + (size_t)L.ngp * 4 * sizeof(double), kAlign);
+    L.rho = off;   off = align_up(off + (size_t)L.ngp * L.ldP * sizeof(double), kAlign);
+    L.lp = off;    off = align_up(off + lp_bytes(prec, L.ngp, L.ldP), kAlign);
+    L.M = off;     off = align_up(off + (size_t)L.ldP * L.ldP * sizeof(double), kAlign);
+    L.h1acc = off; off = align_up(off + (size_t)L.ldP * sizeof(double), kAlign);
+    L.T1 = off;    off = align_up(off + (size_t)kT1Split * L.ldP * sizeof(double), kAlign);
+    L.E = off;     off = align_up(off + (size_t)kESplitMax * L.N * L.N * sizeof(double), kAlign);
+    L.fixed = off;
+    L.per_row = (size_t)8 * sizeof(double) + (size_t)4 * L.ldP * sizeof(double);
+    L.cap = 0;
+    return L;
+}
+
+// Chunk capacity that `bytes` allows, and the offsets of S and D for it.
+void place_chunk(Layout& L, size_t bytes) {
+    const size_t slack = 2 * kAlign;
+    long cap = bytes > L.fixed + slack ? (long)((bytes - L.fixed - slack) / L.per_row) : 0;
+    cap = cap / 4 * 4;
+    if (cap > (long)align_up((size_t)L.Ng, 4)) cap = (long)align_up((size_t)L.Ng, 4);
+    L.cap = (int)cap;
+    L.S = L.fixed;
+    L.D = align_up(L.S + (size_t)cap * 8 * sizeof(double), kAlign);
+}
+
+size_t lds_intermediates(const Layout& L) { return (size_t)L.nocc * L.N * 4 * sizeof(double); }
+
+xtc_status check_problem(const xtc_problem* pb) {
+    if (!pb) return fail(XTC_E_ARG, "problem is NULL");
+    if (pb->reserved != 0) return fail(XTC_E_ARG, "problem.reserved must be 0");
+    if (pb->N < 1 || pb->N > kMaxN) return fail(XTC_E_ARG, "N=%d outside [1,%d]", pb->N, kMaxN);
+    if (pb->Ng < 1) return fail(XTC_E_ARG, "Ng=%d < 1", pb->Ng);
+    if (pb->nocc < 1 || pb->nocc > pb->N || pb->nocc > kMaxOcc)
+        return fail(XTC_E_ARG, "nocc=%d outside [1,min(N,%d)]", pb->nocc, kMaxOcc);
+    if (!pb->xyz || !pb->w || !pb->phi || !pb->occ) return fail(XTC_E_ARG, "NULL array in problem");
+    std::vector<char> seen(pb->N, 0);
+    for (int i = 0; i < pb->nocc; ++i) {
+        const int k = pb->occ[i];
+        if (k < 0 || k >= pb->N) return fail(XTC_E_ARG, "occ[%d]=%d outside [0,N)", i, k);
+        if (seen[k]) return fail(XTC_E_ARG, "occ[%d]=%d repeated", i, k);
+        seen[k] = 1;
+    }
+    if ((size_t)pb->nocc * pb->N * 4 * sizeof(double) > kLdsMax)
+        return fail(XTC_E_UNSUPPORTED, "nocc*N=%d exceeds the on-chip staging of the intermediates",
+                    pb->nocc * pb->N);
+    return XTC_OK;
+}
+
+xtc_status check_prec(int prec) {
+    if (prec != XTC_FP64 && prec != XTC_FP32 && prec != XTC_BF16X3 && prec != XTC_BF16X6)
+        return fail(XTC_E_ARG, "prec=%d unknown", prec);
+    if (prec != XTC_FP64) return fail(XTC_E_UNSUPPORTED, "prec=%d not available in this build", prec);
+    return XTC_OK;
+}
+
+xtc_status check_jastrow(const xtc_jastrow* j, JasDev* out) {
+    if (!j) return fail(XTC_E_ARG, "jastrow is NULL");
+    JasDev d{};
+    d.kind = j->kind;
+    if (j->kind == 0) {
+        if (!(std::isfinite(j->b) && j->b >= 0.0)) return fail(XTC_E_ARG, "Pade b=%g must be finite and >= 0", j->b);
+        d.b = j->b;
+        d.ncoef = 0;
+    } else if (j->kind == 1) {
+        if (j->ncoef < 1 || j->ncoef > 16) return fail(XTC_E_ARG, "ncoef=%d outside [1,16]", j->ncoef);
+        for (int k = 0; k < j->ncoef; ++k) {
+            if (!std::isfinite(j->coef[k])) return fail(XTC_E_ARG, "coef[%d] not finite", k);
+            d.dcoef[k] = (k + 1) * j->coef[k];
+        }
+        d.ncoef = j->ncoef;
+    } else {
+        return fail(XTC_E_ARG, "jastrow kind=%d unknown", j->kind);
+    }
+    *out = d;
+    return XTC_OK;
+}
+
+xtc_status check_ws(const Layout& L, void* ws, size_t bytes) {
+    if (!ws) return fail(XTC_E_WORKSPACE, "workspace is NULL");
+    if ((uintptr_t)ws % kAlign) return fail(XTC_E_WORKSPACE, "workspace not 256-byte aligned");
+    if (L.cap < 4) return fail(XTC_E_WORKSPACE, "workspace of %zu bytes holds no chunk (need > %zu)", bytes,
+                               L.fixed + 2 * kAlign + 4 * L.per_row);
+    return XTC_OK;
+}
+
+xtc_status check_range(const Layout& L, int g0, int g1) {
+    if (!(0 <= g0 && g0 < g1 && g1 <= L.Ng)) return fail(XTC_E_ARG, "rows [%d,%d) not inside [0,%d)", g0, g1, L.Ng);
+    if (g1 - g0 > L.cap)
+        return fail(XTC_E_WORKSPACE, "chunk of %d rows exceeds the workspace capacity of %d rows", g1 - g0, L.cap);
+    return XTC_OK;
+}
+
+xtc_status check_align(const void* p, const char* name) {
+    if ((uintptr_t)p % 32) return fail(XTC_E_ARG, "%s must be 32-byte aligned", name);
+    return XTC_OK;
+}
+
+OccList make_occ(const xtc_problem* pb) {
+    OccList o{};
+    o.n = pb->nocc;
+    for (int i = 0; i < pb->nocc; ++i) o.k[i] = pb->occ[i];
+    return o;
+}
+
+xtc_status launched(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(XTC_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    return XTC_OK;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
+
+xtc_status fill(double* p, size_t n, hipStream_t st) {
+    if (n == 0) return XTC_OK;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, n, 0.0);
+    return launched("fill");
+}
+
+// Intermediates of rows [g0, g1) into D and S of the workspace.
+xtc_status run_intermediates(const Layout& L, const xtc_problem* pb, const double* K, int g0, int g1,
+                             void* ws, hipStream_t st) {
+    const int rows = g1 - g0;
+    const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
+    const size_t dstride = (size_t)L.cap * L.ldP;
+    const int blocks = std::min(rows, 4096);
+    const size_t lds = lds_intermediates(L);
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_intermediates,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return fail(XTC_E_HIP, "intermediates LDS attribute: %s", hipGetErrorString(e));
+    }
+    hipLaunchKernelGGL(k_intermediates, dim3(blocks), dim3(256), lds, st, rho_rows, K, rows, L.ldP, L.N,
+                       make_occ(pb), at<double>(ws, L.D), dstride, at<double>(ws, L.S));
+    return launched("intermediates");
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t xtc_pair_ld(int32_t N) { return N >= 1 ? pair_ld(N) : 0; }
+
+const char* xtc_last_error(void) { return g_err.c_str(); }
+
+size_t xtc_workspace_size(const xtc_problem* pb, int32_t prec, int32_t chunk_rows) {
+    if (check_problem(pb) != XTC_OK) return 0;
+    if (check_prec(prec) != XTC_OK) return 0;
+    if (chunk_rows < 1 || chunk_rows > pb->Ng) {
+        fail(XTC_E_ARG, "chunk_rows=%d outside [1,Ng]", chunk_rows);
+        return 0;
+    }
+    Layout L = make_layout(pb, prec);
+    const size_t rows = align_up((size_t)chunk_rows, 4);
+    return L.fixed + 2 * kAlign + rows * L.per_row;
+}
+
+xtc_status xtc_prepare(const xtc_problem* pb, int32_t prec, int32_t chunk_rows, void* ws, size_t ws_bytes,
+                       void* stream) {
+    xtc_status s;
+    if ((s = check_problem(pb)) != XTC_OK) return s;
+    if ((s = check_prec(prec)) != XTC_OK) return s;
+    Layout L = make_layout(pb, prec);
+    place_chunk(L, ws_bytes);
+    if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
+    if (chunk_rows < 1 || chunk_rows > L.cap)
+        return fail(XTC_E_WORKSPACE, "chunk_rows=%d exceeds the workspace capacity of %d rows", chunk_rows, L.cap);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_prepare_pos, dim3((L.ngp + 255) / 256), dim3(256), 0, st, pb->xyz, L.Ng, L.ngp,
+                       at<d4>(ws, L.pos));
+    if ((s = launched("prepare_pos")) != XTC_OK) return s;
+    const size_t lds = (size_t)L.N * kPrepRows * sizeof(double);
+    hipLaunchKernelGGL(k_prepare_rho, dim3(L.ngp / kPrepRows), dim3(256), lds, st, pb->phi, pb->w, L.N, L.Ng,
+                       L.ngp, L.ldP, at<double>(ws, L.rho));
+    if ((s = launched("prepare_rho")) != XTC_OK) return s;
+    // zero the accumulators and the chunk buffers (padding columns of D stay 0)
+    if ((s = fill(at<double>(ws, L.M), (size_t)L.ldP * L.ldP, st)) != XTC_OK) return s;
+    if ((s = fill(at<double>(ws, L.h1acc), (size_t)L.ldP, st)) != XTC_OK) return s;
+    if ((s = fill(at<double>(ws, L.D), (size_t)4 * L.cap * L.ldP, st)) != XTC_OK) return s;
+    return XTC_OK;
+}
+
+xtc_status xtc_build_K(const xtc_problem* pb, const xtc_jastrow* jas, int32_t g0, int32_t g1, int32_t prec,
+                       double* K, void* ws, size_t ws_bytes, void* stream) {
+    xtc_status s;
+    JasDev J;
+    if ((s = check_problem(pb)) != XTC_OK) return s;
+    if ((s = check_prec(prec)) != XTC_OK) return s;
+    if ((s = check_jastrow(jas, &J)) != XTC_OK) return s;
+    if (!K) return fail(XTC_E_ARG, "K is NULL");
+    if ((s = check_align(K, "K")) != XTC_OK) return s;
+    Layout L = make_layout(pb, prec);
+    place_chunk(L, ws_bytes);
+    if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
+    if ((s = check_range(L, g0, g1)) != XTC_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int rows = g1 - g0;
+    const int n_rt = (rows + kKRows - 1) / kKRows;
+    const int n_ct = L.ldP / kKCols;
+    const dim3 grid(n_rt * n_ct);
+    if (J.kind == 0)
+        hipLaunchKernelGGL(k_build_K_f64<0>, grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
+                           L.ldP, L.ngp, g0, rows, n_rt, J, K);
+    else
+        hipLaunchKernelGGL(k_build_K_f64<1>, grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
+                           L.ldP, L.ngp, g0, rows, n_rt, J, K);
+    return launched("build_K");
+}
+
+xtc_status xtc_contract_2body(const xtc_problem* pb, const double* K, int32_t g0, int32_t g1, int32_t prec,
+                              int32_t flags, double* V2, void* ws, size_t ws_bytes, void* stream) {
+    xtc_status s;
+    if ((s = check_problem(pb)) != XTC_OK) return s;
+    if ((s = check_prec(prec)) != XTC_OK) return s;
+    if (!K) return fail(XTC_E_ARG, "K is NULL");
+    if ((s = check_align(K, "K")) != XTC_OK) return s;
+    if (flags & ~(XTC_RESET | XTC_FINALIZE)) return fail(XTC_E_ARG, "flags=%d unknown bits", flags);
+    if ((flags & XTC_FINALIZE) && !V2) return fail(XTC_E_ARG, "V2 is NULL with XTC_FINALIZE");
+    Layout L = make_layout(pb, prec);
+    place_chunk(L, ws_bytes);
+    if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
+    if ((s = check_range(L, g0, g1)) != XTC_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = run_intermediates(L, pb, K, g0, g1, ws, st)) != XTC_OK) return s;
+    const int rows = g1 - g0;
+    const int n_t = L.ldP / 128;
+    const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
+    hipLaunchKernelGGL(k_gemm2b_f64, dim3(n_t * n_t), dim3(256), 0, st, rho_rows, K, at<double>(ws, L.D),
+                       (size_t)L.cap * L.ldP, rows, L.ldP, n_t, at<double>(ws, L.M),
+                       (flags & XTC_RESET) ? 0 : 1);
+    if ((s = launched("gemm_2body")) != XTC_OK) return s;
+    if (flags & XTC_FINALIZE) {
+        const int NN = L.N * L.N;
+        hipLaunchKernelGGL(k_finalize_V2, dim3((NN + 255) / 256, L.N, L.N), dim3(256), 0, st, at<double>(ws, L.M),
+                           L.ldP, L.N, V2);
+        if ((s = launched("finalize_V2")) != XTC_OK) return s;
+    }
+    return XTC_OK;
+}
+
+xtc_status xtc_contract_1body_0body(const xtc_problem* pb, const double* K, int32_t g0, int32_t g1,
+                                    int32_t prec, int32_t flags, double* h1, double* E0, void* ws,
+                                    size_t ws_bytes, void* stream) {
+    xtc_status s;
+    if ((s = check_problem(pb)) != XTC_OK) return s;
+    if ((s = check_prec(prec)) != XTC_OK) return s;
+    if (!K) return fail(XTC_E_ARG, "K is NULL");
+    if ((s = check_align(K, "K")) != XTC_OK) return s;
+    if (flags & ~(XTC_RESET | XTC_FINALIZE)) return fail(XTC_E_ARG, "flags=%d unknown bits", flags);
+    if ((flags & XTC_FINALIZE) && (!h1 || !E0)) return fail(XTC_E_ARG, "h1/E0 NULL with XTC_FINALIZE");
+    Layout L = make_layout(pb, prec);
+    place_chunk(L, ws_bytes);
+    if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
+    if ((s = check_range(L, g0, g1)) != XTC_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = run_intermediates(L, pb, K, g0, g1, ws, st)) != XTC_OK) return s;
+    const int rows = g1 - g0;
+    const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
+    const size_t dstride = (size_t)L.cap * L.ldP;
+    const int nsplit_t1 = std::min(kT1Split, rows);
+    hipLaunchKernelGGL(k_onebody_T1, dim3((L.Npair + 255) / 256, nsplit_t1), dim3(256), 0, st, rho_rows, K,
+                       at<double>(ws, L.D), dstride, at<double>(ws, L.S), rows, L.ldP, L.Npair,
+                       at<double>(ws, L.T1));
+    if ((s = launched("onebody_T1")) != XTC_OK) return s;
+    const int nbk = (L.N + kEBlk - 1) / kEBlk;
+    int nsplit_e = std::max(1, std::min(kESplitMax, 1024 / (nbk * nbk)));
+    nsplit_e = std::min(nsplit_e, rows);
+    const size_t lds = (size_t)2 * L.nocc * kEBlk * sizeof(double);
+    hipLaunchKernelGGL(k_onebody_E, dim3(nbk * nbk, nsplit_e), dim3(256), lds, st, rho_rows, K,
+                       at<double>(ws, L.D), dstride, rows, L.ldP, L.N, make_occ(pb), at<double>(ws, L.E));
+    if ((s = launched("onebody_E")) != XTC_OK) return s;
+    hipLaunchKernelGGL(k_onebody_accumulate, dim3((L.Npair + 255) / 256), dim3(256), 0, st, at<double>(ws, L.T1),
+                       nsplit_t1, at<double>(ws, L.E), nsplit_e, L.ldP, L.N, at<double>(ws, L.h1acc),
+                       (flags & XTC_RESET) ? 0 : 1);
+    if ((s = launched("onebody_accumulate")) != XTC_OK) return s;
+    if (flags & XTC_FINALIZE) {
+        const int NN = L.N * L.N;
+        hipLaunchKernelGGL(k_onebody_finalize, dim3((NN + 255) / 256), dim3(256), 0, st, at<double>(ws, L.h1acc),
+                           L.N, make_occ(pb), h1, E0);
+        if ((s = launched("onebody_finalize")) != XTC_OK) return s;
+    }
+    return XTC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Device-side helpers shared by the xTC kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xtc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int kPairTile = 128;   // pair-column padding unit (xtc_pair_ld)
+constexpr int kGridPad = 128;    // grid-row padding unit of the prepared operands
+
+// Jastrow parameters as kernels see them.  dcoef[k] = (k+1) coef[k], so the
+// power-form derivative is a Horner polynomial in t = r/(1+r).
+struct JasDev {
+    int32_t kind;    // 0 Pade, 1 power
+    int32_t ncoef;
+    double b;
+    double dcoef[16];
+};
+
+// u'(r)/r for the electron-electron Jastrow, from r^2; exactly 0 at r^2 == 0
+// (coincident points: the gradient of an isotropic function is taken as 0).
+//   Pade : u = r/(2(1+br))      -> u'/r = 1 / (2 r (1+br)^2)
+//   power: u = sum c_k t^k      -> u'/r = (sum k c_k t^(k-1)) / (r (1+r)^2)
+template <int KIND>
+__device__ __forceinline__ double du_over_r(double r2, const JasDev& J) {
+    const double r = __builtin_sqrt(r2);
+    double f;
+    if constexpr (KIND == 0) {
+        const double t = fma(J.b, r, 1.0);
+        f = 0.5 / (r * t * t);
+    } else {
+        const double q = 1.0 / (1.0 + r);
+        const double t = r * q;
+        double p = J.dcoef[J.ncoef - 1];
+        for (int k = J.ncoef - 2; k >= 0; --k) p = fma(p, t, J.dcoef[k]);
+        f = p * q * q / r;
+    }
+    return r2 > 0.0 ? f : 0.0;
+}
+
+template <int KIND>
+__device__ __forceinline__ float du_over_r_f32(float r2, const JasDev& J) {
+    const float r = __builtin_sqrtf(r2);
+    float f;
+    if constexpr (KIND == 0) {
+        const float t = fmaf((float)J.b, r, 1.0f);
+        f = 0.5f / (r * t * t);
+    } else {
+        const float q = 1.0f / (1.0f + r);
+        const float t = r * q;
+        float p = (float)J.dcoef[J.ncoef - 1];
+        for (int k = J.ncoef - 2; k >= 0; --k) p = fmaf(p, t, (float)J.dcoef[k]);
+        f = p * q * q / r;
+    }
+    return r2 > 0.0f ? f : 0.0f;
+}
+
+__device__ __forceinline__ int pair_index(int p, int q, int N) {
+    // p <= q
+    return p * N - (p * (p - 1)) / 2 + (q - p);
+}
+
+__device__ __forceinline__ int pair_sym(int p, int q, int N) {
+    return p <= q ? pair_index(p, q, N) : pair_index(q, p, N);
+}
+
+}  // namespace xtc

@@ -1,0 +1,222 @@
+"""Python binding of libxtc (include/xtc.h): argument marshalling only.
+
+Every numerical step runs in the library's HIP kernels; torch is used to
+hold device memory and to name the current HIP stream.  The functions named
+``xtc_*`` mirror the C entry points one to one; ``forward`` strings them
+together over grid chunks for a whole pass.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxtc.so")
+
+XTC_OK, XTC_E_ARG, XTC_E_WORKSPACE, XTC_E_HIP, XTC_E_UNSUPPORTED = 0, -1, -2, -3, -4
+XTC_FP64, XTC_FP32, XTC_BF16X3, XTC_BF16X6 = 0, 1, 2, 3
+XTC_RESET, XTC_FINALIZE = 1, 2
+PRECISIONS = {"fp64": XTC_FP64, "fp32": XTC_FP32, "bf16x3": XTC_BF16X3, "bf16x6": XTC_BF16X6}
+
+
+class XtcError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"xtc status {status}: {message}")
+        self.status = status
+
+
+class XtcJastrow(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("ncoef", ctypes.c_int32), ("b", ctypes.c_double),
+                ("coef", ctypes.c_double * 16)]
+
+
+class XtcProblem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("Ng", ctypes.c_int32), ("nocc", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("xyz", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("phi", ctypes.c_void_p), ("occ", ctypes.POINTER(ctypes.c_int32))]
+
+
+_SIGS = {
+    "xtc_pair_ld": (ctypes.c_int32, [ctypes.c_int32]),
+    "xtc_last_error": (ctypes.c_char_p, []),
+    "xtc_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(XtcProblem), ctypes.c_int32, ctypes.c_int32]),
+    "xtc_prepare": (ctypes.c_int, [ctypes.POINTER(XtcProblem), ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "xtc_build_K": (ctypes.c_int, [ctypes.POINTER(XtcProblem), ctypes.POINTER(XtcJastrow), ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_size_t, ctypes.c_void_p]),
+    "xtc_contract_2body": (ctypes.c_int, [ctypes.POINTER(XtcProblem), ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "xtc_contract_1body_0body": (ctypes.c_int, [ctypes.POINTER(XtcProblem), ctypes.c_void_p, ctypes.c_int32,
+                                                ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_size_t, ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load the in-tree libxtc.so; fail loudly if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2304_07006_amd/build.py (no CPU fallback exists)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def last_error() -> str:
+    return load().xtc_last_error().decode()
+
+
+def _check(status):
+    if status != XTC_OK:
+        raise XtcError(status, last_error())
+
+
+# ------------------------------------------------------------ marshalling --
+def make_jastrow(jas) -> XtcJastrow:
+    """From an object with .kind ('pade'|'power'), .b, .coef."""
+    j = XtcJastrow()
+    if jas.kind == "pade":
+        j.kind, j.ncoef, j.b = 0, 0, float(jas.b)
+    elif jas.kind == "power":
+        j.kind, j.ncoef, j.b = 1, len(jas.coef), 0.0
+        for k, c in enumerate(jas.coef):
+            j.coef[k] = float(c)
+    else:
+        raise ValueError(jas.kind)
+    return j
+
+
+@dataclass
+class DeviceProblem:
+    """Device copies of the inputs plus the C struct that points at them."""
+    xyz: object
+    w: object
+    phi: object
+    occ_host: np.ndarray
+    c: XtcProblem
+
+    @property
+    def N(self):
+        return self.c.N
+
+    @property
+    def Ng(self):
+        return self.c.Ng
+
+
+def device_problem(xyz, w, phi, occ, device="cuda") -> DeviceProblem:
+    import torch
+    t_xyz = torch.as_tensor(np.ascontiguousarray(xyz, dtype=np.float64)).to(device)
+    t_w = torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64)).to(device)
+    t_phi = torch.as_tensor(np.ascontiguousarray(phi, dtype=np.float64)).to(device)
+    occ_h = np.ascontiguousarray(occ, dtype=np.int32)
+    c = XtcProblem(int(phi.shape[0]), int(phi.shape[1]), int(len(occ_h)), 0, t_xyz.data_ptr(), t_w.data_ptr(),
+                   t_phi.data_ptr(), occ_h.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return DeviceProblem(t_xyz, t_w, t_phi, occ_h, c)
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------- entry points --
+def xtc_pair_ld(N: int) -> int:
+    return load().xtc_pair_ld(N)
+
+
+def xtc_workspace_size(dp: DeviceProblem, prec: int, chunk_rows: int) -> int:
+    n = load().xtc_workspace_size(ctypes.byref(dp.c), prec, chunk_rows)
+    if n == 0:
+        raise XtcError(XTC_E_ARG, last_error())
+    return n
+
+
+def xtc_prepare(dp, prec, chunk_rows, ws, stream=None):
+    _check(load().xtc_prepare(ctypes.byref(dp.c), prec, chunk_rows, _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def xtc_build_K(dp, jas: XtcJastrow, g0, g1, prec, K, ws, stream=None):
+    _check(load().xtc_build_K(ctypes.byref(dp.c), ctypes.byref(jas), g0, g1, prec, _ptr(K), _ptr(ws),
+                              ws.numel(), _stream(stream)))
+
+
+def xtc_contract_2body(dp, K, g0, g1, prec, flags, V2, ws, stream=None):
+    _check(load().xtc_contract_2body(ctypes.byref(dp.c), _ptr(K), g0, g1, prec, flags, _ptr(V2), _ptr(ws),
+                                     ws.numel(), _stream(stream)))
+
+
+def xtc_contract_1body_0body(dp, K, g0, g1, prec, flags, h1, E0, ws, stream=None):
+    _check(load().xtc_contract_1body_0body(ctypes.byref(dp.c), _ptr(K), g0, g1, prec, flags, _ptr(h1), _ptr(E0),
+                                           _ptr(ws), ws.numel(), _stream(stream)))
+
+
+# ------------------------------------------------------------ whole pass --
+class Pass:
+    """Device buffers of one forward pass: workspace, one K chunk, outputs."""
+
+    def __init__(self, dp: DeviceProblem, prec: int = XTC_FP64, chunk_rows: int | None = None, device="cuda"):
+        import torch
+        self.dp, self.prec = dp, prec
+        self.chunk = min(dp.Ng, chunk_rows or dp.Ng)
+        self.ldP = xtc_pair_ld(dp.N)
+        nbytes = xtc_workspace_size(dp, prec, self.chunk)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.K = torch.empty((3, self.chunk, self.ldP), dtype=torch.float64, device=device)
+        N = dp.N
+        self.V2 = torch.empty((N, N, N, N), dtype=torch.float64, device=device)
+        self.h1 = torch.empty((N, N), dtype=torch.float64, device=device)
+        self.E0 = torch.empty((1,), dtype=torch.float64, device=device)
+
+    def chunks(self):
+        Ng = self.dp.Ng
+        return [(g0, min(Ng, g0 + self.chunk)) for g0 in range(0, Ng, self.chunk)]
+
+    def K_view(self, g0, g1):
+        # a [3][g1-g0][ldP] contiguous view at the start of the chunk buffer
+        import torch
+        n = 3 * (g1 - g0) * self.ldP
+        return self.K.view(-1)[:n].view(3, g1 - g0, self.ldP)
+
+    def run(self, jas: XtcJastrow, two_body=True, one_body=True, stream=None):
+        xtc_prepare(self.dp, self.prec, self.chunk, self.ws, stream)
+        ch = self.chunks()
+        for i, (g0, g1) in enumerate(ch):
+            flags = (XTC_RESET if i == 0 else 0) | (XTC_FINALIZE if i == len(ch) - 1 else 0)
+            K = self.K_view(g0, g1)
+            xtc_build_K(self.dp, jas, g0, g1, self.prec, K, self.ws, stream)
+            if two_body:
+                xtc_contract_2body(self.dp, K, g0, g1, self.prec, flags, self.V2, self.ws, stream)
+            if one_body:
+                xtc_contract_1body_0body(self.dp, K, g0, g1, self.prec, flags, self.h1, self.E0, self.ws, stream)
+        return self.V2, self.h1, self.E0
+
+
+def forward(problem, prec="fp64", chunk_rows=None, device="cuda"):
+    """V2, h1, E0 (torch tensors on the device) for an inputs.Problem."""
+    dp = device_problem(problem.xyz, problem.w, problem.phi, problem.occ, device)
+    ps = Pass(dp, PRECISIONS[prec] if isinstance(prec, str) else prec, chunk_rows, device)
+    V2, h1, E0 = ps.run(make_jastrow(problem.jastrow))
+    return V2, h1, E0

@@ -1,0 +1,115 @@
+"""The C ABI: exported symbols and host-side validation (no kernel launches)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2304_07006_amd import xtc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "xtc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(xtc_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(xtc.LIB_PATH):
+        pytest.skip("libxtc.so not built")
+    return xtc.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _header_functions()
+    assert "xtc_build_K" in names and "xtc_contract_2body" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(xtc.exported_symbols())
+
+
+def test_pair_ld(lib):
+    assert lib.xtc_pair_ld(8) == 128
+    assert lib.xtc_pair_ld(128) == 8320
+    assert lib.xtc_pair_ld(0) == 0
+
+
+def _problem(N=8, Ng=100, occ=(0, 1), fake=0x1000):
+    occ = np.array(occ, dtype=np.int32)
+    c = xtc.XtcProblem(N, Ng, len(occ), 0, fake, fake, fake, occ.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return c, occ
+
+
+def _jas(kind=0, ncoef=0, b=1.0):
+    j = xtc.XtcJastrow()
+    j.kind, j.ncoef, j.b = kind, ncoef, b
+    return j
+
+
+def _call_build(lib, c, j, g0=0, g1=10, prec=0, K=0x2000, ws=None, nbytes=None):
+    if nbytes is None:
+        nbytes = lib.xtc_workspace_size(ctypes.byref(c), 0, 50) if ws is None else nbytes
+    return lib.xtc_build_K(ctypes.byref(c), ctypes.byref(j), g0, g1, prec, ctypes.c_void_p(K),
+                           ctypes.c_void_p(ws if ws is not None else 0x100000), nbytes, None)
+
+
+@pytest.mark.parametrize("mut,expect", [
+    (dict(N=0), xtc.XTC_E_ARG),
+    (dict(occ=(0, 0)), xtc.XTC_E_ARG),
+    (dict(occ=(0, 9)), xtc.XTC_E_ARG),
+    (dict(occ=(-1,)), xtc.XTC_E_ARG),
+])
+def test_bad_problem(lib, mut, expect):
+    kw = dict(N=8, Ng=100, occ=(0, 1))
+    kw.update(mut)
+    c, keep = _problem(**kw)
+    assert lib.xtc_workspace_size(ctypes.byref(c), 0, 50) == 0
+    st = _call_build(lib, c, _jas(), nbytes=1 << 30)
+    assert st == expect
+    assert xtc.last_error()
+
+
+def test_bad_jastrow_and_range(lib):
+    c, keep = _problem()
+    n = lib.xtc_workspace_size(ctypes.byref(c), 0, 50)
+    assert n > 0
+    assert _call_build(lib, c, _jas(b=-1.0), nbytes=n) == xtc.XTC_E_ARG
+    assert _call_build(lib, c, _jas(b=float("nan")), nbytes=n) == xtc.XTC_E_ARG
+    assert _call_build(lib, c, _jas(kind=1, ncoef=0), nbytes=n) == xtc.XTC_E_ARG
+    assert _call_build(lib, c, _jas(kind=1, ncoef=17), nbytes=n) == xtc.XTC_E_ARG
+    assert _call_build(lib, c, _jas(kind=7), nbytes=n) == xtc.XTC_E_ARG
+    assert _call_build(lib, c, _jas(), g0=5, g1=5, nbytes=n) == xtc.XTC_E_ARG
+    assert _call_build(lib, c, _jas(), g0=0, g1=101, nbytes=n) == xtc.XTC_E_ARG
+    assert _call_build(lib, c, _jas(), g0=0, g1=60, nbytes=n) == xtc.XTC_E_WORKSPACE   # > capacity
+    assert _call_build(lib, c, _jas(), K=0, nbytes=n) == xtc.XTC_E_ARG
+    assert _call_build(lib, c, _jas(), K=0x2008, nbytes=n) == xtc.XTC_E_ARG           # misaligned
+    assert _call_build(lib, c, _jas(), nbytes=100) == xtc.XTC_E_WORKSPACE
+    assert lib.xtc_build_K(ctypes.byref(c), ctypes.byref(_jas()), 0, 10, 0, ctypes.c_void_p(0x2000),
+                           None, n, None) == xtc.XTC_E_WORKSPACE
+    assert _call_build(lib, c, _jas(), prec=9, nbytes=n) == xtc.XTC_E_ARG
+
+
+def test_contract_flags(lib):
+    c, keep = _problem()
+    n = lib.xtc_workspace_size(ctypes.byref(c), 0, 50)
+    st = lib.xtc_contract_2body(ctypes.byref(c), ctypes.c_void_p(0x2000), 0, 10, 0, 8, None,
+                                ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG
+    st = lib.xtc_contract_2body(ctypes.byref(c), ctypes.c_void_p(0x2000), 0, 10, 0, xtc.XTC_FINALIZE, None,
+                                ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG
+    st = lib.xtc_contract_1body_0body(ctypes.byref(c), ctypes.c_void_p(0x2000), 0, 10, 0, xtc.XTC_FINALIZE,
+                                      None, None, ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG
+
+
+def test_workspace_grows_with_chunk(lib):
+    c, keep = _problem(N=16, Ng=1000, occ=(0, 3, 5))
+    a = lib.xtc_workspace_size(ctypes.byref(c), 0, 100)
+    b = lib.xtc_workspace_size(ctypes.byref(c), 0, 1000)
+    assert 0 < a < b
+    assert lib.xtc_workspace_size(ctypes.byref(c), 0, 1001) == 0

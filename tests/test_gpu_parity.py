@@ -1,0 +1,125 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle."""
+import numpy as np
+import pytest
+
+from paper_2304_07006_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_ABS = 1e-11      # FP64 summation-order noise on outputs of size <= ~1
+
+
+def _note(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def _run(problem, prec="fp64", chunk_rows=None):
+    from paper_2304_07006_amd import xtc
+    V2, h1, E0 = xtc.forward(problem, prec=prec, chunk_rows=chunk_rows)
+    return V2.cpu().numpy(), h1.cpu().numpy(), float(E0.cpu().numpy()[0])
+
+
+def _K(problem, g0, g1, chunk_rows=None):
+    """Grid intermediate of rows [g0,g1) through xtc_prepare + xtc_build_K."""
+    import torch
+    from paper_2304_07006_amd import xtc
+    dp = xtc.device_problem(problem.xyz, problem.w, problem.phi, problem.occ)
+    ps = xtc.Pass(dp, xtc.XTC_FP64, chunk_rows or (g1 - g0))
+    xtc.xtc_prepare(dp, xtc.XTC_FP64, ps.chunk, ps.ws)
+    K = ps.K_view(g0, g1)
+    xtc.xtc_build_K(dp, xtc.make_jastrow(problem.jastrow), g0, g1, xtc.XTC_FP64, K, ps.ws)
+    torch.cuda.synchronize()
+    return K.cpu().numpy()
+
+
+def _unpack(Kp, N):
+    """[3][rows][ldP] packed pairs -> [3][rows][N][N]."""
+    out = np.zeros(Kp.shape[:2] + (N, N))
+    P = 0
+    for p in range(N):
+        for q in range(p, N):
+            out[:, :, p, q] = Kp[:, :, P]
+            out[:, :, q, p] = Kp[:, :, P]
+            P += 1
+    return out
+
+
+def test_tiny_against_explicit_L(torch_cuda):
+    """N=8, 2 occupied, Ng=2000 against the explicit six-index L (tier A)."""
+    from oracle import explicit as ex
+    p = inputs.make_workload("N8-occ2-Ng2k")
+    _note("case: N8-occ2-Ng2k fp64 vs explicit L")
+    A = ex.tier_a(p.xyz, p.w, p.phi, p.occ, p.jastrow)
+    V2, h1, E0 = _run(p)
+    assert np.abs(V2 - A["V2"]).max() < TOL_ABS
+    assert np.abs(h1 - A["h1"]).max() < TOL_ABS
+    assert abs(E0 - A["E0"]) < TOL_ABS
+
+
+def test_tiny_K_entries(torch_cuda):
+    from oracle import explicit as ex
+    p = inputs.make_workload("N8-occ2-Ng2k")
+    _note("case: N8-occ2-Ng2k K rows [100,1700)")
+    K = _K(p, 100, 1700)
+    N = p.N
+    rng = np.random.default_rng(0)
+    Ku = _unpack(K, N)
+    for _ in range(40):
+        g = int(rng.integers(0, 1600))
+        a, b = sorted(int(x) for x in rng.integers(0, N, size=2))
+        e = ex.exact_K_entry(p.xyz, p.w, p.phi, p.jastrow, 100 + g, a, b)
+        assert np.abs(Ku[:, g, a, b] - e).max() < 1e-14
+    ldP = K.shape[2]
+    assert np.all(K[:, :, N * (N + 1) // 2:ldP] == 0.0)
+
+
+@pytest.mark.parametrize("chunk_rows", [None, 1000])
+def test_mid_against_factorised(torch_cuda, chunk_rows):
+    """N=64, 8 occupied on a 3001-point grid (ragged in rows, pairs, chunks)."""
+    from oracle import factorised as fb
+    p = inputs.make_workload("N64-occ8-Ng50k", Ng=3001)
+    _note(f"case: N64-occ8-Ng3001 fp64 chunk={chunk_rows}")
+    V2o, h1o, E0o = fb.closed_shell(p.xyz, p.w, p.phi, p.occ, p.jastrow)
+    V2, h1, E0 = _run(p, chunk_rows=chunk_rows)
+    assert np.abs(V2 - V2o).max() < TOL_ABS
+    assert np.abs(h1 - h1o).max() < TOL_ABS
+    assert abs(E0 - E0o) < TOL_ABS
+
+
+def test_power_jastrow_random_occ(torch_cuda):
+    """16-term power Jastrow, seeded random occupied set, N=24."""
+    from oracle import factorised as fb
+    occ = inputs.random_occ(24, 5, seed=3)
+    p = inputs.make_problem(24, 5, 1500, 6, "chain", "power16", seed=21, occ=occ)
+    _note("case: N24 power16 random occ")
+    V2o, h1o, E0o = fb.closed_shell(p.xyz, p.w, p.phi, p.occ, p.jastrow)
+    V2, h1, E0 = _run(p, chunk_rows=700)
+    assert np.abs(V2 - V2o).max() < TOL_ABS
+    assert np.abs(h1 - h1o).max() < TOL_ABS
+    assert abs(E0 - E0o) < TOL_ABS
+
+
+def test_symmetry_and_determinism(torch_cuda):
+    p = inputs.make_workload("N64-occ8-Ng50k", Ng=2500)
+    _note("case: N64-occ8-Ng2500 symmetry + determinism")
+    V2, h1, E0 = _run(p, chunk_rows=900)
+    for perm in [(1, 0, 2, 3), (0, 1, 3, 2), (2, 3, 0, 1), (3, 2, 1, 0)]:
+        assert np.array_equal(V2, V2.transpose(perm))
+    assert np.array_equal(h1, h1.T)
+    V2b, h1b, E0b = _run(p, chunk_rows=900)
+    assert np.array_equal(V2, V2b) and np.array_equal(h1, h1b) and E0 == E0b
+
+
+def test_single_occupied_E0_zero(torch_cuda):
+    p = inputs.make_problem(8, 1, 700, 2, "pair", "pade", seed=4)
+    _note("case: N8 n=1")
+    V2, h1, E0 = _run(p)
+    assert abs(E0) < 1e-15
