@@ -1,0 +1,160 @@
+"""Throughput of the xTC folding on one MI355X.
+
+One step = one whole pass of the hot path over the workload: prepare the
+pair densities, then per grid chunk build K, form the intermediates and add
+the two-body and one-/zero-body terms, finalising V2, h1 and E0 on the last
+chunk.  Inputs are resident in HBM before the timed region starts.
+
+The value is algorithmic GFLOP/s:
+    F_alg = 6 Ng^2 Npair + 8 Ng Npair^2 + (18 n + 10) Ng Npair
+(K build, two-body assembly, intermediates; Npair = N(N+1)/2) divided by the
+wall time of one step.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "xTC 2-body build GFLOP/s at N=128: FP64 vs split-BF16 at ≤1e-6 Eh error"
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}   # TFLOP/s, dense MFMA
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}
+
+
+def f_alg(N, n, Ng):
+    P = N * (N + 1) // 2
+    return 6 * Ng * Ng * P + 8 * Ng * P * P + (18 * n + 10) * Ng * P
+
+
+def f_kbuild(N, rows, Ng):
+    return 6 * rows * Ng * (N * (N + 1) // 2)
+
+
+def run_gpu(problem, prec, steps, warmup, chunk):
+    import torch
+    from paper_2304_07006_amd import xtc
+    dp = xtc.device_problem(problem.xyz, problem.w, problem.phi, problem.occ)
+    ps = xtc.Pass(dp, xtc.PRECISIONS[prec], chunk)
+    jas = xtc.make_jastrow(problem.jastrow)
+    stream = torch.cuda.current_stream()
+    kev = []
+
+    def step(record):
+        xtc.xtc_prepare(dp, ps.prec, ps.chunk, ps.ws)
+        ch = ps.chunks()
+        for i, (g0, g1) in enumerate(ch):
+            flags = (xtc.XTC_RESET if i == 0 else 0) | (xtc.XTC_FINALIZE if i == len(ch) - 1 else 0)
+            K = ps.K_view(g0, g1)
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            xtc.xtc_build_K(dp, jas, g0, g1, ps.prec, K, ps.ws)
+            if record:
+                e1.record(stream)
+                kev.append((e0, e1, g1 - g0))
+            xtc.xtc_contract_2body(dp, K, g0, g1, ps.prec, flags, ps.V2, ps.ws)
+            xtc.xtc_contract_1body_0body(dp, K, g0, g1, ps.prec, flags, ps.h1, ps.E0, ps.ws)
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kt = [(a.elapsed_time(b) * 1e-3, rows) for a, b, rows in kev]
+    return dict(sec=dt, kbuild=kt, outputs=(ps.V2, ps.h1, ps.E0), ws_bytes=ps.ws.numel())
+
+
+def cpu_baseline(name, budget_rows):
+    """The oracle (Appendix-B equations, numpy FP64) on the same workload's
+    orbitals and generator, on a reduced grid of `budget_rows` points."""
+    import numpy as np
+    from paper_2304_07006_amd import inputs
+    from oracle import factorised
+    wl = inputs.WORKLOADS[name]
+    p = inputs.make_workload(name, Ng=budget_rows)
+    t0 = time.perf_counter()
+    factorised.closed_shell(p.xyz, p.w, p.phi, p.occ, p.jastrow)
+    dt = time.perf_counter() - t0
+    F = f_alg(wl.N, wl.nocc, budget_rows)
+    cores = len(os.sched_getaffinity(0))
+    return {"value": F / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"N={wl.N} n={wl.nocc} on a {budget_rows}-point grid from the same generator "
+                      f"(full orbital set, Appendix-B equations in numpy FP64); {dt:.1f} s wall; "
+                      f"rate = F_alg(sample)/time",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="N128-occ16-Ng150k")
+    ap.add_argument("--prec", default="fp64", choices=list(PEAK))
+    ap.add_argument("--chunk", type=int, default=16384)
+    ap.add_argument("--cpu-rows", type=int, default=300, help="grid points of the CPU oracle sample (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the grid-row sharding is described in the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2304_07006_amd import inputs, xtc
+    xtc.load()
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    wl = inputs.WORKLOADS[args.workload]
+    problem = inputs.make_workload(args.workload)
+    print(f"[bench] {args.workload} prec={args.prec} chunk={args.chunk} warmup={args.warmup} steps={args.steps}",
+          file=sys.stderr, flush=True)
+    r = run_gpu(problem, args.prec, args.steps, args.warmup, args.chunk)
+    F = f_alg(wl.N, wl.nocc, wl.Ng)
+    # roofline of the dominant kernel (K build): algorithmic flops per launch over
+    # its average launch duration from HIP events on the launch stream
+    tot_f = sum(f_kbuild(wl.N, rows, wl.Ng) for _, rows in r["kbuild"])
+    tot_t = sum(t for t, _ in r["kbuild"])
+    nl = len(r["kbuild"])
+    achieved = (tot_f / nl) / (tot_t / nl) / 1e12
+    peak = PEAK[args.prec]
+    print(f"[bench] step {r['sec']:.3f} s; K build {nl} launches, avg {tot_t / nl * 1e3:.1f} ms, "
+          f"{achieved:.1f} TFLOP/s", file=sys.stderr, flush=True)
+    cpu = None
+    if args.cpu_rows > 0:
+        print(f"[bench] CPU oracle sample: {args.cpu_rows} grid points", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args.workload, args.cpu_rows)
+    out = {
+        "metric": METRIC,
+        "value": F / r["sec"] / 1e9,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["sec"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.prec],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N": wl.N, "nocc": wl.nocc, "Ng": wl.Ng, "prec": args.prec,
+                   "chunk_rows": args.chunk, "jastrow": wl.jastrow_kind, "F_alg_flop": F,
+                   "workspace_bytes": r["ws_bytes"]},
+        "roofline": {"bound": "mfma", "kernel": "k_build_K", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "per_launch_flop": tot_f / nl, "avg_launch_ms": tot_t / nl * 1e3},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

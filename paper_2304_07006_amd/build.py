@@ -16,6 +16,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
     "-Wall", "-Wno-unused-function",
+    # MFMA accumulators in ordinary VGPRs (no per-iteration AGPR copies)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 
