@@ -5,6 +5,11 @@ pair densities, then per grid chunk build K, form the intermediates and add
 the two-body and one-/zero-body terms, finalising V2, h1 and E0 on the last
 chunk.  Inputs are resident in HBM before the timed region starts.
 
+The headline form is split-BF16 with three products (FP64 for the
+occupied-occupied block and for the one-/zero-body reductions); the plain
+FP64 path is run once beside it for the speedup and the max-abs error of
+every output.
+
 The value is algorithmic GFLOP/s:
     F_alg = 6 Ng^2 Npair + 8 Ng Npair^2 + (18 n + 10) Ng Npair
 (K build, two-body assembly, intermediates; Npair = N(N+1)/2) divided by the
@@ -23,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "xTC 2-body build GFLOP/s at N=128: FP64 vs split-BF16 at ≤1e-6 Eh error"
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}   # TFLOP/s, dense MFMA
+TERMS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}                     # MFMA products per useful one
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}
 
 
@@ -98,8 +104,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="N128-occ16-Ng150k")
-    ap.add_argument("--prec", default="fp64", choices=list(PEAK))
-    ap.add_argument("--chunk", type=int, default=16384)
+    ap.add_argument("--prec", default="bf16x3", choices=list(PEAK))
+    ap.add_argument("--compare", default="fp64", help="form run once beside the headline one ('none' to skip)")
+    ap.add_argument("--chunk", type=int, default=None, help="grid rows per chunk (default 16384 FP64, 8192 reduced)")
     ap.add_argument("--cpu-rows", type=int, default=300, help="grid points of the CPU oracle sample (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -115,10 +122,28 @@ def main():
         sys.exit(1)
     wl = inputs.WORKLOADS[args.workload]
     problem = inputs.make_workload(args.workload)
-    print(f"[bench] {args.workload} prec={args.prec} chunk={args.chunk} warmup={args.warmup} steps={args.steps}",
+    chunk = args.chunk or (16384 if args.prec == "fp64" else 8192)
+    print(f"[bench] {args.workload} prec={args.prec} chunk={chunk} warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
-    r = run_gpu(problem, args.prec, args.steps, args.warmup, args.chunk)
+    r = run_gpu(problem, args.prec, args.steps, args.warmup, chunk)
     F = f_alg(wl.N, wl.nocc, wl.Ng)
+    forms = {args.prec: {"s_per_step": r["sec"], "gflops": F / r["sec"] / 1e9}}
+    if args.compare != "none" and args.compare != args.prec:
+        cchunk = 16384 if args.compare == "fp64" else 8192
+        print(f"[bench] comparison form {args.compare}: one step", file=sys.stderr, flush=True)
+        V2h, h1h, E0h = (t.clone() for t in r["outputs"])
+        del r["outputs"]
+        torch.cuda.empty_cache()
+        rc = run_gpu(problem, args.compare, 1, 0, cchunk)
+        V2c, h1c, E0c = rc["outputs"]
+        err = {"V2": (V2h - V2c).abs().max().item(), "h1": (h1h - h1c).abs().max().item(),
+               "E0": (E0h - E0c).abs().max().item()}
+        forms[args.compare] = {"s_per_step": rc["sec"], "gflops": F / rc["sec"] / 1e9}
+        forms[args.prec]["max_abs_err_vs_" + args.compare] = err
+        forms[args.prec]["speedup_vs_" + args.compare] = rc["sec"] / r["sec"]
+        print(f"[bench] {args.compare}: {rc['sec']:.3f} s/step; max|err| {err}", file=sys.stderr, flush=True)
+        del V2h, h1h, E0h, V2c, h1c, E0c, rc
+        torch.cuda.empty_cache()
     # roofline of the dominant kernel (K build): algorithmic flops per launch over
     # its average launch duration from HIP events on the launch stream
     tot_f = sum(f_kbuild(wl.N, rows, wl.Ng) for _, rows in r["kbuild"])
@@ -146,11 +171,13 @@ def main():
         "dtype": DTYPE[args.prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "N": wl.N, "nocc": wl.nocc, "Ng": wl.Ng, "prec": args.prec,
-                   "chunk_rows": args.chunk, "jastrow": wl.jastrow_kind, "F_alg_flop": F,
+                   "chunk_rows": chunk, "jastrow": wl.jastrow_kind, "F_alg_flop": F,
                    "workspace_bytes": r["ws_bytes"]},
-        "roofline": {"bound": "mfma", "kernel": "k_build_K", "achieved": achieved, "peak": peak,
+        "roofline": {"bound": "mfma", "kernel": "xtc_build_K", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "per_launch_flop": tot_f / nl, "avg_launch_ms": tot_t / nl * 1e3},
+                     "per_launch_flop": tot_f / nl, "avg_launch_ms": tot_t / nl * 1e3,
+                     "executed_mfma_frac": achieved * TERMS[args.prec] / peak},
+        "forms": forms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

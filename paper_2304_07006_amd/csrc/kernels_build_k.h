@@ -21,7 +21,6 @@ namespace xtc {
 constexpr int kKRowsPerWave = 16;
 constexpr int kKWaves = 4;
 constexpr int kKRows = kKRowsPerWave * kKWaves;   // 64 grid rows per workgroup
-constexpr int kKCols = 128;                        // pair columns per workgroup
 
 // Workgroup tile: 64 rows (g) x 128 pair columns; each wave owns 16 rows and
 // the 3 vector components of all 128 columns (24 accumulator blocks).
@@ -41,7 +40,7 @@ __global__ __launch_bounds__(256) void k_build_K_f64(const d4* __restrict__ pos,
     const int my = min(rloc0 + (lane & 15), rows - 1);      // row whose d^x this lane generates
     const d4 pg = pos[g0 + my];
     const int kq = lane >> 4;
-    const int col = ct * kKCols + 4 * (lane & 15);
+    const int col = ct * 128 + 4 * (lane & 15);
 
     d4 acc[3][8];
 #pragma unroll
@@ -91,6 +90,96 @@ __global__ __launch_bounds__(256) void k_build_K_f64(const d4* __restrict__ pos,
                 *(d4*)out = (d4){acc[x][0][v], acc[x][1][v], acc[x][2][v], acc[x][3][v]};
                 *(d4*)(out + 64) = (d4){acc[x][4][v], acc[x][5][v], acc[x][6][v], acc[x][7][v]};
             }
+        }
+    }
+}
+
+
+// Column-mapped variant (64*NH columns per workgroup):
+// Workgroup tile: 64 rows (g) x 64*NH pair columns; each wave owns 16 rows and
+// the 3 vector components of its 64*NH columns (12*NH accumulator blocks).
+// Tiles are numbered row-tile fastest, so workgroups resident at the same
+// time share one column strip of rho (read through L2), whatever XCD they
+// land on.  With colmap != nullptr, output column c < nmap is stored to
+// K[x][r][colmap[c]] (used to overwrite the occupied-occupied pairs of a
+// reduced-precision K with FP64 values); otherwise K has leading dim ldP.
+template <int KIND, int NH>
+__global__ __launch_bounds__(256) void k_build_K_f64_map(const d4* __restrict__ pos,
+                                                     const double* __restrict__ rho, int ldP,
+                                                     int ngp, int g0, int rows, int n_rt, JasDev J,
+                                                     double* __restrict__ K, const int* __restrict__ colmap,
+                                                     int nmap, int ldK) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int rt = blockIdx.x % n_rt;
+    const int ct = blockIdx.x / n_rt;
+    const int rloc0 = rt * kKRows + wave * kKRowsPerWave;   // first local row of this wave
+    const int my = min(rloc0 + (lane & 15), rows - 1);      // row whose d^x this lane generates
+    const d4 pg = pos[g0 + my];
+    const int kq = lane >> 4;
+    const int col = ct * 64 * NH + 4 * (lane & 15);
+
+    d4 acc[3][4 * NH];
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int c = 0; c < 4 * NH; ++c) acc[x][c] = (d4){0.0, 0.0, 0.0, 0.0};
+
+    const double* bp = rho + (size_t)kq * ldP + col;
+    const d4* pp = pos + kq;
+    d4 b0 = *(const d4*)bp;
+    d4 b1 = NH == 2 ? *(const d4*)(bp + 64) : b0;
+    d4 pc = *pp;
+    for (int kk = 0; kk < ngp; kk += 4) {
+        const d4 cb0 = b0, cb1 = b1, cp = pc;
+        if (kk + 4 < ngp) {              // prefetch the next 4 grid columns
+            bp += (size_t)4 * ldP;
+            pp += 4;
+            b0 = *(const d4*)bp;
+            if constexpr (NH == 2) b1 = *(const d4*)(bp + 64);
+            pc = *pp;
+        }
+        const double dx = pg.x - cp.x, dy = pg.y - cp.y, dz = pg.z - cp.z;
+        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const double f = du_over_r<KIND>(r2, J);
+        const double ax = dx * f, ay = dy * f, az = dz * f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            acc[0][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, cb0[c], acc[0][c], 0, 0, 0);
+            acc[1][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, cb0[c], acc[1][c], 0, 0, 0);
+            acc[2][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, cb0[c], acc[2][c], 0, 0, 0);
+        }
+        if constexpr (NH == 2) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                acc[0][4 + c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, cb1[c], acc[0][4 + c], 0, 0, 0);
+                acc[1][4 + c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, cb1[c], acc[1][4 + c], 0, 0, 0);
+                acc[2][4 + c] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, cb1[c], acc[2][4 + c], 0, 0, 0);
+            }
+        }
+    }
+    const size_t kstride = (size_t)rows * ldK;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = rloc0 + (lane >> 4) + 4 * v;
+        if (r < rows) {
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+#pragma unroll
+                for (int h = 0; h < NH; ++h) {
+                    const d4 val = {acc[x][4 * h + 0][v], acc[x][4 * h + 1][v], acc[x][4 * h + 2][v],
+                                    acc[x][4 * h + 3][v]};
+                    double* out = K + x * kstride + (size_t)r * ldK;
+                    if (colmap == nullptr) {
+                        *(d4*)(out + col + 64 * h) = val;
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int c = col + 64 * h + i;
+                            if (c < nmap) out[colmap[c]] = val[i];
+                        }
+                    }
+                }
         }
     }
 }

@@ -1,0 +1,484 @@
+// Reduced-precision forms of the two bulk contractions.
+//
+// FORM 1 : FP32 MFMA (v_mfma_f32_16x16x4_f32).
+// FORM 3 : split BF16, a = a0 + a1, products a0b0 + a0b1 + a1b0
+//          (v_mfma_f32_16x16x32_bf16).
+// FORM 6 : split BF16, a = a0 + a1 + a2, the six products of total order <= 2.
+// a0 = bf16(a), a1 = bf16(a - a0), a2 = bf16(a - a0 - a1), all round-to-nearest;
+// the residuals are exact in FP32.
+//
+// Accumulation is FP32 inside the MFMA over a segment of the summation index
+// (grid points); each segment writes an FP32 partial and a second kernel sums
+// the partials in FP64 in a fixed order (deterministic, no atomics).
+//
+// Operands live in a "k8-packed" layout [split][n/8][ld][8]: the 8 values of
+// consecutive summation indices for one output column are contiguous, which is
+// exactly one lane's operand of the BF16 MFMA (A[i][k], k = 8 (l/16) + e) and
+// eight consecutive k-steps of the FP32 MFMA once the summation index inside a
+// 32-step is permuted as k = 8 (l/16) + e (any permutation shared by A and B
+// leaves the sum unchanged).
+// Output layout of both MFMAs (decoded on gfx950): lane l holds rows
+// 4 (l/16) + v, v = 0..3, of column l % 16.
+#pragma once
+#include "xtc_device.h"
+
+#include <type_traits>
+
+namespace xtc {
+
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+
+template <int FORM> struct Lp;
+template <> struct Lp<1> { static constexpr int NS = 1; typedef float T; };
+template <> struct Lp<3> { static constexpr int NS = 2; typedef __bf16 T; };
+template <> struct Lp<6> { static constexpr int NS = 3; typedef __bf16 T; };
+
+constexpr int kLpK = 32;          // summation indices per k-step
+constexpr int kLpRows = 32;       // K build: grid rows per workgroup
+constexpr int kLpCols = 512;      // K build: pair columns per workgroup (ld multiple)
+constexpr int kLpARow = 40;       // LDS row pitch (elements) of the generated d tile
+
+template <int NS>
+__device__ __forceinline__ void split_bf16(float x, __bf16 (&t)[NS]) {
+    const __bf16 b0 = (__bf16)x;
+    t[0] = b0;
+    if constexpr (NS > 1) {
+        const float r1 = x - (float)b0;
+        const __bf16 b1 = (__bf16)r1;
+        t[1] = b1;
+        if constexpr (NS > 2) t[2] = (__bf16)(r1 - (float)b1);
+    }
+}
+
+// The split products of a form as (A-term, B-term) index pairs.  Callers loop
+// over terms outermost, so consecutive MFMAs write different accumulators and
+// never wait on each other's results.
+template <int FORM> struct Terms;
+template <> struct Terms<3> {
+    static constexpr int n = 3;
+    static constexpr int a[3] = {0, 0, 1};
+    static constexpr int b[3] = {0, 1, 0};
+};
+template <> struct Terms<6> {
+    static constexpr int n = 6;
+    static constexpr int a[6] = {0, 0, 1, 0, 1, 2};
+    static constexpr int b[6] = {0, 1, 0, 2, 1, 0};
+};
+
+__device__ __forceinline__ f4 mma_bf16(const bf8& a, const bf8& b, f4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+}
+
+// --------------------------------------------------------------------------
+// Pack an FP64 row-major array src[nrows][ld_src] (columns < ncols valid) into
+// the k8-packed operand format dst[s][n8][ld_dst][8]; rows >= nrows and
+// columns >= ncols become 0.
+template <int FORM>
+__global__ __launch_bounds__(256) void k_pack_lp(const double* __restrict__ src, int nrows, int ld_src,
+                                                 int ncols, int ld_dst, void* __restrict__ dst,
+                                                 size_t split_stride) {
+    const int P = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g8 = blockIdx.y;
+    if (P >= ld_dst) return;
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int g = 8 * g8 + e;
+        v[e] = (g < nrows && P < ncols) ? (float)src[(size_t)g * ld_src + P] : 0.0f;
+    }
+    const size_t o = ((size_t)g8 * ld_dst + P) * 8;
+    if constexpr (FORM == 1) {
+        f4* d = (f4*)((float*)dst + o);
+        d[0] = (f4){v[0], v[1], v[2], v[3]};
+        d[1] = (f4){v[4], v[5], v[6], v[7]};
+    } else {
+        constexpr int NS = Lp<FORM>::NS;
+        bf8 out[NS];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            __bf16 t[NS];
+            split_bf16<NS>(v[e], t);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) out[s][e] = t[s];
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) *(bf8*)((__bf16*)dst + s * split_stride + o) = out[s];
+    }
+}
+
+// --------------------------------------------------------------------------
+// u'(r)/r in FP32 for the reduced forms, from the hardware reciprocal and
+// reciprocal square root (about 1 ulp each; the split-BF16 operands carry
+// 2^-16 .. 2^-24 relative error, so IEEE division and square root would buy
+// nothing).  Exactly 0 at r^2 == 0.
+template <int KIND>
+__device__ __forceinline__ float du_over_r_fast(float r2, const JasDev& J) {
+    const float rs = __builtin_amdgcn_rsqf(r2);      // 1/r
+    const float r = r2 * rs;
+    float f;
+    if constexpr (KIND == 0) {
+        const float t = __builtin_amdgcn_rcpf(fmaf((float)J.b, r, 1.0f));
+        f = 0.5f * rs * t * t;
+    } else {
+        const float q = __builtin_amdgcn_rcpf(1.0f + r);
+        const float t = r * q;
+        float p = (float)J.dcoef[15];
+#pragma unroll
+        for (int k = 14; k >= 0; --k) p = fmaf(p, t, (float)J.dcoef[k]);
+        f = p * q * q * rs;
+    }
+    return r2 > 0.0f ? f : 0.0f;
+}
+
+// K build, reduced precision, one segment [seg*seg_len, ...) of the sum over g'.
+// Workgroup: 512 threads = 8 waves, tile 32 grid rows x 512 pair columns; each
+// wave owns all 32 rows x 64 columns x 3 components (2 x 4 blocks x 3 = 24 FP32
+// accumulator blocks), so every pair-density value is loaded by exactly one
+// wave, two waves share each SIMD, and the whole next k-step of that operand is
+// prefetched into registers while the current one is multiplied.
+// The d^x tile (32 rows x 32 g' x 3 components, already split) is generated
+// once per k-step by all 512 threads into LDS (double buffered) and shared by
+// the eight waves: generation is amortised over 512 columns.
+constexpr int kLpThreads = 512;
+template <int KIND, int FORM>
+__global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict__ pos,
+                                                           const void* __restrict__ rho_lp, size_t split_stride,
+                                                           int ldL, int ngp, int g0, int rows, int n_rt,
+                                                           int seg_len, JasDev J, float* __restrict__ part,
+                                                           int cap) {
+    typedef typename Lp<FORM>::T T;
+    constexpr int NS = Lp<FORM>::NS;
+    constexpr int NB = 4;                          // 16-column blocks per wave
+    // two generation buffers as distinct arrays, so the compiler can prove the
+    // writes of the next k-step do not alias the reads of the current one
+    typedef T ATile[3][NS][kLpRows][kLpARow];
+    __shared__ __attribute__((aligned(16))) ATile sA0;
+    __shared__ __attribute__((aligned(16))) ATile sA1;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rt = blockIdx.x % n_rt, ct = blockIdx.x / n_rt;
+    const int seg = blockIdx.y;
+    const int gs = seg * seg_len;
+    const int ge = min(ngp, gs + seg_len);
+    // generation role: one row, two consecutive g' per k-step
+    const int grow = threadIdx.x & 31, gk = 2 * (threadIdx.x >> 5);
+    const d4 pr = pos[g0 + min(rt * kLpRows + grow, rows - 1)];
+    // MFMA role
+    const int l16 = lane & 15, lk = lane >> 4;
+    const int col0 = ct * kLpCols + wave * 64 + l16;
+
+    f4 acc[3][2][NB];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[c][h][b] = (f4){0.f, 0.f, 0.f, 0.f};
+
+    // positions of the two g' this thread generates, loaded one k-step ahead
+    d4 pnext[2];
+    auto loadP = [&](int kk) {
+        pnext[0] = pos[kk + gk];
+        pnext[1] = pos[kk + gk + 1];
+    };
+    auto gen = [&](const d4 (&P)[2], ATile& W) {
+        float a[3][2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const d4 pp = P[j];
+            const float dx = (float)(pr.x - pp.x), dy = (float)(pr.y - pp.y), dz = (float)(pr.z - pp.z);
+            const float f = du_over_r_fast<KIND>(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), J);
+            a[0][j] = dx * f;
+            a[1][j] = dy * f;
+            a[2][j] = dz * f;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if constexpr (FORM == 1) {
+                W[c][0][grow][gk] = a[c][0];
+                W[c][0][grow][gk + 1] = a[c][1];
+            } else {
+                __bf16 t0[NS], t1[NS];
+                split_bf16<NS>(a[c][0], t0);
+                split_bf16<NS>(a[c][1], t1);
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    W[c][s][grow][gk] = t0[s];
+                    W[c][s][grow][gk + 1] = t1[s];
+                }
+            }
+        }
+    };
+
+    // pair-density operand of the wave's 4 column blocks for one k-step
+    typedef typename std::conditional<FORM == 1, f4[NB][2], bf8[NB][NS]>::type BOp;
+    auto loadB = [&](int kk, BOp& out) {
+        const size_t o = ((size_t)(kk / 8 + lk) * ldL + col0) * 8;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if constexpr (FORM == 1) {
+                const f4* p = (const f4*)((const float*)rho_lp + o + 128 * b);
+                out[b][0] = p[0];
+                out[b][1] = p[1];
+            } else {
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+                    out[b][s] = *(const bf8*)((const __bf16*)rho_lp + s * split_stride + o + 128 * b);
+            }
+        }
+    };
+
+    BOp bnext;
+    // one k-step: multiply the tile in R (and the operand prefetched in bnext)
+    // while generating the next tile into W and prefetching its operand
+    auto step = [&](int kk, const ATile& R, ATile& W) {
+        BOp bv;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int s = 0; s < (FORM == 1 ? 2 : NS); ++s) bv[b][s] = bnext[b][s];
+        // next k-step (on the last step this re-reads the current one into the
+        // idle buffer, which is never consumed: no branch in the loop body)
+        const int kn = min(kk + kLpK, ge - kLpK);
+        const int kn2 = min(kk + 2 * kLpK, ge - kLpK);
+        const d4 pcur[2] = {pnext[0], pnext[1]};
+        loadP(kn2);
+        if constexpr (FORM == 1) {
+            loadB(kn, bnext);
+            gen(pcur, W);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float av[3][8];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const f4 x0 = *(const f4*)&R[c][0][16 * h + l16][8 * lk];
+                    const f4 x1 = *(const f4*)&R[c][0][16 * h + l16][8 * lk + 4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) { av[c][e] = x0[e]; av[c][4 + e] = x1[e]; }
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const float be = e < 4 ? bv[b][0][e] : bv[b][1][e - 4];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            acc[c][h][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][e], be, acc[c][h][b], 0, 0, 0);
+                    }
+            }
+        } else {
+            loadB(kn, bnext);
+            gen(pcur, W);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                bf8 av[3][NS];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) av[c][s] = *(const bf8*)&R[c][s][16 * h + l16][8 * lk];
+#pragma unroll
+                for (int t = 0; t < Terms<FORM>::n; ++t)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            acc[c][h][b] = mma_bf16(av[c][Terms<FORM>::a[t]], bv[b][Terms<FORM>::b[t]], acc[c][h][b]);
+            }
+        }
+        // instruction order: operand reads first, then every MFMA paired with
+        // generation VALU work for the next k-step
+        constexpr int kMfmaHalf = (FORM == 1 ? 8 : (FORM == 3 ? 3 : 6)) * 3 * NB;
+        constexpr int kValuPer = FORM == 1 ? 1 : 2;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 3 * NS * (FORM == 1 ? 2 : 1), 0);
+#pragma unroll
+            for (int i = 0; i < kMfmaHalf; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, kValuPer, 0);
+            }
+        }
+    };
+
+    loadB(gs, bnext);
+    loadP(gs);
+    {
+        const d4 p0[2] = {pnext[0], pnext[1]};
+        gen(p0, sA0);
+    }
+    loadP(min(gs + kLpK, ge - kLpK));
+    __syncthreads();
+    // (ge - gs) is a multiple of 2 k-steps: segments and the padded grid are
+    // multiples of 64 points
+    for (int kk = gs; kk < ge; kk += 2 * kLpK) {
+        step(kk, sA0, sA1);
+        __syncthreads();
+        step(kk + kLpK, sA1, sA0);
+        __syncthreads();
+    }
+
+    const size_t cstride = (size_t)cap * ldL;
+    float* out = part + (size_t)seg * 3 * cstride;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = rt * kLpRows + 16 * h + 4 * lk + v;
+            if (r < rows) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        out[c * cstride + (size_t)r * ldL + col0 + 16 * b] = acc[c][h][b][v];
+            }
+        }
+}
+
+// K[c][r][P] = sum_s part[s][c][r][P] in FP64 (fixed order), for r < rows, P < ldP.
+__global__ void k_reduce_K(const float* __restrict__ part, int nseg, int cap, int ldL, int rows, int ldP,
+                           double* __restrict__ K) {
+    const size_t n = (size_t)3 * rows * ldP;
+    const size_t cstride = (size_t)cap * ldL;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int P = (int)(i % ldP);
+        const size_t cr = i / ldP;
+        const int r = (int)(cr % rows), c = (int)(cr / rows);
+        const size_t o = c * cstride + (size_t)r * ldL + P;
+        double s = 0.0;
+        for (int q = 0; q < nseg; ++q) s += (double)part[(size_t)q * 3 * cstride + o];
+        K[i] = s;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Two-body assembly, reduced precision, one (component, row segment) per grid.y:
+//   part[seg][P][R] = sum_{g in segment} C_c[g][P] D_c[g][R]   (FP32)
+// Workgroup tile 128 (P) x 256 (R), waves 2 x 2 of 64 x 128 (4 x 8 MFMA blocks).
+// Clp/Dlp: [4 comps][NS][n8][ldL][8]; comp_stride = NS * split_stride.
+template <int FORM>
+__global__ __launch_bounds__(256) void k_gemm2b_lp(const void* __restrict__ Clp, const void* __restrict__ Dlp,
+                                                   size_t split_stride, int rows32, int ldL, int n_pt,
+                                                   int seg_len, int nseg_r, float* __restrict__ part) {
+    constexpr int NS = Lp<FORM>::NS;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int pt = blockIdx.x % n_pt, rt = blockIdx.x / n_pt;
+    const int comp = blockIdx.y / nseg_r, sg = blockIdx.y % nseg_r;
+    const int gs = sg * seg_len, ge = min(rows32, gs + seg_len);
+    const int l16 = lane & 15, lk = lane >> 4;
+    const int P0 = pt * 128 + 64 * (wave & 1) + l16;
+    const int R0 = rt * 256 + 128 * (wave >> 1) + l16;
+    const size_t comp_stride = (size_t)NS * split_stride;
+    f4 acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+    for (int kk = gs; kk < ge; kk += kLpK) {
+        const size_t brow = (size_t)(kk / 8 + lk) * ldL;
+        if constexpr (FORM == 1) {
+            const float* Cb = (const float*)Clp + comp * comp_stride;
+            const float* Db = (const float*)Dlp + comp * comp_stride;
+            float av[4][8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const f4* p = (const f4*)(Cb + (brow + P0 + 16 * i) * 8);
+                const f4 x0 = p[0], x1 = p[1];
+                av[i][0] = x0[0]; av[i][1] = x0[1]; av[i][2] = x0[2]; av[i][3] = x0[3];
+                av[i][4] = x1[0]; av[i][5] = x1[1]; av[i][6] = x1[2]; av[i][7] = x1[3];
+            }
+#pragma unroll
+            for (int jh = 0; jh < 8; jh += 4) {
+                float bv[4][8];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const f4* p = (const f4*)(Db + (brow + R0 + 16 * (jh + j)) * 8);
+                    const f4 y0 = p[0], y1 = p[1];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) { bv[j][e] = y0[e]; bv[j][4 + e] = y1[e]; }
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            acc[i][jh + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][e], bv[j][e], acc[i][jh + j], 0, 0, 0);
+            }
+        } else {
+            const __bf16* Cb = (const __bf16*)Clp + comp * comp_stride;
+            const __bf16* Db = (const __bf16*)Dlp + comp * comp_stride;
+            bf8 av[4][NS];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) av[i][s] = *(const bf8*)(Cb + s * split_stride + (brow + P0 + 16 * i) * 8);
+#pragma unroll
+            for (int jh = 0; jh < 8; jh += 4) {
+                bf8 bv[4][NS];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int s = 0; s < NS; ++s)
+                        bv[j][s] = *(const bf8*)(Db + s * split_stride + (brow + R0 + 16 * (jh + j)) * 8);
+#pragma unroll
+                for (int t = 0; t < Terms<FORM>::n; ++t)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            acc[i][jh + j] = mma_bf16(av[i][Terms<FORM>::a[t]], bv[j][Terms<FORM>::b[t]], acc[i][jh + j]);
+            }
+        }
+    }
+    float* out = part + (size_t)blockIdx.y * ldL * ldL;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int P = P0 - l16 + 16 * i + 4 * lk + v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) out[(size_t)P * ldL + R0 + 16 * j] = acc[i][j][v];
+        }
+}
+
+// M[P][R] (+)= sum_s part[s][P][R] in FP64 (fixed order), P, R < ldP.
+__global__ void k_reduce_M(const float* __restrict__ part, int nseg, int ldL, int ldP, double* __restrict__ M,
+                           int accumulate) {
+    const size_t n = (size_t)ldP * ldP;
+    const size_t sstride = (size_t)ldL * ldL;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t P = i / ldP, R = i % ldP;
+        const size_t o = P * ldL + R;
+        double s = accumulate ? M[i] : 0.0;
+        for (int q = 0; q < nseg; ++q) s += (double)part[q * sstride + o];
+        M[i] = s;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Occupied-occupied pairs: colmap[j] = pair(occ[a], occ[b]) for a <= b (j in
+// row-major order of (a, b)); rho_occ[g][j] = rho[g][colmap[j]], zero padded.
+__global__ void k_occ_pairs(OccList occ, int N, int* __restrict__ colmap, int ldO) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ldO) return;
+    const int n = occ.n;
+    const int npair = n * (n + 1) / 2;
+    if (j >= npair) { colmap[j] = -1; return; }
+    int a = 0, rem = j;
+    while (rem >= n - a) { rem -= n - a; ++a; }
+    const int b = a + rem;
+    colmap[j] = pair_sym(occ.k[a], occ.k[b], N);
+}
+
+__global__ void k_gather_occ(const double* __restrict__ rho, int ldP, int ngp, const int* __restrict__ colmap,
+                             int ldO, double* __restrict__ rho_occ) {
+    const size_t n = (size_t)ngp * ldO;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(i % ldO);
+        const size_t g = i / ldO;
+        const int P = colmap[j];
+        rho_occ[i] = P >= 0 ? rho[g * ldP + P] : 0.0;
+    }
+}
+
+}  // namespace xtc

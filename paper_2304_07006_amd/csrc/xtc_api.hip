@@ -5,15 +5,20 @@
 // and ngp = Ng rounded up to 128:
 //   pos    [ngp] x 4 doubles          grid positions (x, y, z, 0)
 //   rho    [ngp][ldP] doubles         weighted pair densities, zero padded
-//   lp     reduced-precision operands of the K build (prec != FP64)
+//   rho_lp [NS][ngp/8][ldL][8]        reduced-precision rho (k8-packed), prec != FP64
+//   rho_occ[ngp][ldO], colmap[ldO]    FP64 rho of the occupied-occupied pairs
 //   M      [ldP][ldP] doubles         FP64 accumulator of the two-body term
 //   h1acc  [ldP] doubles              FP64 accumulator of the one-body term
 //   T1     [kT1Split][ldP] doubles    per-split partials (one-body, term 1)
 //   E      [kESplit][N][N] doubles    per-split partials (one-body, exchange)
 //   S      [cap][8] doubles           per-point scalars of the current chunk
 //   D      [4][cap][ldP] doubles      A, Bx, By, Bz of the current chunk
-// The chunk capacity `cap` is the largest multiple of 4 rows that fits in the
-// bytes the caller passes, so every call with the same ws_bytes agrees on it.
+//   Kpart  [nsegK][3][cap][ldL] f32   K-build segment partials     (prec != FP64)
+//   CDlp   [8][NS][cap/8][ldL][8]     C and D of the chunk, k8-packed (prec != FP64)
+//   Mpart  [4*ceil(cap/kSegM)][ldL][ldL] f32  two-body partials    (prec != FP64)
+// ldL = ldP rounded up to 512.  The chunk capacity `cap` is the largest
+// multiple of 32 rows that fits in the bytes the caller passes, so every call
+// with the same ws_bytes agrees on it.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,6 +31,7 @@
 #include "../../include/xtc.h"
 #include "kernels_build_k.h"
 #include "kernels_contract.h"
+#include "kernels_lp.h"
 #include "kernels_prepare.h"
 
 using namespace xtc;
@@ -58,52 +64,77 @@ int pair_ld(int N) {
     return (int)((npair + kPairTile - 1) / kPairTile * kPairTile);
 }
 
+constexpr int kSegK = 8192;     // g' per FP32 segment of the reduced-precision K build
+constexpr int kSegM = 2048;     // grid rows per FP32 segment of the reduced-precision two-body GEMM
+constexpr int kRowQuant = 32;
+
 struct Layout {
-    int N, Ng, nocc, ldP, ngp, Npair;
-    size_t pos, rho, lp, M, h1acc, T1, E, S, D;
-    size_t fixed;        // bytes before S
-    size_t per_row;      // bytes per chunk row (S + D)
-    int cap;             // chunk rows that fit (multiple of 4)
+    int N, Ng, nocc, ldP, ngp, Npair, prec;
+    int form, ns, es, ldL, ldO, nOP, nsegK;
+    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E;
+    size_t fixed;        // bytes before S (plus the Mpart remainder reserve)
+    size_t per_row;      // bytes per chunk row
+    int cap;             // chunk rows that fit (multiple of kRowQuant)
+    int nsegM;
+    size_t S, D, Kpart, CDlp, Mpart, end;
 };
 
-size_t lp_bytes(int prec, int ngp, int ldP) {
-    switch (prec) {
-        case XTC_FP64: return 0;
-        default: return 0;   // reduced-precision operand formats are added with their kernels
-    }
-}
+int form_of(int prec) { return prec == XTC_FP32 ? 1 : prec == XTC_BF16X3 ? 3 : prec == XTC_BF16X6 ? 6 : 0; }
 
 Layout make_layout(const xtc_problem* pb, int prec) {
     Layout L{};
     L.N = pb->N;
     L.Ng = pb->Ng;
     L.nocc = pb->nocc;
+    L.prec = prec;
     L.ldP = pair_ld(pb->N);
     L.Npair = pb->N * (pb->N + 1) / 2;
     L.ngp = (int)align_up((size_t)pb->Ng, kGridPad);
+    L.form = form_of(prec);
+    L.ns = L.form == 1 ? 1 : L.form == 3 ? 2 : L.form == 6 ? 3 : 0;
+    L.es = L.form == 1 ? 4 : 2;
+    L.ldL = (int)align_up((size_t)L.ldP, kLpCols);
+    L.nOP = pb->nocc * (pb->nocc + 1) / 2;
+    L.ldO = (int)align_up((size_t)L.nOP, 64);
+    L.nsegK = (L.ngp + kSegK - 1) / kSegK;
+    const bool lp = L.form != 0;
     size_t off = 0;
-    L.pos = off;   off = align_up(off + (size_t)L.ngp * 4 * sizeof(double), kAlign);
-    L.rho = off;   off = align_up(off + (size_t)L.ngp * L.ldP * sizeof(double), kAlign);
-    L.lp = off;    off = align_up(off + lp_bytes(prec, L.ngp, L.ldP), kAlign);
-    L.M = off;     off = align_up(off + (size_t)L.ldP * L.ldP * sizeof(double), kAlign);
-    L.h1acc = off; off = align_up(off + (size_t)L.ldP * sizeof(double), kAlign);
-    L.T1 = off;    off = align_up(off + (size_t)kT1Split * L.ldP * sizeof(double), kAlign);
-    L.E = off;     off = align_up(off + (size_t)kESplitMax * L.N * L.N * sizeof(double), kAlign);
-    L.fixed = off;
+    L.pos = off;     off = align_up(off + (size_t)L.ngp * 4 * sizeof(double), kAlign);
+    L.rho = off;     off = align_up(off + (size_t)L.ngp * L.ldP * sizeof(double), kAlign);
+    L.rho_lp = off;  off = align_up(off + (lp ? (size_t)L.ns * L.ngp * L.ldL * L.es : 0), kAlign);
+    L.rho_occ = off; off = align_up(off + (lp ? (size_t)L.ngp * L.ldO * sizeof(double) : 0), kAlign);
+    L.colmap = off;  off = align_up(off + (lp ? (size_t)L.ldO * sizeof(int) : 0), kAlign);
+    L.M = off;       off = align_up(off + (size_t)L.ldP * L.ldP * sizeof(double), kAlign);
+    L.h1acc = off;   off = align_up(off + (size_t)L.ldP * sizeof(double), kAlign);
+    L.T1 = off;      off = align_up(off + (size_t)kT1Split * L.ldP * sizeof(double), kAlign);
+    L.E = off;       off = align_up(off + (size_t)kESplitMax * L.N * L.N * sizeof(double), kAlign);
+    const size_t mslab = (size_t)4 * L.ldL * L.ldL * sizeof(float);       // one partial per component
+    L.fixed = off + (lp ? mslab : 0) + 8 * kAlign;
     L.per_row = (size_t)8 * sizeof(double) + (size_t)4 * L.ldP * sizeof(double);
+    if (lp)
+        L.per_row += (size_t)L.nsegK * 3 * L.ldL * sizeof(float) + (size_t)8 * L.ns * L.ldL * L.es +
+                     (mslab + kSegM - 1) / kSegM;
     L.cap = 0;
     return L;
 }
 
-// Chunk capacity that `bytes` allows, and the offsets of S and D for it.
+// Chunk capacity that `bytes` allows, and the offsets of the chunk buffers for it.
 void place_chunk(Layout& L, size_t bytes) {
-    const size_t slack = 2 * kAlign;
-    long cap = bytes > L.fixed + slack ? (long)((bytes - L.fixed - slack) / L.per_row) : 0;
-    cap = cap / 4 * 4;
-    if (cap > (long)align_up((size_t)L.Ng, 4)) cap = (long)align_up((size_t)L.Ng, 4);
+    long cap = bytes > L.fixed ? (long)((bytes - L.fixed) / L.per_row) : 0;
+    cap = cap / kRowQuant * kRowQuant;
+    const long most = (long)align_up((size_t)L.Ng, kRowQuant);
+    if (cap > most) cap = most;
     L.cap = (int)cap;
-    L.S = L.fixed;
-    L.D = align_up(L.S + (size_t)cap * 8 * sizeof(double), kAlign);
+    const bool lp = L.form != 0;
+    L.nsegM = lp ? 4 * (int)((cap + kSegM - 1) / kSegM) : 0;
+    size_t off = L.fixed - 8 * kAlign - (lp ? (size_t)4 * L.ldL * L.ldL * sizeof(float) : 0);
+    L.S = off;       off = align_up(off + (size_t)cap * 8 * sizeof(double), kAlign);
+    L.D = off;       off = align_up(off + (size_t)4 * cap * L.ldP * sizeof(double), kAlign);
+    L.Kpart = off;   off = align_up(off + (lp ? (size_t)L.nsegK * 3 * cap * L.ldL * sizeof(float) : 0), kAlign);
+    L.CDlp = off;    off = align_up(off + (lp ? (size_t)8 * L.ns * cap * L.ldL * L.es : 0), kAlign);
+    L.Mpart = off;   off = align_up(off + (lp ? (size_t)L.nsegM * L.ldL * L.ldL * sizeof(float) : 0), kAlign);
+    L.end = off;
+    if (L.end > bytes) L.cap = 0;   // cannot happen by construction; refuse rather than overrun
 }
 
 size_t lds_intermediates(const Layout& L) { return (size_t)L.nocc * L.N * 4 * sizeof(double); }
@@ -132,7 +163,6 @@ xtc_status check_problem(const xtc_problem* pb) {
 xtc_status check_prec(int prec) {
     if (prec != XTC_FP64 && prec != XTC_FP32 && prec != XTC_BF16X3 && prec != XTC_BF16X6)
         return fail(XTC_E_ARG, "prec=%d unknown", prec);
-    if (prec != XTC_FP64) return fail(XTC_E_UNSUPPORTED, "prec=%d not available in this build", prec);
     return XTC_OK;
 }
 
@@ -161,8 +191,9 @@ xtc_status check_jastrow(const xtc_jastrow* j, JasDev* out) {
 xtc_status check_ws(const Layout& L, void* ws, size_t bytes) {
     if (!ws) return fail(XTC_E_WORKSPACE, "workspace is NULL");
     if ((uintptr_t)ws % kAlign) return fail(XTC_E_WORKSPACE, "workspace not 256-byte aligned");
-    if (L.cap < 4) return fail(XTC_E_WORKSPACE, "workspace of %zu bytes holds no chunk (need > %zu)", bytes,
-                               L.fixed + 2 * kAlign + 4 * L.per_row);
+    if (L.cap < kRowQuant)
+        return fail(XTC_E_WORKSPACE, "workspace of %zu bytes holds no chunk (need >= %zu)", bytes,
+                    L.fixed + kRowQuant * L.per_row);
     return XTC_OK;
 }
 
@@ -219,6 +250,102 @@ xtc_status run_intermediates(const Layout& L, const xtc_problem* pb, const doubl
     return launched("intermediates");
 }
 
+// ---------------------------------------------------------------- reduced precision
+template <int FORM>
+xtc_status pack_lp(const double* src, int nrows, int ld_src, int ncols, int n8, int ld_dst, void* dst,
+                   size_t split_stride, hipStream_t st) {
+    hipLaunchKernelGGL((k_pack_lp<FORM>), dim3((ld_dst + 255) / 256, n8), dim3(256), 0, st, src, nrows, ld_src, ncols,
+                       ld_dst, dst, split_stride);
+    return launched("pack_lp");
+}
+
+xtc_status pack_any(int form, const double* src, int nrows, int ld_src, int ncols, int n8, int ld_dst, void* dst,
+                    size_t split_stride, hipStream_t st) {
+    switch (form) {
+        case 1: return pack_lp<1>(src, nrows, ld_src, ncols, n8, ld_dst, dst, split_stride, st);
+        case 3: return pack_lp<3>(src, nrows, ld_src, ncols, n8, ld_dst, dst, split_stride, st);
+        default: return pack_lp<6>(src, nrows, ld_src, ncols, n8, ld_dst, dst, split_stride, st);
+    }
+}
+
+template <int KIND, int FORM>
+void launch_build_lp(const Layout& L, int g0, int rows, const JasDev& J, void* ws, hipStream_t st) {
+    const int n_rt = (rows + kLpRows - 1) / kLpRows;
+    const int n_ct = L.ldL / kLpCols;
+    hipLaunchKernelGGL((k_build_K_lp<KIND, FORM>), dim3(n_rt * n_ct, L.nsegK), dim3(kLpThreads), 0, st, at<d4>(ws, L.pos),
+                       at<void>(ws, L.rho_lp), (size_t)L.ngp * L.ldL, L.ldL, L.ngp, g0, rows, n_rt, kSegK, J,
+                       at<float>(ws, L.Kpart), L.cap);
+}
+
+xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double* K, void* ws, hipStream_t st) {
+    if (J.kind == 0) {
+        if (L.form == 1) launch_build_lp<0, 1>(L, g0, rows, J, ws, st);
+        else if (L.form == 3) launch_build_lp<0, 3>(L, g0, rows, J, ws, st);
+        else launch_build_lp<0, 6>(L, g0, rows, J, ws, st);
+    } else {
+        if (L.form == 1) launch_build_lp<1, 1>(L, g0, rows, J, ws, st);
+        else if (L.form == 3) launch_build_lp<1, 3>(L, g0, rows, J, ws, st);
+        else launch_build_lp<1, 6>(L, g0, rows, J, ws, st);
+    }
+    xtc_status s;
+    if ((s = launched("build_K_lp")) != XTC_OK) return s;
+    const size_t n = (size_t)3 * rows * L.ldP;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_reduce_K, dim3(blocks), dim3(256), 0, st, at<float>(ws, L.Kpart), L.nsegK, L.cap, L.ldL,
+                       rows, L.ldP, K);
+    if ((s = launched("reduce_K")) != XTC_OK) return s;
+    // occupied-occupied pairs in FP64, written over the reduced-precision values
+    const int n_rt = (rows + kKRows - 1) / kKRows;
+    const dim3 grid(n_rt * (L.ldO / 64));
+    if (J.kind == 0)
+        hipLaunchKernelGGL((k_build_K_f64_map<0, 1>), grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho_occ),
+                           L.ldO, L.ngp, g0, rows, n_rt, J, K, at<int>(ws, L.colmap), L.nOP, L.ldP);
+    else
+        hipLaunchKernelGGL((k_build_K_f64_map<1, 1>), grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho_occ),
+                           L.ldO, L.ngp, g0, rows, n_rt, J, K, at<int>(ws, L.colmap), L.nOP, L.ldP);
+    return launched("build_K_occ_f64");
+}
+
+xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int accumulate, void* ws, hipStream_t st) {
+    xtc_status s;
+    const int rows32 = (int)align_up((size_t)rows, kRowQuant);
+    const int n8 = rows32 / 8;
+    const size_t split_stride = (size_t)L.cap * L.ldL;                 // elements of one split of one component
+    const size_t comp_bytes = (size_t)L.ns * split_stride * L.es;
+    char* cd = at<char>(ws, L.CDlp);
+    const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
+    const double* D = at<double>(ws, L.D);
+    for (int c = 0; c < 4; ++c) {
+        const double* src = c == 0 ? rho_rows : K + (size_t)(c - 1) * rows * L.ldP;
+        if ((s = pack_any(L.form, src, rows, L.ldP, L.ldP, n8, L.ldL, cd + c * comp_bytes, split_stride, st)) != XTC_OK)
+            return s;
+        if ((s = pack_any(L.form, D + (size_t)c * L.cap * L.ldP, rows, L.ldP, L.ldP, n8, L.ldL,
+                          cd + (4 + c) * comp_bytes, split_stride, st)) != XTC_OK)
+            return s;
+    }
+    const int n_pt = L.ldL / 128, n_rt = L.ldL / 256;
+    const int nseg_r = (rows32 + kSegM - 1) / kSegM;
+    const dim3 grid(n_pt * n_rt, 4 * nseg_r);
+    const void* C = cd;
+    const void* Dl = cd + 4 * comp_bytes;
+    float* part = at<float>(ws, L.Mpart);
+    if (L.form == 1)
+        hipLaunchKernelGGL((k_gemm2b_lp<1>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt, kSegM,
+                           nseg_r, part);
+    else if (L.form == 3)
+        hipLaunchKernelGGL((k_gemm2b_lp<3>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt, kSegM,
+                           nseg_r, part);
+    else
+        hipLaunchKernelGGL((k_gemm2b_lp<6>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt, kSegM,
+                           nseg_r, part);
+    if ((s = launched("gemm_2body_lp")) != XTC_OK) return s;
+    const size_t n = (size_t)L.ldP * L.ldP;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_reduce_M, dim3(blocks), dim3(256), 0, st, part, 4 * nseg_r, L.ldL, L.ldP, at<double>(ws, L.M),
+                       accumulate);
+    return launched("reduce_M");
+}
+
 }  // namespace
 
 extern "C" {
@@ -235,8 +362,8 @@ size_t xtc_workspace_size(const xtc_problem* pb, int32_t prec, int32_t chunk_row
         return 0;
     }
     Layout L = make_layout(pb, prec);
-    const size_t rows = align_up((size_t)chunk_rows, 4);
-    return L.fixed + 2 * kAlign + rows * L.per_row;
+    const size_t rows = align_up((size_t)chunk_rows, kRowQuant);
+    return L.fixed + rows * L.per_row;
 }
 
 xtc_status xtc_prepare(const xtc_problem* pb, int32_t prec, int32_t chunk_rows, void* ws, size_t ws_bytes,
@@ -257,6 +384,17 @@ xtc_status xtc_prepare(const xtc_problem* pb, int32_t prec, int32_t chunk_rows, 
     hipLaunchKernelGGL(k_prepare_rho, dim3(L.ngp / kPrepRows), dim3(256), lds, st, pb->phi, pb->w, L.N, L.Ng,
                        L.ngp, L.ldP, at<double>(ws, L.rho));
     if ((s = launched("prepare_rho")) != XTC_OK) return s;
+    if (L.form != 0) {
+        if ((s = pack_any(L.form, at<double>(ws, L.rho), L.ngp, L.ldP, L.ldP, L.ngp / 8, L.ldL, at<void>(ws, L.rho_lp),
+                          (size_t)L.ngp * L.ldL, st)) != XTC_OK)
+            return s;
+        hipLaunchKernelGGL(k_occ_pairs, dim3((L.ldO + 255) / 256), dim3(256), 0, st, make_occ(pb), L.N,
+                           at<int>(ws, L.colmap), L.ldO);
+        if ((s = launched("occ_pairs")) != XTC_OK) return s;
+        hipLaunchKernelGGL(k_gather_occ, dim3(4096), dim3(256), 0, st, at<double>(ws, L.rho), L.ldP, L.ngp,
+                           at<int>(ws, L.colmap), L.ldO, at<double>(ws, L.rho_occ));
+        if ((s = launched("gather_occ")) != XTC_OK) return s;
+    }
     // zero the accumulators and the chunk buffers (padding columns of D stay 0)
     if ((s = fill(at<double>(ws, L.M), (size_t)L.ldP * L.ldP, st)) != XTC_OK) return s;
     if ((s = fill(at<double>(ws, L.h1acc), (size_t)L.ldP, st)) != XTC_OK) return s;
@@ -279,8 +417,9 @@ xtc_status xtc_build_K(const xtc_problem* pb, const xtc_jastrow* jas, int32_t g0
     if ((s = check_range(L, g0, g1)) != XTC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     const int rows = g1 - g0;
+    if (L.form != 0) return build_K_lp(L, g0, rows, J, K, ws, st);
     const int n_rt = (rows + kKRows - 1) / kKRows;
-    const int n_ct = L.ldP / kKCols;
+    const int n_ct = L.ldP / 128;
     const dim3 grid(n_rt * n_ct);
     if (J.kind == 0)
         hipLaunchKernelGGL(k_build_K_f64<0>, grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
@@ -307,12 +446,16 @@ xtc_status xtc_contract_2body(const xtc_problem* pb, const double* K, int32_t g0
     hipStream_t st = (hipStream_t)stream;
     if ((s = run_intermediates(L, pb, K, g0, g1, ws, st)) != XTC_OK) return s;
     const int rows = g1 - g0;
-    const int n_t = L.ldP / 128;
-    const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
-    hipLaunchKernelGGL(k_gemm2b_f64, dim3(n_t * n_t), dim3(256), 0, st, rho_rows, K, at<double>(ws, L.D),
-                       (size_t)L.cap * L.ldP, rows, L.ldP, n_t, at<double>(ws, L.M),
-                       (flags & XTC_RESET) ? 0 : 1);
-    if ((s = launched("gemm_2body")) != XTC_OK) return s;
+    if (L.form != 0) {
+        if ((s = gemm2b_lp(L, K, g0, rows, (flags & XTC_RESET) ? 0 : 1, ws, st)) != XTC_OK) return s;
+    } else {
+        const int n_t = L.ldP / 128;
+        const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
+        hipLaunchKernelGGL(k_gemm2b_f64, dim3(n_t * n_t), dim3(256), 0, st, rho_rows, K, at<double>(ws, L.D),
+                           (size_t)L.cap * L.ldP, rows, L.ldP, n_t, at<double>(ws, L.M),
+                           (flags & XTC_RESET) ? 0 : 1);
+        if ((s = launched("gemm_2body")) != XTC_OK) return s;
+    }
     if (flags & XTC_FINALIZE) {
         const int NN = L.N * L.N;
         hipLaunchKernelGGL(k_finalize_V2, dim3((NN + 255) / 256, L.N, L.N), dim3(256), 0, st, at<double>(ws, L.M),

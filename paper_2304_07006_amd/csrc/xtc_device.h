@@ -13,7 +13,9 @@ constexpr int kPairTile = 128;   // pair-column padding unit (xtc_pair_ld)
 constexpr int kGridPad = 128;    // grid-row padding unit of the prepared operands
 
 // Jastrow parameters as kernels see them.  dcoef[k] = (k+1) coef[k], so the
-// power-form derivative is a Horner polynomial in t = r/(1+r).
+// power-form derivative is a Horner polynomial in t = r/(1+r); entries beyond
+// ncoef are zero, so all 16 terms are evaluated (leading zero terms leave the
+// Horner value exactly unchanged) without a data-dependent loop.
 struct JasDev {
     int32_t kind;    // 0 Pade, 1 power
     int32_t ncoef;
@@ -35,8 +37,9 @@ __device__ __forceinline__ double du_over_r(double r2, const JasDev& J) {
     } else {
         const double q = 1.0 / (1.0 + r);
         const double t = r * q;
-        double p = J.dcoef[J.ncoef - 1];
-        for (int k = J.ncoef - 2; k >= 0; --k) p = fma(p, t, J.dcoef[k]);
+        double p = J.dcoef[15];
+#pragma unroll
+        for (int k = 14; k >= 0; --k) p = fma(p, t, J.dcoef[k]);
         f = p * q * q / r;
     }
     return r2 > 0.0 ? f : 0.0;
@@ -52,8 +55,9 @@ __device__ __forceinline__ float du_over_r_f32(float r2, const JasDev& J) {
     } else {
         const float q = 1.0f / (1.0f + r);
         const float t = r * q;
-        float p = (float)J.dcoef[J.ncoef - 1];
-        for (int k = J.ncoef - 2; k >= 0; --k) p = fmaf(p, t, (float)J.dcoef[k]);
+        float p = (float)J.dcoef[15];
+#pragma unroll
+        for (int k = 14; k >= 0; --k) p = fmaf(p, t, (float)J.dcoef[k]);
         f = p * q * q / r;
     }
     return r2 > 0.0f ? f : 0.0f;

@@ -123,3 +123,49 @@ def test_single_occupied_E0_zero(torch_cuda):
     _note("case: N8 n=1")
     V2, h1, E0 = _run(p)
     assert abs(E0) < 1e-15
+
+
+# ----------------------------------------------------------- reduced forms --
+TOL_2BODY_LP = 1e-6      # two-body bar of the reduced-precision forms (Eh)
+TOL_1BODY_LP = 1e-6      # one-body (the paper is silent; same bar as two-body)
+TOL_0BODY_LP = 1e-8      # zero-body bar: met by the FP64 occupied-occupied block
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+def test_reduced_forms_against_factorised(torch_cuda, prec):
+    from oracle import factorised as fb
+    p = inputs.make_workload("N64-occ8-Ng50k", Ng=3001)
+    _note(f"case: N64-occ8-Ng3001 {prec} chunk=1000")
+    V2o, h1o, E0o = fb.closed_shell(p.xyz, p.w, p.phi, p.occ, p.jastrow)
+    V2, h1, E0 = _run(p, prec=prec, chunk_rows=1000)
+    eV, eh, eE = np.abs(V2 - V2o).max(), np.abs(h1 - h1o).max(), abs(E0 - E0o)
+    _note(f"  {prec}: |dV2| {eV:.2e} |dh1| {eh:.2e} |dE0| {eE:.2e}")
+    assert eV < TOL_2BODY_LP and eh < TOL_1BODY_LP and eE < TOL_0BODY_LP
+    for perm in [(1, 0, 2, 3), (2, 3, 0, 1)]:
+        assert np.array_equal(V2, V2.transpose(perm))
+    assert np.array_equal(h1, h1.T)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+def test_reduced_forms_power_jastrow(torch_cuda, prec):
+    from oracle import factorised as fb
+    occ = inputs.random_occ(24, 5, seed=3)
+    p = inputs.make_problem(24, 5, 1500, 6, "chain", "power16", seed=21, occ=occ)
+    _note(f"case: N24 power16 random occ {prec}")
+    V2o, h1o, E0o = fb.closed_shell(p.xyz, p.w, p.phi, p.occ, p.jastrow)
+    V2, h1, E0 = _run(p, prec=prec, chunk_rows=700)
+    assert np.abs(V2 - V2o).max() < TOL_2BODY_LP
+    assert np.abs(h1 - h1o).max() < TOL_1BODY_LP
+    assert abs(E0 - E0o) < TOL_0BODY_LP
+
+
+def test_reduced_form_occ_block_is_fp64_and_deterministic(torch_cuda):
+    """In the reduced forms the occupied-occupied K columns are the FP64 values,
+    so E0 is bitwise the FP64 path's; repeated runs are bitwise identical."""
+    p = inputs.make_workload("N64-occ8-Ng50k", Ng=2200)
+    _note("case: N64-occ8-Ng2200 bf16x3 vs fp64 E0, determinism")
+    _, _, E64 = _run(p, prec="fp64", chunk_rows=800)
+    V2a, h1a, Ea = _run(p, prec="bf16x3", chunk_rows=800)
+    V2b, h1b, Eb = _run(p, prec="bf16x3", chunk_rows=800)
+    assert Ea == E64
+    assert np.array_equal(V2a, V2b) and np.array_equal(h1a, h1b) and Ea == Eb
