@@ -67,6 +67,10 @@ typedef enum {
  * one- and zero-body reductions are computed in FP64. */
 typedef enum { XTC_FP64 = 0, XTC_FP32 = 1, XTC_BF16X3 = 2, XTC_BF16X6 = 3 } xtc_prec;
 
+/* OR-ed into prec: lay the workspace out for xtc_backward as well (extra
+ * per-row buffers).  Every call on that workspace must pass the same value. */
+enum { XTC_WITH_BACKWARD = 0x10 };
+
 /* flags of the contraction calls */
 enum {
     XTC_RESET = 1,       /* zero the accumulator before adding this chunk           */
@@ -154,6 +158,26 @@ xtc_status xtc_contract_1body_0body(const xtc_problem *pb, const double *K,
                                     int32_t g0, int32_t g1, int32_t prec, int32_t flags,
                                     double *h1, double *E0,
                                     void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of the loss
+ *   L = gE0 * E0 + sum_pq gh1[p][q] h1[p][q] + sum_pqrs gV2[p][q][r][s] V2[p][q][r][s]
+ * with respect to the power-Jastrow coefficients (kind 1 only):
+ *   gcoef[k-1] = dL/dc_k,  k = 1..ncoef   (device, FP64, written at the end).
+ * The effective seed of V2 folds gh1 and gE0 through the linear one- and
+ * zero-body equations of Appendix B; the packed two-body accumulator's adjoint
+ * is propagated through eq. tcmf:2el and eq. tcmf:inter to the grid
+ * intermediate, and K is linear in the coefficients (Theory, definition of V),
+ * so dL/dc_k = sum_{g,g'} d_k^x(g,g') Kbar^x(g) . rho(g').  K is recomputed
+ * chunk by chunk (never stored); the contraction with the Jastrow basis runs
+ * over all (g, g') in FP64 with a fixed-order reduction (deterministic).
+ * Requires a workspace prepared (xtc_prepare) with prec | XTC_WITH_BACKWARD.
+ * gV2: device [N]^4 or NULL (= 0); gh1: device [N][N] or NULL; gE0: host value.
+ * The K recompute follows prec (reduced forms keep the occupied block FP64);
+ * the adjoint GEMMs and the coefficient contraction are FP64.
+ * Errors: XTC_E_UNSUPPORTED for a Pade Jastrow or nocc > 24. */
+xtc_status xtc_backward(const xtc_problem *pb, const xtc_jastrow *jas, int32_t prec,
+                        const double *gV2, const double *gh1, double gE0, double *gcoef,
+                        void *ws, size_t ws_bytes, void *stream);
 
 /* Message for the last non-OK status returned on the calling thread. */
 const char *xtc_last_error(void);

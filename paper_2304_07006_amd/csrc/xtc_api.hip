@@ -16,6 +16,9 @@
 //   Kpart  [nsegK][3][cap][ldL] f32   K-build segment partials     (prec != FP64)
 //   CDlp   [8][NS][cap/8][ldL][8]     C and D of the chunk, k8-packed (prec != FP64)
 //   Mpart  [4*ceil(cap/kSegM)][ldL][ldL] f32  two-body partials    (prec != FP64)
+// and with XTC_WITH_BACKWARD in prec (the adjoint reuses M for Gbar):
+//   Kc [3][cap][ldP], Y [7][cap][ldP], T [cap][3][N][nocc], Wbar [cap][3],
+//   gpart [ceil(cap/32) * ngp/128][16], gacc [16], isocc [N], kidx [N]
 // ldL = ldP rounded up to 512.  The chunk capacity `cap` is the largest
 // multiple of 32 rows that fits in the bytes the caller passes, so every call
 // with the same ws_bytes agrees on it.
@@ -32,6 +35,7 @@
 #include "kernels_build_k.h"
 #include "kernels_contract.h"
 #include "kernels_lp.h"
+#include "kernels_bwd.h"
 #include "kernels_prepare.h"
 
 using namespace xtc;
@@ -71,15 +75,19 @@ constexpr int kRowQuant = 32;
 struct Layout {
     int N, Ng, nocc, ldP, ngp, Npair, prec;
     int form, ns, es, ldL, ldO, nOP, nsegK;
-    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E;
+    bool bwd;
+    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, isocc, kidx;
     size_t fixed;        // bytes before S (plus the Mpart remainder reserve)
     size_t per_row;      // bytes per chunk row
     int cap;             // chunk rows that fit (multiple of kRowQuant)
     int nsegM;
-    size_t S, D, Kpart, CDlp, Mpart, end;
+    size_t S, D, Kpart, CDlp, Mpart, Kc, Y, T, Wbar, gpart, end;
 };
 
-int form_of(int prec) { return prec == XTC_FP32 ? 1 : prec == XTC_BF16X3 ? 3 : prec == XTC_BF16X6 ? 6 : 0; }
+int form_of(int prec) {
+    prec &= 0xF;
+    return prec == XTC_FP32 ? 1 : prec == XTC_BF16X3 ? 3 : prec == XTC_BF16X6 ? 6 : 0;
+}
 
 Layout make_layout(const xtc_problem* pb, int prec) {
     Layout L{};
@@ -97,6 +105,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.nOP = pb->nocc * (pb->nocc + 1) / 2;
     L.ldO = (int)align_up((size_t)L.nOP, 64);
     L.nsegK = (L.ngp + kSegK - 1) / kSegK;
+    L.bwd = (prec & XTC_WITH_BACKWARD) != 0;
     const bool lp = L.form != 0;
     size_t off = 0;
     L.pos = off;     off = align_up(off + (size_t)L.ngp * 4 * sizeof(double), kAlign);
@@ -108,12 +117,19 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.h1acc = off;   off = align_up(off + (size_t)L.ldP * sizeof(double), kAlign);
     L.T1 = off;      off = align_up(off + (size_t)kT1Split * L.ldP * sizeof(double), kAlign);
     L.E = off;       off = align_up(off + (size_t)kESplitMax * L.N * L.N * sizeof(double), kAlign);
+    L.gacc = off;    off = align_up(off + (L.bwd ? kGradMax * sizeof(double) : 0), kAlign);
+    L.isocc = off;   off = align_up(off + (L.bwd ? (size_t)L.N : 0), kAlign);
+    L.kidx = off;    off = align_up(off + (L.bwd ? (size_t)L.N * sizeof(int) : 0), kAlign);
+    const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);   // one 32-row tile of partials
     const size_t mslab = (size_t)4 * L.ldL * L.ldL * sizeof(float);       // one partial per component
-    L.fixed = off + (lp ? mslab : 0) + 8 * kAlign;
+    L.fixed = off + (lp ? mslab : 0) + (L.bwd ? gslab : 0) + 12 * kAlign;
     L.per_row = (size_t)8 * sizeof(double) + (size_t)4 * L.ldP * sizeof(double);
     if (lp)
         L.per_row += (size_t)L.nsegK * 3 * L.ldL * sizeof(float) + (size_t)8 * L.ns * L.ldL * L.es +
                      (mslab + kSegM - 1) / kSegM;
+    if (L.bwd)
+        L.per_row += (size_t)10 * L.ldP * sizeof(double) + (size_t)3 * L.N * L.nocc * sizeof(double) +
+                     3 * sizeof(double) + (gslab + 31) / 32;
     L.cap = 0;
     return L;
 }
@@ -127,12 +143,19 @@ void place_chunk(Layout& L, size_t bytes) {
     L.cap = (int)cap;
     const bool lp = L.form != 0;
     L.nsegM = lp ? 4 * (int)((cap + kSegM - 1) / kSegM) : 0;
-    size_t off = L.fixed - 8 * kAlign - (lp ? (size_t)4 * L.ldL * L.ldL * sizeof(float) : 0);
+    const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);
+    size_t off = L.fixed - 12 * kAlign - (lp ? (size_t)4 * L.ldL * L.ldL * sizeof(float) : 0) - (L.bwd ? gslab : 0);
     L.S = off;       off = align_up(off + (size_t)cap * 8 * sizeof(double), kAlign);
     L.D = off;       off = align_up(off + (size_t)4 * cap * L.ldP * sizeof(double), kAlign);
     L.Kpart = off;   off = align_up(off + (lp ? (size_t)L.nsegK * 3 * cap * L.ldL * sizeof(float) : 0), kAlign);
     L.CDlp = off;    off = align_up(off + (lp ? (size_t)8 * L.ns * cap * L.ldL * L.es : 0), kAlign);
     L.Mpart = off;   off = align_up(off + (lp ? (size_t)L.nsegM * L.ldL * L.ldL * sizeof(float) : 0), kAlign);
+    const bool b = L.bwd;
+    L.Kc = off;      off = align_up(off + (b ? (size_t)3 * cap * L.ldP * sizeof(double) : 0), kAlign);
+    L.Y = off;       off = align_up(off + (b ? (size_t)7 * cap * L.ldP * sizeof(double) : 0), kAlign);
+    L.T = off;       off = align_up(off + (b ? (size_t)cap * 3 * L.N * L.nocc * sizeof(double) : 0), kAlign);
+    L.Wbar = off;    off = align_up(off + (b ? (size_t)cap * 3 * sizeof(double) : 0), kAlign);
+    L.gpart = off;   off = align_up(off + (b ? (size_t)((cap + 31) / 32) * gslab : 0), kAlign);
     L.end = off;
     if (L.end > bytes) L.cap = 0;   // cannot happen by construction; refuse rather than overrun
 }
@@ -161,7 +184,9 @@ xtc_status check_problem(const xtc_problem* pb) {
 }
 
 xtc_status check_prec(int prec) {
-    if (prec != XTC_FP64 && prec != XTC_FP32 && prec != XTC_BF16X3 && prec != XTC_BF16X6)
+    const int base = prec & 0xF;
+    if ((prec & ~(0xF | XTC_WITH_BACKWARD)) ||
+        (base != XTC_FP64 && base != XTC_FP32 && base != XTC_BF16X3 && base != XTC_BF16X6))
         return fail(XTC_E_ARG, "prec=%d unknown", prec);
     return XTC_OK;
 }
@@ -346,6 +371,20 @@ xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int acc
     return launched("reduce_M");
 }
 
+xtc_status build_K_any(const Layout& L, const JasDev& J, int g0, int rows, double* K, void* ws, hipStream_t st) {
+    if (L.form != 0) return build_K_lp(L, g0, rows, J, K, ws, st);
+    const int n_rt = (rows + kKRows - 1) / kKRows;
+    const int n_ct = L.ldP / 128;
+    const dim3 grid(n_rt * n_ct);
+    if (J.kind == 0)
+        hipLaunchKernelGGL(k_build_K_f64<0>, grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
+                           L.ldP, L.ngp, g0, rows, n_rt, J, K);
+    else
+        hipLaunchKernelGGL(k_build_K_f64<1>, grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
+                           L.ldP, L.ngp, g0, rows, n_rt, J, K);
+    return launched("build_K");
+}
+
 }  // namespace
 
 extern "C" {
@@ -415,19 +454,7 @@ xtc_status xtc_build_K(const xtc_problem* pb, const xtc_jastrow* jas, int32_t g0
     place_chunk(L, ws_bytes);
     if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
     if ((s = check_range(L, g0, g1)) != XTC_OK) return s;
-    hipStream_t st = (hipStream_t)stream;
-    const int rows = g1 - g0;
-    if (L.form != 0) return build_K_lp(L, g0, rows, J, K, ws, st);
-    const int n_rt = (rows + kKRows - 1) / kKRows;
-    const int n_ct = L.ldP / 128;
-    const dim3 grid(n_rt * n_ct);
-    if (J.kind == 0)
-        hipLaunchKernelGGL(k_build_K_f64<0>, grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
-                           L.ldP, L.ngp, g0, rows, n_rt, J, K);
-    else
-        hipLaunchKernelGGL(k_build_K_f64<1>, grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
-                           L.ldP, L.ngp, g0, rows, n_rt, J, K);
-    return launched("build_K");
+    return build_K_any(L, J, g0, g1 - g0, K, ws, (hipStream_t)stream);
 }
 
 xtc_status xtc_contract_2body(const xtc_problem* pb, const double* K, int32_t g0, int32_t g1, int32_t prec,
@@ -505,6 +532,79 @@ xtc_status xtc_contract_1body_0body(const xtc_problem* pb, const double* K, int3
         hipLaunchKernelGGL(k_onebody_finalize, dim3((NN + 255) / 256), dim3(256), 0, st, at<double>(ws, L.h1acc),
                            L.N, make_occ(pb), h1, E0);
         if ((s = launched("onebody_finalize")) != XTC_OK) return s;
+    }
+    return XTC_OK;
+}
+
+xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t prec, const double* gV2,
+                        const double* gh1, double gE0, double* gcoef, void* ws, size_t ws_bytes, void* stream) {
+    xtc_status s;
+    JasDev J;
+    if ((s = check_problem(pb)) != XTC_OK) return s;
+    if ((s = check_prec(prec)) != XTC_OK) return s;
+    if ((s = check_jastrow(jas, &J)) != XTC_OK) return s;
+    if (J.kind != 1) return fail(XTC_E_UNSUPPORTED, "the adjoint is taken with respect to power-form coefficients");
+    if (!(prec & XTC_WITH_BACKWARD)) return fail(XTC_E_ARG, "prec must carry XTC_WITH_BACKWARD");
+    if (!gcoef) return fail(XTC_E_ARG, "gcoef is NULL");
+    if (!std::isfinite(gE0)) return fail(XTC_E_ARG, "gE0 not finite");
+    if (pb->nocc > kMaxOccAdj) return fail(XTC_E_UNSUPPORTED, "the adjoint supports nocc <= %d", kMaxOccAdj);
+    Layout L = make_layout(pb, prec);
+    place_chunk(L, ws_bytes);
+    if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const OccList occ = make_occ(pb);
+    hipLaunchKernelGGL(k_occ_flags, dim3((L.N + 255) / 256), dim3(256), 0, st, occ, L.N, at<unsigned char>(ws, L.isocc),
+                       at<int>(ws, L.kidx));
+    if ((s = launched("occ_flags")) != XTC_OK) return s;
+    double* G = at<double>(ws, L.M);
+    hipLaunchKernelGGL(k_make_gbar, dim3((L.ldP + 255) / 256, L.ldP), dim3(256), 0, st, gV2, gh1, gE0,
+                       at<unsigned char>(ws, L.isocc), L.N, L.ldP, G);
+    if ((s = launched("make_gbar")) != XTC_OK) return s;
+    const size_t ystride = (size_t)L.cap * L.ldP;
+    double* Kc = at<double>(ws, L.Kc);
+    double* Y = at<double>(ws, L.Y);
+    const int n_jt_pi = L.ngp / 128;
+    bool first = true;
+    for (int g0 = 0; g0 < L.Ng; g0 += L.cap) {
+        const int rows = std::min(L.cap, L.Ng - g0);
+        const bool last = g0 + rows >= L.Ng;
+        if ((s = build_K_any(L, J, g0, rows, Kc, ws, st)) != XTC_OK) return s;
+        if ((s = run_intermediates(L, pb, Kc, g0, g0 + rows, ws, st)) != XTC_OK) return s;
+        const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
+        const double* D = at<double>(ws, L.D);
+        const size_t kstride = (size_t)rows * L.ldP;
+        // Y slots: 0..2 Cbar_{1..3} = D_{1..3} Gbar, 3 Abar = rho Gbar, 4..6 Bbar = K Gbar
+        const double* src[7] = {D + ystride, D + 2 * ystride, D + 3 * ystride, rho_rows, Kc, Kc + kstride,
+                                Kc + 2 * kstride};
+        const int n_it = (rows + 63) / 64, n_jt = L.ldP / 128;
+        for (int y = 0; y < 7; ++y) {
+            hipLaunchKernelGGL(k_gemm_xg_f64, dim3(n_it * n_jt), dim3(256), 0, st, src[y], (size_t)L.ldP, rows, G,
+                               L.ldP, n_jt, Y + y * ystride, (size_t)L.ldP);
+            if ((s = launched("gemm_xg")) != XTC_OK) return s;
+        }
+        const size_t lds = (size_t)L.nocc * L.N * 4 * sizeof(double);
+        if (lds > 64 * 1024) {
+            const hipError_t e = hipFuncSetAttribute((const void*)k_adj_T, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)lds);
+            if (e != hipSuccess) return fail(XTC_E_HIP, "adj_T LDS attribute: %s", hipGetErrorString(e));
+        }
+        hipLaunchKernelGGL(k_adj_T, dim3(std::min(rows, 4096)), dim3(256), lds, st, rho_rows, Kc, Y, ystride, rows,
+                           L.ldP, L.N, occ, at<double>(ws, L.T), at<double>(ws, L.Wbar));
+        if ((s = launched("adj_T")) != XTC_OK) return s;
+        const size_t nel = (size_t)rows * L.Npair;
+        hipLaunchKernelGGL(k_adj_assemble, dim3((unsigned)std::min<size_t>((nel + 255) / 256, 16384)), dim3(256), 0, st,
+                           Y, ystride, at<double>(ws, L.S), at<double>(ws, L.T), at<double>(ws, L.Wbar),
+                           at<int>(ws, L.kidx), rows, L.ldP, L.N, L.nocc);
+        if ((s = launched("adj_assemble")) != XTC_OK) return s;
+        const int n_it_pi = (rows + 31) / 32;
+        hipLaunchKernelGGL(k_pi_grad, dim3(n_it_pi * n_jt_pi), dim3(256), 0, st, Y, ystride, rows,
+                           at<double>(ws, L.rho), L.ldP, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_jt_pi, J.ncoef,
+                           at<double>(ws, L.gpart));
+        if ((s = launched("pi_grad")) != XTC_OK) return s;
+        hipLaunchKernelGGL(k_reduce_grad, dim3(1), dim3(64), 0, st, at<double>(ws, L.gpart), n_it_pi * n_jt_pi, J.ncoef,
+                           at<double>(ws, L.gacc), first ? 0 : 1, last ? gcoef : nullptr);
+        if ((s = launched("reduce_grad")) != XTC_OK) return s;
+        first = false;
     }
     return XTC_OK;
 }

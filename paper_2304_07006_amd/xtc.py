@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libxtc.so")
 XTC_OK, XTC_E_ARG, XTC_E_WORKSPACE, XTC_E_HIP, XTC_E_UNSUPPORTED = 0, -1, -2, -3, -4
 XTC_FP64, XTC_FP32, XTC_BF16X3, XTC_BF16X6 = 0, 1, 2, 3
 XTC_RESET, XTC_FINALIZE = 1, 2
+XTC_WITH_BACKWARD = 0x10
 PRECISIONS = {"fp64": XTC_FP64, "fp32": XTC_FP32, "bf16x3": XTC_BF16X3, "bf16x6": XTC_BF16X6}
 
 
@@ -55,6 +56,9 @@ _SIGS = {
                                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                 ctypes.c_size_t, ctypes.c_void_p]),
+    "xtc_backward": (ctypes.c_int, [ctypes.POINTER(XtcProblem), ctypes.POINTER(XtcJastrow), ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
 }
 
 _lib = None
@@ -173,6 +177,11 @@ def xtc_contract_1body_0body(dp, K, g0, g1, prec, flags, h1, E0, ws, stream=None
                                            _ptr(ws), ws.numel(), _stream(stream)))
 
 
+def xtc_backward(dp, jas: XtcJastrow, prec, gV2, gh1, gE0, gcoef, ws, stream=None):
+    _check(load().xtc_backward(ctypes.byref(dp.c), ctypes.byref(jas), prec, _ptr(gV2), _ptr(gh1), float(gE0),
+                               _ptr(gcoef), _ptr(ws), ws.numel(), _stream(stream)))
+
+
 # ------------------------------------------------------------ whole pass --
 class Pass:
     """Device buffers of one forward pass: workspace, one K chunk, outputs."""
@@ -214,9 +223,64 @@ class Pass:
         return self.V2, self.h1, self.E0
 
 
-def forward(problem, prec="fp64", chunk_rows=None, device="cuda"):
+def forward(problem, prec="fp64", chunk_rows=None, device="cuda", jastrow=None):
     """V2, h1, E0 (torch tensors on the device) for an inputs.Problem."""
     dp = device_problem(problem.xyz, problem.w, problem.phi, problem.occ, device)
     ps = Pass(dp, PRECISIONS[prec] if isinstance(prec, str) else prec, chunk_rows, device)
-    V2, h1, E0 = ps.run(make_jastrow(problem.jastrow))
+    V2, h1, E0 = ps.run(make_jastrow(jastrow or problem.jastrow))
     return V2, h1, E0
+
+
+def power_jastrow(coef) -> XtcJastrow:
+    j = XtcJastrow()
+    j.kind, j.ncoef, j.b = 1, len(coef), 0.0
+    for k, c in enumerate(coef):
+        j.coef[k] = float(c)
+    return j
+
+
+def backward(dp: DeviceProblem, coef, gV2, gh1, gE0, prec="fp64", chunk_rows=None, device="cuda"):
+    """dL/dc for L = gE0 E0 + <gh1, h1> + <gV2, V2> (device tensors or None), power Jastrow."""
+    import torch
+    p = (PRECISIONS[prec] if isinstance(prec, str) else prec) | XTC_WITH_BACKWARD
+    chunk = min(dp.Ng, chunk_rows or dp.Ng)
+    ws = torch.empty(xtc_workspace_size(dp, p, chunk), dtype=torch.uint8, device=device)
+    xtc_prepare(dp, p, chunk, ws)
+    g = torch.empty(len(coef), dtype=torch.float64, device=device)
+    xtc_backward(dp, power_jastrow(coef), p, gV2, gh1, gE0, g, ws)
+    return g
+
+
+class XtcFunction:
+    """torch.autograd.Function over the power-Jastrow coefficients:
+    (V2, h1, E0) = XtcFunction.apply(coef, problem_on_device, prec, chunk_rows).
+    The backward calls xtc_backward with the incoming output gradients as seeds
+    (K is recomputed there, never stored)."""
+
+    @staticmethod
+    def _cls():
+        import torch
+
+        class _F(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, coef, dp, prec, chunk_rows):
+                ps = Pass(dp, PRECISIONS[prec] if isinstance(prec, str) else prec, chunk_rows)
+                V2, h1, E0 = ps.run(power_jastrow(coef.detach().cpu().tolist()))
+                ctx.dp, ctx.prec, ctx.chunk = dp, prec, chunk_rows
+                ctx.save_for_backward(coef)
+                return V2.clone(), h1.clone(), E0.clone()
+
+            @staticmethod
+            def backward(ctx, gV2, gh1, gE0):
+                (coef,) = ctx.saved_tensors
+                gE = float(gE0.detach().cpu().reshape(-1)[0]) if gE0 is not None else 0.0
+                g = backward(ctx.dp, coef.detach().cpu().tolist(),
+                             gV2.contiguous() if gV2 is not None else None,
+                             gh1.contiguous() if gh1 is not None else None, gE, ctx.prec, ctx.chunk)
+                return g.to(coef.dtype).to(coef.device), None, None, None
+
+        return _F
+
+    @classmethod
+    def apply(cls, coef, dp, prec="fp64", chunk_rows=None):
+        return cls._cls().apply(coef, dp, prec, chunk_rows)

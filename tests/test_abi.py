@@ -1,4 +1,7 @@
-"""The C ABI: exported symbols and host-side validation (no kernel launches)."""
+"""The C ABI: exported symbols and host-side validation (no kernel launches).
+
+Every call here passes fake device pointers and is built to fail validation
+before any HIP call, so the tests are safe with or without a device."""
 import ctypes
 import os
 import re
@@ -84,7 +87,8 @@ def test_bad_jastrow_and_range(lib):
     assert _call_build(lib, c, _jas(kind=7), nbytes=n) == xtc.XTC_E_ARG
     assert _call_build(lib, c, _jas(), g0=5, g1=5, nbytes=n) == xtc.XTC_E_ARG
     assert _call_build(lib, c, _jas(), g0=0, g1=101, nbytes=n) == xtc.XTC_E_ARG
-    assert _call_build(lib, c, _jas(), g0=0, g1=60, nbytes=n) == xtc.XTC_E_WORKSPACE   # > capacity
+    # every call below must fail validation (fake pointers: nothing may launch)
+    assert _call_build(lib, c, _jas(), g0=0, g1=100, nbytes=n) == xtc.XTC_E_WORKSPACE  # > 64-row capacity
     assert _call_build(lib, c, _jas(), K=0, nbytes=n) == xtc.XTC_E_ARG
     assert _call_build(lib, c, _jas(), K=0x2008, nbytes=n) == xtc.XTC_E_ARG           # misaligned
     assert _call_build(lib, c, _jas(), nbytes=100) == xtc.XTC_E_WORKSPACE
@@ -105,6 +109,31 @@ def test_contract_flags(lib):
     st = lib.xtc_contract_1body_0body(ctypes.byref(c), ctypes.c_void_p(0x2000), 0, 10, 0, xtc.XTC_FINALIZE,
                                       None, None, ctypes.c_void_p(0x100000), n, None)
     assert st == xtc.XTC_E_ARG
+
+
+def test_backward_validation(lib):
+    c, keep = _problem()
+    n = lib.xtc_workspace_size(ctypes.byref(c), xtc.XTC_WITH_BACKWARD, 50)
+    assert n > lib.xtc_workspace_size(ctypes.byref(c), 0, 50)
+    j = _jas(kind=0)
+    st = lib.xtc_backward(ctypes.byref(c), ctypes.byref(j), xtc.XTC_WITH_BACKWARD, None, None, 1.0,
+                          ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_UNSUPPORTED                                 # Pade: no coefficients
+    j = _jas(kind=1, ncoef=4)
+    for k in range(4):
+        j.coef[k] = 0.1
+    st = lib.xtc_backward(ctypes.byref(c), ctypes.byref(j), 0, None, None, 1.0,
+                          ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG                                         # workspace flag missing
+    st = lib.xtc_backward(ctypes.byref(c), ctypes.byref(j), xtc.XTC_WITH_BACKWARD, None, None, 1.0,
+                          None, ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG                                         # gcoef NULL
+    st = lib.xtc_backward(ctypes.byref(c), ctypes.byref(j), xtc.XTC_WITH_BACKWARD, None, None, float("inf"),
+                          ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG                                         # gE0 not finite
+    st = lib.xtc_backward(ctypes.byref(c), ctypes.byref(j), xtc.XTC_WITH_BACKWARD | 0x100, None, None, 1.0,
+                          ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG                                         # unknown prec bits
 
 
 def test_workspace_grows_with_chunk(lib):
