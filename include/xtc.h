@@ -179,6 +179,20 @@ xtc_status xtc_backward(const xtc_problem *pb, const xtc_jastrow *jas, int32_t p
                         const double *gV2, const double *gh1, double gE0, double *gcoef,
                         void *ws, size_t ws_bytes, void *stream);
 
+/* Symmetric (Loewdin) orthonormalisation under the grid weights, FP64.
+ * The paper works with orthonormal orbitals (HF orbitals, Results section);
+ * on a Monte-Carlo grid the functions are orthonormalised under the same
+ * quadrature that the grid intermediates use:
+ *   S[m][n] = sum_g w_g chi_m(g) chi_n(g),   phi = S^{-1/2} chi
+ * with S^{-1/2} symmetric (cyclic Jacobi eigen-decomposition of S, which keeps
+ * small eigenvalues to high relative accuracy; S must be positive definite).
+ * chi, phi: device [N][Ng]; w: device [Ng]; lambda: device [N] (eigenvalues
+ * of S, unordered) or NULL.  Workspace of xtc_lowdin_workspace_size(N, Ng)
+ * bytes, 256-byte aligned; no state is kept in it after the call. */
+size_t xtc_lowdin_workspace_size(int32_t N, int32_t Ng);
+xtc_status xtc_lowdin(int32_t N, int32_t Ng, const double *chi, const double *w, double *phi,
+                      double *lambda, void *ws, size_t ws_bytes, void *stream);
+
 /* Message for the last non-OK status returned on the calling thread. */
 const char *xtc_last_error(void);
 

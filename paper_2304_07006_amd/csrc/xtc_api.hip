@@ -36,6 +36,7 @@
 #include "kernels_contract.h"
 #include "kernels_lp.h"
 #include "kernels_bwd.h"
+#include "kernels_lowdin.h"
 #include "kernels_prepare.h"
 
 using namespace xtc;
@@ -605,6 +606,71 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
                            at<double>(ws, L.gacc), first ? 0 : 1, last ? gcoef : nullptr);
         if ((s = launched("reduce_grad")) != XTC_OK) return s;
         first = false;
+    }
+    return XTC_OK;
+}
+
+// ------------------------------------------------------------- Loewdin --
+namespace {
+constexpr int kLowdinSeg = 4096;
+constexpr int kJacobiMaxSweeps = 40;
+struct LowdinLayout {
+    int ldS, nseg;
+    size_t part, S, U, X, sweeps, total;
+};
+LowdinLayout lowdin_layout(int N, int Ng) {
+    LowdinLayout L{};
+    L.ldS = (int)align_up((size_t)N, 64);
+    L.nseg = (Ng + kLowdinSeg - 1) / kLowdinSeg;
+    size_t off = 0;
+    L.part = off;   off = align_up(off + (size_t)L.nseg * L.ldS * L.ldS * sizeof(double), kAlign);
+    L.S = off;      off = align_up(off + (size_t)N * N * sizeof(double), kAlign);
+    L.U = off;      off = align_up(off + (size_t)N * N * sizeof(double), kAlign);
+    L.X = off;      off = align_up(off + (size_t)N * N * sizeof(double), kAlign);
+    L.sweeps = off; off = align_up(off + sizeof(int), kAlign);
+    L.total = off;
+    return L;
+}
+}  // namespace
+
+size_t xtc_lowdin_workspace_size(int32_t N, int32_t Ng) {
+    if (N < 1 || N > kMaxN || Ng < 1) {
+        fail(XTC_E_ARG, "N=%d or Ng=%d out of range", N, Ng);
+        return 0;
+    }
+    return lowdin_layout(N, Ng).total;
+}
+
+xtc_status xtc_lowdin(int32_t N, int32_t Ng, const double* chi, const double* w, double* phi, double* lambda,
+                      void* ws, size_t ws_bytes, void* stream) {
+    if (N < 1 || N > kMaxN || Ng < 1) return fail(XTC_E_ARG, "N=%d or Ng=%d out of range", N, Ng);
+    if (!chi || !w || !phi) return fail(XTC_E_ARG, "NULL array");
+    if (!ws) return fail(XTC_E_WORKSPACE, "workspace is NULL");
+    if ((uintptr_t)ws % kAlign) return fail(XTC_E_WORKSPACE, "workspace not 256-byte aligned");
+    const LowdinLayout L = lowdin_layout(N, Ng);
+    if (ws_bytes < L.total) return fail(XTC_E_WORKSPACE, "workspace of %zu bytes < %zu", ws_bytes, L.total);
+    hipStream_t st = (hipStream_t)stream;
+    xtc_status s;
+    const int n_t = L.ldS / 64;
+    hipLaunchKernelGGL(k_syrk_w_part, dim3(n_t * n_t, L.nseg), dim3(256), 0, st, chi, w, N, Ng, L.ldS, n_t,
+                       kLowdinSeg, at<double>(ws, L.part));
+    if ((s = launched("syrk_w")) != XTC_OK) return s;
+    const int NN = N * N;
+    hipLaunchKernelGGL(k_syrk_reduce, dim3((NN + 255) / 256), dim3(256), 0, st, at<double>(ws, L.part), L.nseg, N,
+                       L.ldS, at<double>(ws, L.S), at<double>(ws, L.U));
+    if ((s = launched("syrk_reduce")) != XTC_OK) return s;
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(kJacobiThreads), 0, st, at<double>(ws, L.S), at<double>(ws, L.U), N,
+                       kJacobiMaxSweeps, at<int>(ws, L.sweeps));
+    if ((s = launched("jacobi")) != XTC_OK) return s;
+    hipLaunchKernelGGL(k_inv_sqrt, dim3((NN + 255) / 256), dim3(256), 0, st, at<double>(ws, L.S), at<double>(ws, L.U),
+                       N, at<double>(ws, L.X));
+    if ((s = launched("inv_sqrt")) != XTC_OK) return s;
+    hipLaunchKernelGGL(k_apply_X, dim3((Ng + 255) / 256, N), dim3(256), (size_t)N * sizeof(double), st,
+                       at<double>(ws, L.X), chi, N, Ng, phi);
+    if ((s = launched("apply_X")) != XTC_OK) return s;
+    if (lambda) {
+        hipLaunchKernelGGL(k_diag_copy, dim3((N + 255) / 256), dim3(256), 0, st, at<double>(ws, L.S), N, lambda);
+        if ((s = launched("diag_copy")) != XTC_OK) return s;
     }
     return XTC_OK;
 }

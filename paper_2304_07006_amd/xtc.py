@@ -59,6 +59,10 @@ _SIGS = {
     "xtc_backward": (ctypes.c_int, [ctypes.POINTER(XtcProblem), ctypes.POINTER(XtcJastrow), ctypes.c_int32,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "xtc_lowdin_workspace_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "xtc_lowdin": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p]),
 }
 
 _lib = None
@@ -180,6 +184,27 @@ def xtc_contract_1body_0body(dp, K, g0, g1, prec, flags, h1, E0, ws, stream=None
 def xtc_backward(dp, jas: XtcJastrow, prec, gV2, gh1, gE0, gcoef, ws, stream=None):
     _check(load().xtc_backward(ctypes.byref(dp.c), ctypes.byref(jas), prec, _ptr(gV2), _ptr(gh1), float(gE0),
                                _ptr(gcoef), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def xtc_lowdin(N, Ng, chi, w, phi, lam, ws, stream=None):
+    _check(load().xtc_lowdin(N, Ng, _ptr(chi), _ptr(w), _ptr(phi), _ptr(lam), _ptr(ws), ws.numel(),
+                             _stream(stream)))
+
+
+def lowdin(chi, w, device="cuda"):
+    """phi = S^{-1/2} chi and the eigenvalues of S on the device (FP64)."""
+    import torch
+    chi_t = torch.as_tensor(np.ascontiguousarray(chi, dtype=np.float64)).to(device)
+    w_t = torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64)).to(device)
+    N, Ng = chi_t.shape
+    n = load().xtc_lowdin_workspace_size(N, Ng)
+    if n == 0:
+        raise XtcError(XTC_E_ARG, last_error())
+    ws = torch.empty(n, dtype=torch.uint8, device=device)
+    phi = torch.empty_like(chi_t)
+    lam = torch.empty(N, dtype=torch.float64, device=device)
+    xtc_lowdin(N, Ng, chi_t, w_t, phi, lam, ws)
+    return phi, lam
 
 
 # ------------------------------------------------------------ whole pass --

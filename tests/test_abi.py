@@ -142,3 +142,15 @@ def test_workspace_grows_with_chunk(lib):
     b = lib.xtc_workspace_size(ctypes.byref(c), 0, 1000)
     assert 0 < a < b
     assert lib.xtc_workspace_size(ctypes.byref(c), 0, 1001) == 0
+
+
+def test_lowdin_validation(lib):
+    assert lib.xtc_lowdin_workspace_size(0, 10) == 0
+    assert lib.xtc_lowdin_workspace_size(8, 100) > 0
+    n = lib.xtc_lowdin_workspace_size(8, 100)
+    st = lib.xtc_lowdin(8, 100, None, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x4000), None,
+                        ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG
+    st = lib.xtc_lowdin(8, 100, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x4000), None,
+                        ctypes.c_void_p(0x100000), n - 1, None)
+    assert st == xtc.XTC_E_WORKSPACE

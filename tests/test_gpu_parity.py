@@ -169,3 +169,25 @@ def test_reduced_form_occ_block_is_fp64_and_deterministic(torch_cuda):
     V2b, h1b, Eb = _run(p, prec="bf16x3", chunk_rows=800)
     assert Ea == E64
     assert np.array_equal(V2a, V2b) and np.array_equal(h1a, h1b) and Ea == Eb
+
+
+# ----------------------------------------------------------------- Loewdin --
+@pytest.mark.parametrize("name,Ng", [("N8-occ2-Ng2k", None), ("N64-occ8-Ng50k", 3001), ("N128-occ16-Ng150k", 6000)])
+def test_lowdin_against_oracle(torch_cuda, name, Ng):
+    """GPU Loewdin vs the oracle's (eigh-based) one; both are exact up to
+    eps * cond(S), which sets the tolerance."""
+    from oracle import lowdin as ol
+    from paper_2304_07006_amd import xtc
+    p = inputs.make_workload(name, Ng=Ng)
+    _note(f"case: lowdin {name} Ng={p.Ng}")
+    phi_o, C, lam_o = ol.lowdin(p.chi, p.w)
+    phi_g, lam_g = xtc.lowdin(p.chi, p.w)
+    phi_g = phi_g.cpu().numpy()
+    cond = lam_o.max() / lam_o.min()
+    tol = 50 * np.finfo(float).eps * cond * np.abs(phi_o).max()
+    err = np.abs(phi_g - phi_o).max()
+    _note(f"  cond(S) {cond:.2e}  max|dphi| {err:.2e}  tol {tol:.2e}")
+    assert err < tol
+    S = (phi_g * p.w) @ phi_g.T
+    assert np.abs(S - np.eye(p.N)).max() < 50 * np.finfo(float).eps * cond
+    assert np.allclose(np.sort(lam_g.cpu().numpy()), np.sort(lam_o), rtol=1e-9, atol=1e-14 * lam_o.max())
