@@ -482,3 +482,141 @@ __global__ void k_gather_occ(const double* __restrict__ rho, int ldP, int ngp, c
 }
 
 }  // namespace xtc
+
+namespace xtc {
+
+// --------------------------------------------------------------------------
+// Row-major split copy: dst[s][r][c] = term s of src[r][c] (r < rows, c < ld),
+// used for the operands of the reduced-precision Pi contraction, whose
+// summation index (the pair) is the contiguous one.
+template <int FORM>
+__global__ void k_split_rows(const double* __restrict__ src, size_t n, void* __restrict__ dst, size_t split_stride) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float v = (float)src[i];
+        if constexpr (FORM == 1) {
+            ((float*)dst)[i] = v;
+        } else {
+            constexpr int NS = Lp<FORM>::NS;
+            __bf16 t[NS];
+            split_bf16<NS>(v, t);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) ((__bf16*)dst)[s * split_stride + i] = t[s];
+        }
+    }
+}
+
+// Reduced-precision Pi tiles with the gradient epilogue (see k_pi_grad):
+// Pi^x(g,g') = sum_P Kbar^x[g][P] rho[g'][P] with FP32 accumulation over all
+// pairs; workgroup 4 waves as 2 (g) x 2 (g'), wave tile 16 g x 128 g' x 3.
+// Kb: [3][NS][rows][ldP], rr: [NS][ngp][ldP] (row-major splits).
+template <int FORM>
+__global__ __launch_bounds__(256) void k_pi_grad_lp(const void* __restrict__ Kb, size_t kb_comp, size_t kb_split,
+                                                    int rows, const void* __restrict__ rr, size_t rr_split,
+                                                    int ldP, const d4* __restrict__ pos, int g0, int ngp, int n_jt,
+                                                    int ncoef, double* __restrict__ part) {
+    constexpr int NS = Lp<FORM>::NS;
+    constexpr int NB = 8;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int it = blockIdx.x / n_jt, jt = blockIdx.x % n_jt;
+    const int i0 = it * 32 + 16 * (wave & 1), j0 = jt * 256 + 128 * (wave >> 1);
+    const int l16 = lane & 15, kq = 8 * (lane >> 4);
+    f4 acc[3][NB];
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[x][b] = (f4){0.f, 0.f, 0.f, 0.f};
+    const size_t irow = (size_t)min(i0 + l16, rows - 1);
+    size_t jrow[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) jrow[b] = (size_t)min(j0 + 16 * b + l16, ngp - 1);
+    for (int k = 0; k < ldP; k += kLpK) {
+        if constexpr (FORM == 1) {
+            const float* A = (const float*)Kb;
+            const float* B = (const float*)rr;
+            float av[3][8];
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                const f4* p = (const f4*)(A + x * kb_comp + irow * ldP + k + kq);
+                const f4 y0 = p[0], y1 = p[1];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) { av[x][e] = y0[e]; av[x][4 + e] = y1[e]; }
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const f4* p = (const f4*)(B + jrow[b] * ldP + k + kq);
+                const f4 y0 = p[0], y1 = p[1];
+                const float bv[8] = {y0[0], y0[1], y0[2], y0[3], y1[0], y1[1], y1[2], y1[3]};
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+#pragma unroll
+                    for (int x = 0; x < 3; ++x)
+                        acc[x][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x][e], bv[e], acc[x][b], 0, 0, 0);
+            }
+        } else {
+            const __bf16* A = (const __bf16*)Kb;
+            const __bf16* B = (const __bf16*)rr;
+            bf8 av[3][NS];
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) av[x][s] = *(const bf8*)(A + x * kb_comp + s * kb_split + irow * ldP + k + kq);
+#pragma unroll
+            for (int bh = 0; bh < NB; bh += 4) {
+                bf8 bv[4][NS];
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) bv[b][s] = *(const bf8*)(B + s * rr_split + jrow[bh + b] * ldP + k + kq);
+#pragma unroll
+                for (int t = 0; t < Terms<FORM>::n; ++t)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+#pragma unroll
+                        for (int x = 0; x < 3; ++x)
+                            acc[x][bh + b] = mma_bf16(av[x][Terms<FORM>::a[t]], bv[b][Terms<FORM>::b[t]], acc[x][bh + b]);
+            }
+        }
+    }
+    double gsum[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) gsum[j] = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 4 * (lane >> 4) + v;          // FP32/BF16 MFMA output rows: 4 (l/16) + v
+        if (i >= rows) continue;
+        const d4 pi = pos[g0 + i];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int jg = j0 + 16 * b + l16;
+            if (jg >= ngp) continue;
+            const d4 pj = pos[jg];
+            const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            if (!(r2 > 0.0)) continue;
+            const double r = sqrt(r2);
+            const double q = 1.0 / (1.0 + r);
+            const double t = r * q;
+            const double s = (dx * (double)acc[0][b][v] + dy * (double)acc[1][b][v] + dz * (double)acc[2][b][v]) * q * q / r;
+            double tp = s;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                gsum[j] = fma((double)(j + 1), tp, gsum[j]);
+                tp *= t;
+            }
+        }
+    }
+    __shared__ double red[4][16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        double v = gsum[j];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+        if (lane == 0) red[wave][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16 && threadIdx.x < ncoef)
+        part[(size_t)blockIdx.x * 16 + threadIdx.x] =
+            red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+}  // namespace xtc

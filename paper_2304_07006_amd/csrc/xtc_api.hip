@@ -77,12 +77,12 @@ struct Layout {
     int N, Ng, nocc, ldP, ngp, Npair, prec;
     int form, ns, es, ldL, ldO, nOP, nsegK;
     bool bwd;
-    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, isocc, kidx;
+    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, isocc, kidx, rhoR;
     size_t fixed;        // bytes before S (plus the Mpart remainder reserve)
     size_t per_row;      // bytes per chunk row
     int cap;             // chunk rows that fit (multiple of kRowQuant)
     int nsegM;
-    size_t S, D, Kpart, CDlp, Mpart, Kc, Y, T, Wbar, gpart, end;
+    size_t S, D, Kpart, CDlp, Mpart, Kc, Y, T, Wbar, gpart, KbL, end;
 };
 
 int form_of(int prec) {
@@ -121,6 +121,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.gacc = off;    off = align_up(off + (L.bwd ? kGradMax * sizeof(double) : 0), kAlign);
     L.isocc = off;   off = align_up(off + (L.bwd ? (size_t)L.N : 0), kAlign);
     L.kidx = off;    off = align_up(off + (L.bwd ? (size_t)L.N * sizeof(int) : 0), kAlign);
+    L.rhoR = off;    off = align_up(off + (L.bwd && lp ? (size_t)L.ns * L.ngp * L.ldP * L.es : 0), kAlign);
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);   // one 32-row tile of partials
     const size_t mslab = (size_t)4 * L.ldL * L.ldL * sizeof(float);       // one partial per component
     L.fixed = off + (lp ? mslab : 0) + (L.bwd ? gslab : 0) + 12 * kAlign;
@@ -130,7 +131,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
                      (mslab + kSegM - 1) / kSegM;
     if (L.bwd)
         L.per_row += (size_t)10 * L.ldP * sizeof(double) + (size_t)3 * L.N * L.nocc * sizeof(double) +
-                     3 * sizeof(double) + (gslab + 31) / 32;
+                     3 * sizeof(double) + (gslab + 31) / 32 + (lp ? (size_t)3 * L.ns * L.ldP * L.es : 0);
     L.cap = 0;
     return L;
 }
@@ -157,6 +158,7 @@ void place_chunk(Layout& L, size_t bytes) {
     L.T = off;       off = align_up(off + (b ? (size_t)cap * 3 * L.N * L.nocc * sizeof(double) : 0), kAlign);
     L.Wbar = off;    off = align_up(off + (b ? (size_t)cap * 3 * sizeof(double) : 0), kAlign);
     L.gpart = off;   off = align_up(off + (b ? (size_t)((cap + 31) / 32) * gslab : 0), kAlign);
+    L.KbL = off;     off = align_up(off + (b && lp ? (size_t)3 * L.ns * cap * L.ldP * L.es : 0), kAlign);
     L.end = off;
     if (L.end > bytes) L.cap = 0;   // cannot happen by construction; refuse rather than overrun
 }
@@ -372,6 +374,14 @@ xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int acc
     return launched("reduce_M");
 }
 
+xtc_status split_rows_any(int form, const double* src, size_t n, void* dst, size_t split_stride, hipStream_t st) {
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
+    if (form == 1) hipLaunchKernelGGL(k_split_rows<1>, dim3(blocks), dim3(256), 0, st, src, n, dst, split_stride);
+    else if (form == 3) hipLaunchKernelGGL(k_split_rows<3>, dim3(blocks), dim3(256), 0, st, src, n, dst, split_stride);
+    else hipLaunchKernelGGL(k_split_rows<6>, dim3(blocks), dim3(256), 0, st, src, n, dst, split_stride);
+    return launched("split_rows");
+}
+
 xtc_status build_K_any(const Layout& L, const JasDev& J, int g0, int rows, double* K, void* ws, hipStream_t st) {
     if (L.form != 0) return build_K_lp(L, g0, rows, J, K, ws, st);
     const int n_rt = (rows + kKRows - 1) / kKRows;
@@ -434,6 +444,10 @@ xtc_status xtc_prepare(const xtc_problem* pb, int32_t prec, int32_t chunk_rows, 
         hipLaunchKernelGGL(k_gather_occ, dim3(4096), dim3(256), 0, st, at<double>(ws, L.rho), L.ldP, L.ngp,
                            at<int>(ws, L.colmap), L.ldO, at<double>(ws, L.rho_occ));
         if ((s = launched("gather_occ")) != XTC_OK) return s;
+        if (L.bwd &&
+            (s = split_rows_any(L.form, at<double>(ws, L.rho), (size_t)L.ngp * L.ldP, at<void>(ws, L.rhoR),
+                                (size_t)L.ngp * L.ldP, st)) != XTC_OK)
+            return s;
     }
     // zero the accumulators and the chunk buffers (padding columns of D stay 0)
     if ((s = fill(at<double>(ws, L.M), (size_t)L.ldP * L.ldP, st)) != XTC_OK) return s;
@@ -598,11 +612,38 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
                            at<int>(ws, L.kidx), rows, L.ldP, L.N, L.nocc);
         if ((s = launched("adj_assemble")) != XTC_OK) return s;
         const int n_it_pi = (rows + 31) / 32;
-        hipLaunchKernelGGL(k_pi_grad, dim3(n_it_pi * n_jt_pi), dim3(256), 0, st, Y, ystride, rows,
-                           at<double>(ws, L.rho), L.ldP, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_jt_pi, J.ncoef,
-                           at<double>(ws, L.gpart));
-        if ((s = launched("pi_grad")) != XTC_OK) return s;
-        hipLaunchKernelGGL(k_reduce_grad, dim3(1), dim3(64), 0, st, at<double>(ws, L.gpart), n_it_pi * n_jt_pi, J.ncoef,
+        int nblk_pi;
+        if (L.form == 0) {
+            nblk_pi = n_it_pi * n_jt_pi;
+            hipLaunchKernelGGL(k_pi_grad, dim3(nblk_pi), dim3(256), 0, st, Y, ystride, rows, at<double>(ws, L.rho),
+                               L.ldP, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_jt_pi, J.ncoef, at<double>(ws, L.gpart));
+            if ((s = launched("pi_grad")) != XTC_OK) return s;
+        } else {
+            // Kbar of the chunk to the row-major split format, then the reduced Pi tiles
+            const size_t kb_split = (size_t)rows * L.ldP, kb_comp = (size_t)L.ns * kb_split;
+            char* kb = at<char>(ws, L.KbL);
+            for (int x = 0; x < 3; ++x)
+                if ((s = split_rows_any(L.form, Y + x * ystride, (size_t)rows * L.ldP, kb + x * kb_comp * L.es,
+                                        kb_split, st)) != XTC_OK)
+                    return s;
+            const int n_jt_lp = (L.ngp + 255) / 256;
+            nblk_pi = n_it_pi * n_jt_lp;
+            const size_t rr_split = (size_t)L.ngp * L.ldP;
+            if (L.form == 1)
+                hipLaunchKernelGGL(k_pi_grad_lp<1>, dim3(nblk_pi), dim3(256), 0, st, (const void*)kb, kb_comp, kb_split,
+                                   rows, at<void>(ws, L.rhoR), rr_split, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_jt_lp,
+                                   J.ncoef, at<double>(ws, L.gpart));
+            else if (L.form == 3)
+                hipLaunchKernelGGL(k_pi_grad_lp<3>, dim3(nblk_pi), dim3(256), 0, st, (const void*)kb, kb_comp, kb_split,
+                                   rows, at<void>(ws, L.rhoR), rr_split, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_jt_lp,
+                                   J.ncoef, at<double>(ws, L.gpart));
+            else
+                hipLaunchKernelGGL(k_pi_grad_lp<6>, dim3(nblk_pi), dim3(256), 0, st, (const void*)kb, kb_comp, kb_split,
+                                   rows, at<void>(ws, L.rhoR), rr_split, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_jt_lp,
+                                   J.ncoef, at<double>(ws, L.gpart));
+            if ((s = launched("pi_grad_lp")) != XTC_OK) return s;
+        }
+        hipLaunchKernelGGL(k_reduce_grad, dim3(1), dim3(64), 0, st, at<double>(ws, L.gpart), nblk_pi, J.ncoef,
                            at<double>(ws, L.gacc), first ? 0 : 1, last ? gcoef : nullptr);
         if ((s = launched("reduce_grad")) != XTC_OK) return s;
         first = false;
