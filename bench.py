@@ -32,6 +32,36 @@ TERMS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}                     # M
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}
 
 
+def default_chunk(Ng, prec):
+    """Equal-sized grid chunks, so every K-build launch covers the same rows."""
+    parts = 10 if prec == "fp64" else 20
+    return -(-Ng // parts)
+
+
+def kernel_sources_hash():
+    """Hash of the HIP sources the K build is made of (the traffic figures in
+    profiles/ are only reported while it matches)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("xtc_device.h", "kernels_build_k.h", "kernels_lp.h", "kernels_prepare.h"):
+        with open(os.path.join(ROOT, "paper_2304_07006_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(prec, workload, chunk):
+    """Per-launch HBM bytes of xtc_build_K from the committed counter summary."""
+    path = os.path.join(ROOT, "profiles", "traffic_xtc_build_K.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    key = f"{workload}/{prec}/{chunk}"
+    e = rec.get(key)
+    if not e or e.get("sources") != kernel_sources_hash():
+        return None
+    return e
+
+
 def f_alg(N, n, Ng):
     P = N * (N + 1) // 2
     return 6 * Ng * Ng * P + 8 * Ng * P * P + (18 * n + 10) * Ng * P
@@ -78,6 +108,25 @@ def run_gpu(problem, prec, steps, warmup, chunk):
     return dict(sec=dt, kbuild=kt, outputs=(ps.V2, ps.h1, ps.E0), ws_bytes=ps.ws.numel())
 
 
+def probe(problem, prec, chunk):
+    """Counter pass: a plain 1 GiB device-to-device copy (reads and writes
+    exactly 2^30 bytes; it calibrates FETCH_SIZE / WRITE_SIZE) followed by one
+    xtc_build_K launch of `chunk` rows (the dominant kernel)."""
+    import torch
+    from paper_2304_07006_amd import xtc
+    a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    dp = xtc.device_problem(problem.xyz, problem.w, problem.phi, problem.occ)
+    ps = xtc.Pass(dp, xtc.PRECISIONS[prec], chunk)
+    xtc.xtc_prepare(dp, ps.prec, ps.chunk, ps.ws)
+    xtc.xtc_build_K(dp, xtc.make_jastrow(problem.jastrow), 0, chunk, ps.prec, ps.K_view(0, chunk), ps.ws)
+    torch.cuda.synchronize()
+    print(f"[probe] copy 1 GiB + build_K {prec} rows=0..{chunk}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(name, budget_rows):
     """The oracle (Appendix-B equations, numpy FP64) on the same workload's
     orbitals and generator, on a reduced grid of `budget_rows` points."""
@@ -106,8 +155,11 @@ def main():
     ap.add_argument("--workload", default="N128-occ16-Ng150k")
     ap.add_argument("--prec", default="bf16x3", choices=list(PEAK))
     ap.add_argument("--compare", default="fp64", help="form run once beside the headline one ('none' to skip)")
-    ap.add_argument("--chunk", type=int, default=None, help="grid rows per chunk (default 16384 FP64, 8192 reduced)")
+    ap.add_argument("--chunk", type=int, default=None,
+                    help="grid rows per chunk (default: Ng/10 for FP64, Ng/20 for the reduced forms: equal launches)")
     ap.add_argument("--cpu-rows", type=int, default=300, help="grid points of the CPU oracle sample (0: skip)")
+    ap.add_argument("--probe", action="store_true",
+                    help="counter pass: one 1 GiB device copy (calibration) and one K-build launch, no JSON")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -122,14 +174,17 @@ def main():
         sys.exit(1)
     wl = inputs.WORKLOADS[args.workload]
     problem = inputs.make_workload(args.workload)
-    chunk = args.chunk or (16384 if args.prec == "fp64" else 8192)
+    chunk = args.chunk or default_chunk(wl.Ng, args.prec)
+    if args.probe:
+        probe(problem, args.prec, chunk)
+        return
     print(f"[bench] {args.workload} prec={args.prec} chunk={chunk} warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
     r = run_gpu(problem, args.prec, args.steps, args.warmup, chunk)
     F = f_alg(wl.N, wl.nocc, wl.Ng)
     forms = {args.prec: {"s_per_step": r["sec"], "gflops": F / r["sec"] / 1e9}}
     if args.compare != "none" and args.compare != args.prec:
-        cchunk = 16384 if args.compare == "fp64" else 8192
+        cchunk = default_chunk(wl.Ng, args.compare)
         print(f"[bench] comparison form {args.compare}: one step", file=sys.stderr, flush=True)
         V2h, h1h, E0h = (t.clone() for t in r["outputs"])
         del r["outputs"]
@@ -174,7 +229,9 @@ def main():
                    "chunk_rows": chunk, "jastrow": wl.jastrow_kind, "F_alg_flop": F,
                    "workspace_bytes": r["ws_bytes"]},
         "roofline": {"bound": "mfma", "kernel": "xtc_build_K", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": (tr["bytes_per_launch"] if (tr := traffic_record(args.prec, args.workload, chunk))
+                                 else None),
                      "per_launch_flop": tot_f / nl, "avg_launch_ms": tot_t / nl * 1e3,
                      "executed_mfma_frac": achieved * TERMS[args.prec] / peak},
         "forms": forms,

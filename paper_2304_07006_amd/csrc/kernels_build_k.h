@@ -108,11 +108,15 @@ __global__ __launch_bounds__(256) void k_build_K_f64_map(const d4* __restrict__ 
                                                      const double* __restrict__ rho, int ldP,
                                                      int ngp, int g0, int rows, int n_rt, JasDev J,
                                                      double* __restrict__ K, const int* __restrict__ colmap,
-                                                     int nmap, int ldK) {
+                                                     int nmap, int ldK, int seg_len) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int rt = blockIdx.x % n_rt;
     const int ct = blockIdx.x / n_rt;
+    // grid.y selects a segment [gs, ge) of the sum over g'; with several
+    // segments each writes its own slab K + seg * 3 * rows * ldK
+    const int gs = blockIdx.y * seg_len, ge = min(ngp, gs + seg_len);
+    K += (size_t)blockIdx.y * 3 * rows * ldK;
     const int rloc0 = rt * kKRows + wave * kKRowsPerWave;   // first local row of this wave
     const int my = min(rloc0 + (lane & 15), rows - 1);      // row whose d^x this lane generates
     const d4 pg = pos[g0 + my];
@@ -125,14 +129,14 @@ __global__ __launch_bounds__(256) void k_build_K_f64_map(const d4* __restrict__ 
 #pragma unroll
         for (int c = 0; c < 4 * NH; ++c) acc[x][c] = (d4){0.0, 0.0, 0.0, 0.0};
 
-    const double* bp = rho + (size_t)kq * ldP + col;
-    const d4* pp = pos + kq;
+    const double* bp = rho + (size_t)(gs + kq) * ldP + col;
+    const d4* pp = pos + gs + kq;
     d4 b0 = *(const d4*)bp;
     d4 b1 = NH == 2 ? *(const d4*)(bp + 64) : b0;
     d4 pc = *pp;
-    for (int kk = 0; kk < ngp; kk += 4) {
+    for (int kk = gs; kk < ge; kk += 4) {
         const d4 cb0 = b0, cb1 = b1, cp = pc;
-        if (kk + 4 < ngp) {              // prefetch the next 4 grid columns
+        if (kk + 4 < ge) {               // prefetch the next 4 grid columns
             bp += (size_t)4 * ldP;
             pp += 4;
             b0 = *(const d4*)bp;

@@ -470,6 +470,21 @@ __global__ void k_occ_pairs(OccList occ, int N, int* __restrict__ colmap, int ld
     colmap[j] = pair_sym(occ.k[a], occ.k[b], N);
 }
 
+// K[x][r][colmap[j]] = sum_s part[s][x][r][j] (FP64, fixed order), j < nmap.
+__global__ void k_reduce_occ(const double* __restrict__ part, int nseg, int rows, int ldO, const int* __restrict__ colmap,
+                             int nmap, int ldP, double* __restrict__ K) {
+    const size_t n = (size_t)3 * rows * nmap;
+    const size_t sstride = (size_t)3 * rows * ldO;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(i % nmap);
+        const size_t xr = i / nmap;                  // x * rows + r
+        double s = 0.0;
+        for (int q = 0; q < nseg; ++q) s += part[q * sstride + xr * ldO + j];
+        const int x = (int)(xr / rows), r = (int)(xr % rows);
+        K[((size_t)x * rows + r) * ldP + colmap[j]] = s;
+    }
+}
+
 __global__ void k_gather_occ(const double* __restrict__ rho, int ldP, int ngp, const int* __restrict__ colmap,
                              int ldO, double* __restrict__ rho_occ) {
     const size_t n = (size_t)ngp * ldO;

@@ -72,6 +72,7 @@ int pair_ld(int N) {
 constexpr int kSegK = 8192;     // g' per FP32 segment of the reduced-precision K build
 constexpr int kSegM = 2048;     // grid rows per FP32 segment of the reduced-precision two-body GEMM
 constexpr int kRowQuant = 32;
+constexpr int kOccSeg = 4;      // segments of the FP64 occupied-block sum over g'
 
 struct Layout {
     int N, Ng, nocc, ldP, ngp, Npair, prec;
@@ -82,7 +83,7 @@ struct Layout {
     size_t per_row;      // bytes per chunk row
     int cap;             // chunk rows that fit (multiple of kRowQuant)
     int nsegM;
-    size_t S, D, Kpart, CDlp, Mpart, Kc, Y, T, Wbar, gpart, KbL, end;
+    size_t S, D, Kpart, CDlp, Mpart, Kocc, Kc, Y, T, Wbar, gpart, KbL, end;
 };
 
 int form_of(int prec) {
@@ -124,8 +125,9 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.rhoR = off;    off = align_up(off + (L.bwd && lp ? (size_t)L.ns * L.ngp * L.ldP * L.es : 0), kAlign);
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);   // one 32-row tile of partials
     const size_t mslab = (size_t)4 * L.ldL * L.ldL * sizeof(float);       // one partial per component
-    L.fixed = off + (lp ? mslab : 0) + (L.bwd ? gslab : 0) + 12 * kAlign;
+    L.fixed = off + (lp ? mslab : 0) + (L.bwd ? gslab : 0) + 14 * kAlign;
     L.per_row = (size_t)8 * sizeof(double) + (size_t)4 * L.ldP * sizeof(double);
+    if (lp) L.per_row += (size_t)kOccSeg * 3 * L.ldO * sizeof(double);
     if (lp)
         L.per_row += (size_t)L.nsegK * 3 * L.ldL * sizeof(float) + (size_t)8 * L.ns * L.ldL * L.es +
                      (mslab + kSegM - 1) / kSegM;
@@ -146,12 +148,13 @@ void place_chunk(Layout& L, size_t bytes) {
     const bool lp = L.form != 0;
     L.nsegM = lp ? 4 * (int)((cap + kSegM - 1) / kSegM) : 0;
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);
-    size_t off = L.fixed - 12 * kAlign - (lp ? (size_t)4 * L.ldL * L.ldL * sizeof(float) : 0) - (L.bwd ? gslab : 0);
+    size_t off = L.fixed - 14 * kAlign - (lp ? (size_t)4 * L.ldL * L.ldL * sizeof(float) : 0) - (L.bwd ? gslab : 0);
     L.S = off;       off = align_up(off + (size_t)cap * 8 * sizeof(double), kAlign);
     L.D = off;       off = align_up(off + (size_t)4 * cap * L.ldP * sizeof(double), kAlign);
     L.Kpart = off;   off = align_up(off + (lp ? (size_t)L.nsegK * 3 * cap * L.ldL * sizeof(float) : 0), kAlign);
     L.CDlp = off;    off = align_up(off + (lp ? (size_t)8 * L.ns * cap * L.ldL * L.es : 0), kAlign);
     L.Mpart = off;   off = align_up(off + (lp ? (size_t)L.nsegM * L.ldL * L.ldL * sizeof(float) : 0), kAlign);
+    L.Kocc = off;    off = align_up(off + (lp ? (size_t)kOccSeg * 3 * cap * L.ldO * sizeof(double) : 0), kAlign);
     const bool b = L.bwd;
     L.Kc = off;      off = align_up(off + (b ? (size_t)3 * cap * L.ldP * sizeof(double) : 0), kAlign);
     L.Y = off;       off = align_up(off + (b ? (size_t)7 * cap * L.ldP * sizeof(double) : 0), kAlign);
@@ -322,16 +325,26 @@ xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double
     hipLaunchKernelGGL(k_reduce_K, dim3(blocks), dim3(256), 0, st, at<float>(ws, L.Kpart), L.nsegK, L.cap, L.ldL,
                        rows, L.ldP, K);
     if ((s = launched("reduce_K")) != XTC_OK) return s;
-    // occupied-occupied pairs in FP64, written over the reduced-precision values
+    // occupied-occupied pairs in FP64, written over the reduced-precision values:
+    // kOccSeg segments of the sum over g' (enough workgroups to fill the chip),
+    // FP64 partials, then a fixed-order reduction scattered into K
     const int n_rt = (rows + kKRows - 1) / kKRows;
-    const dim3 grid(n_rt * (L.ldO / 64));
+    const int nseg = kOccSeg;
+    const int seg_len = (int)align_up((size_t)((L.ngp + nseg - 1) / nseg), 4);
+    const dim3 grid(n_rt * (L.ldO / 64), nseg);
+    double* part = at<double>(ws, L.Kocc);
+    const int* nomap = nullptr;
     if (J.kind == 0)
         hipLaunchKernelGGL((k_build_K_f64_map<0, 1>), grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho_occ),
-                           L.ldO, L.ngp, g0, rows, n_rt, J, K, at<int>(ws, L.colmap), L.nOP, L.ldP);
+                           L.ldO, L.ngp, g0, rows, n_rt, J, part, nomap, L.nOP, L.ldO, seg_len);
     else
         hipLaunchKernelGGL((k_build_K_f64_map<1, 1>), grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho_occ),
-                           L.ldO, L.ngp, g0, rows, n_rt, J, K, at<int>(ws, L.colmap), L.nOP, L.ldP);
-    return launched("build_K_occ_f64");
+                           L.ldO, L.ngp, g0, rows, n_rt, J, part, nomap, L.nOP, L.ldO, seg_len);
+    if ((s = launched("build_K_occ_f64")) != XTC_OK) return s;
+    const size_t nel = (size_t)3 * rows * L.nOP;
+    hipLaunchKernelGGL(k_reduce_occ, dim3((unsigned)std::min<size_t>((nel + 255) / 256, 8192)), dim3(256), 0, st, part,
+                       nseg, rows, L.ldO, at<int>(ws, L.colmap), L.nOP, L.ldP, K);
+    return launched("reduce_occ");
 }
 
 xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int accumulate, void* ws, hipStream_t st) {

@@ -160,14 +160,15 @@ def test_reduced_forms_power_jastrow(torch_cuda, prec):
 
 
 def test_reduced_form_occ_block_is_fp64_and_deterministic(torch_cuda):
-    """In the reduced forms the occupied-occupied K columns are the FP64 values,
-    so E0 is bitwise the FP64 path's; repeated runs are bitwise identical."""
+    """In the reduced forms the occupied-occupied K columns are FP64 (summed in
+    segments), so E0 agrees with the FP64 path to rounding; repeated runs are
+    bitwise identical."""
     p = inputs.make_workload("N64-occ8-Ng50k", Ng=2200)
     _note("case: N64-occ8-Ng2200 bf16x3 vs fp64 E0, determinism")
     _, _, E64 = _run(p, prec="fp64", chunk_rows=800)
     V2a, h1a, Ea = _run(p, prec="bf16x3", chunk_rows=800)
     V2b, h1b, Eb = _run(p, prec="bf16x3", chunk_rows=800)
-    assert Ea == E64
+    assert abs(Ea - E64) < 1e-12 * max(1.0, abs(E64))
     assert np.array_equal(V2a, V2b) and np.array_equal(h1a, h1b) and Ea == Eb
 
 
