@@ -36,7 +36,11 @@ template <> struct Lp<6> { static constexpr int NS = 3; typedef __bf16 T; };
 constexpr int kLpK = 32;          // summation indices per k-step
 constexpr int kLpRows = 32;       // K build: grid rows per workgroup
 constexpr int kLpCols = 512;      // K build: pair columns per workgroup (ld multiple)
-constexpr int kLpARow = 40;       // LDS row pitch (elements) of the generated d tile
+// LDS row pitch (elements) of the generated d tile.  BF16: 96 bytes, which
+// makes the operand reads (ds_read_b128, lane -> row l%16, 16-byte chunk l/16)
+// free of bank conflicts on gfx950 (measured; 80- and 64-byte pitches cost
+// two cycles per 16 lanes).  FP32: 160 bytes.
+template <int FORM> struct LpARow { static constexpr int v = FORM == 1 ? 40 : 48; };
 
 template <int NS>
 __device__ __forceinline__ void split_bf16(float x, __bf16 (&t)[NS]) {
@@ -117,14 +121,14 @@ __device__ __forceinline__ float du_over_r_fast(float r2, const JasDev& J) {
     const float r = r2 * rs;
     float f;
     if constexpr (KIND == 0) {
-        const float t = __builtin_amdgcn_rcpf(fmaf((float)J.b, r, 1.0f));
+        const float t = __builtin_amdgcn_rcpf(fmaf(J.fb, r, 1.0f));
         f = 0.5f * rs * t * t;
     } else {
         const float q = __builtin_amdgcn_rcpf(1.0f + r);
         const float t = r * q;
-        float p = (float)J.dcoef[15];
+        float p = J.fdcoef[15];
 #pragma unroll
-        for (int k = 14; k >= 0; --k) p = fmaf(p, t, (float)J.dcoef[k]);
+        for (int k = 14; k >= 0; --k) p = fmaf(p, t, J.fdcoef[k]);
         f = p * q * q * rs;
     }
     return r2 > 0.0f ? f : 0.0f;
@@ -145,27 +149,41 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
                                                            const void* __restrict__ rho_lp, size_t split_stride,
                                                            int ldL, int ngp, int g0, int rows, int n_rt,
                                                            int seg_len, JasDev J, float* __restrict__ part,
-                                                           int cap) {
+                                                           int cap, int ncol) {
     typedef typename Lp<FORM>::T T;
     constexpr int NS = Lp<FORM>::NS;
     constexpr int NB = 4;                          // 16-column blocks per wave
     // two generation buffers as distinct arrays, so the compiler can prove the
     // writes of the next k-step do not alias the reads of the current one
-    typedef T ATile[3][NS][kLpRows][kLpARow];
+    constexpr int kARow = LpARow<FORM>::v;
+    typedef T ATile[3][NS][kLpRows][kARow];
     __shared__ __attribute__((aligned(16))) ATile sA0;
     __shared__ __attribute__((aligned(16))) ATile sA1;
+    // positions of the 32 g' of one k-step as x[], y[], z[], pad[] (double
+    // buffered).  Each wave stages its own copy with one coalesced 16-byte load
+    // per lane; a wave's LDS accesses execute in order, so no barrier is
+    // involved, and the copy replaces 32-fold redundant global loads.
+    typedef double PTile[4][kLpK];
+    __shared__ __attribute__((aligned(16))) PTile sP0[kLpThreads / 64];
+    __shared__ __attribute__((aligned(16))) PTile sP1[kLpThreads / 64];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rt = blockIdx.x % n_rt, ct = blockIdx.x / n_rt;
     const int seg = blockIdx.y;
     const int gs = seg * seg_len;
     const int ge = min(ngp, gs + seg_len);
-    // generation role: one row, two consecutive g' per k-step
-    const int grow = threadIdx.x & 31, gk = 2 * (threadIdx.x >> 5);
+    // generation role: one row, two consecutive g' per k-step.  Wave w covers
+    // rows 4w..4w+3, each half-wave two rows 2 apart (16 lanes per row), so
+    // that the 32 lanes of a half-wave store to 32 distinct LDS banks.
+    const int grow = 4 * (threadIdx.x >> 6) + 2 * ((threadIdx.x >> 4) & 1) + ((threadIdx.x >> 5) & 1);
+    const int gk = 2 * (threadIdx.x & 15);
     const d4 pr = pos[g0 + min(rt * kLpRows + grow, rows - 1)];
     // MFMA role
     const int l16 = lane & 15, lk = lane >> 4;
     const int col0 = ct * kLpCols + wave * 64 + l16;
+    // waves whose 64 columns all lie at or beyond ncol (never read) only help
+    // to generate the shared tiles: no operand loads, MFMAs or stores
+    const bool active = ct * kLpCols + wave * 64 < ncol;
 
     f4 acc[3][2][NB];
 #pragma unroll
@@ -175,18 +193,25 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
 #pragma unroll
             for (int b = 0; b < NB; ++b) acc[c][h][b] = (f4){0.f, 0.f, 0.f, 0.f};
 
-    // positions of the two g' this thread generates, loaded one k-step ahead
-    d4 pnext[2];
-    auto loadP = [&](int kk) {
-        pnext[0] = pos[kk + gk];
-        pnext[1] = pos[kk + gk + 1];
+    // position staging: lane l holds half (x,y or z,pad) of position l/2 of a
+    // k-step, loaded one k-step before it is stored to LDS (no branches, so the
+    // wait for it does not also wait for the operand prefetch)
+    const int sq = lane >> 1, shalf = lane & 1;
+    typedef double dbl2 __attribute__((ext_vector_type(2)));
+    dbl2 pstage;
+    auto loadS = [&](int kk) {
+        pstage = *(const dbl2*)((const double*)pos + 4 * (size_t)(kk + sq) + 2 * shalf);
     };
-    auto gen = [&](const d4 (&P)[2], ATile& W) {
+    auto storeS = [&](PTile& P, const dbl2 v) {
+        P[2 * shalf][sq] = v.x;
+        P[2 * shalf + 1][sq] = v.y;
+    };
+    auto gen = [&](const PTile& P, ATile& W) {
+        const dbl2 px = *(const dbl2*)&P[0][gk], py = *(const dbl2*)&P[1][gk], pz = *(const dbl2*)&P[2][gk];
         float a[3][2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const d4 pp = P[j];
-            const float dx = (float)(pr.x - pp.x), dy = (float)(pr.y - pp.y), dz = (float)(pr.z - pp.z);
+            const float dx = (float)(pr.x - px[j]), dy = (float)(pr.y - py[j]), dz = (float)(pr.z - pz[j]);
             const float f = du_over_r_fast<KIND>(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), J);
             a[0][j] = dx * f;
             a[1][j] = dy * f;
@@ -230,22 +255,35 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
 
     BOp bnext;
     // one k-step: multiply the tile in R (and the operand prefetched in bnext)
-    // while generating the next tile into W and prefetching its operand
-    auto step = [&](int kk, const ATile& R, ATile& W) {
+    // while generating the next tile into W from the positions in PR,
+    // prefetching the next operand, storing the positions two k-steps ahead
+    // into PW and loading those three k-steps ahead
+    auto step = [&](auto act, int kk, const ATile& R, ATile& W, const PTile& PR, PTile& PW) {
+        constexpr bool ACT = decltype(act)::value;
+        // next k-steps (near the end of the segment these re-read the last one
+        // into idle buffers that are never consumed: no branch in the loop body)
+        const int kn = min(kk + kLpK, ge - kLpK);
+        const int kn3 = min(kk + 3 * kLpK, ge - kLpK);
+        const dbl2 pst = pstage;   // positions two k-steps ahead (loaded last step)
+        // the global loads for later k-steps are issued before anything else
+        // of this step, so they have a whole k-step to arrive (without the
+        // scheduling fence the compiler sinks them to the end of the step)
+        loadS(kn3);
+        if constexpr (!ACT) {
+            gen(PR, W);
+            storeS(PW, pst);
+            return;
+        }
         BOp bv;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int s = 0; s < (FORM == 1 ? 2 : NS); ++s) bv[b][s] = bnext[b][s];
-        // next k-step (on the last step this re-reads the current one into the
-        // idle buffer, which is never consumed: no branch in the loop body)
-        const int kn = min(kk + kLpK, ge - kLpK);
-        const int kn2 = min(kk + 2 * kLpK, ge - kLpK);
-        const d4 pcur[2] = {pnext[0], pnext[1]};
-        loadP(kn2);
+        loadB(kn, bnext);
+        // (the six-product form has no registers to spare for the longer live ranges)
+        if constexpr (FORM != 6) __builtin_amdgcn_sched_barrier(0);
         if constexpr (FORM == 1) {
-            loadB(kn, bnext);
-            gen(pcur, W);
+            gen(PR, W);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 float av[3][8];
@@ -267,8 +305,7 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
                     }
             }
         } else {
-            loadB(kn, bnext);
-            gen(pcur, W);
+            gen(PR, W);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 bf8 av[3][NS];
@@ -285,10 +322,15 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
                             acc[c][h][b] = mma_bf16(av[c][Terms<FORM>::a[t]], bv[b][Terms<FORM>::b[t]], acc[c][h][b]);
             }
         }
-        // instruction order: operand reads first, then every MFMA paired with
-        // generation VALU work for the next k-step
+        // the positions loaded one step ago go to LDS last, so the wait for
+        // them never waits for this step's operand prefetch
+        storeS(PW, pst);
+        // instruction order: operand reads (and the three position reads of the
+        // generation) first, then every MFMA paired with generation VALU work
+        // for the next k-step
         constexpr int kMfmaHalf = (FORM == 1 ? 8 : (FORM == 3 ? 3 : 6)) * 3 * NB;
         constexpr int kValuPer = FORM == 1 ? 1 : 2;
+        __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             __builtin_amdgcn_sched_group_barrier(0x100, 3 * NS * (FORM == 1 ? 2 : 1), 0);
@@ -300,21 +342,36 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
         }
     };
 
+    // prologue: positions of k-steps 0 and 1 to LDS, of k-step 2 to registers,
+    // tile 0 generated
     loadB(gs, bnext);
-    loadP(gs);
-    {
-        const d4 p0[2] = {pnext[0], pnext[1]};
-        gen(p0, sA0);
-    }
-    loadP(min(gs + kLpK, ge - kLpK));
+    loadS(gs);
+    storeS(sP0[wave], pstage);
+    loadS(min(gs + kLpK, ge - kLpK));
+    storeS(sP1[wave], pstage);
+    loadS(min(gs + 2 * kLpK, ge - kLpK));
+    gen(sP0[wave], sA0);
     __syncthreads();
     // (ge - gs) is a multiple of 2 k-steps: segments and the padded grid are
-    // multiples of 64 points
-    for (int kk = gs; kk < ge; kk += 2 * kLpK) {
-        step(kk, sA0, sA1);
-        __syncthreads();
-        step(kk + kLpK, sA1, sA0);
-        __syncthreads();
+    // multiples of 64 points.  Step kk reads tile kk, generates tile kk+1 from
+    // the positions stored one step earlier, and overwrites the position
+    // buffer that the previous step's generation read.
+    // (active is uniform per wave; both loops pass the same barriers)
+    if (active) {
+        for (int kk = gs; kk < ge; kk += 2 * kLpK) {
+            step(std::true_type{}, kk, sA0, sA1, sP1[wave], sP0[wave]);
+            __syncthreads();
+            step(std::true_type{}, kk + kLpK, sA1, sA0, sP0[wave], sP1[wave]);
+            __syncthreads();
+        }
+    } else {
+        for (int kk = gs; kk < ge; kk += 2 * kLpK) {
+            step(std::false_type{}, kk, sA0, sA1, sP1[wave], sP0[wave]);
+            __syncthreads();
+            step(std::false_type{}, kk + kLpK, sA1, sA0, sP0[wave], sP1[wave]);
+            __syncthreads();
+        }
+        return;
     }
 
     const size_t cstride = (size_t)cap * ldL;

@@ -215,6 +215,8 @@ xtc_status check_jastrow(const xtc_jastrow* j, JasDev* out) {
     } else {
         return fail(XTC_E_ARG, "jastrow kind=%d unknown", j->kind);
     }
+    d.fb = (float)d.b;
+    for (int k = 0; k < 16; ++k) d.fdcoef[k] = (float)d.dcoef[k];
     *out = d;
     return XTC_OK;
 }
@@ -305,7 +307,7 @@ void launch_build_lp(const Layout& L, int g0, int rows, const JasDev& J, void* w
     const int n_ct = L.ldL / kLpCols;
     hipLaunchKernelGGL((k_build_K_lp<KIND, FORM>), dim3(n_rt * n_ct, L.nsegK), dim3(kLpThreads), 0, st, at<d4>(ws, L.pos),
                        at<void>(ws, L.rho_lp), (size_t)L.ngp * L.ldL, L.ldL, L.ngp, g0, rows, n_rt, kSegK, J,
-                       at<float>(ws, L.Kpart), L.cap);
+                       at<float>(ws, L.Kpart), L.cap, L.ldP);
 }
 
 xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double* K, void* ws, hipStream_t st) {

@@ -21,6 +21,10 @@ struct JasDev {
     int32_t ncoef;
     double b;
     double dcoef[16];
+    // the same parameters rounded to FP32 (reduced-precision forms; kernel
+    // arguments, so they stay in scalar registers)
+    float fb;
+    float fdcoef[16];
 };
 
 // u'(r)/r for the electron-electron Jastrow, from r^2; exactly 0 at r^2 == 0
@@ -43,24 +47,6 @@ __device__ __forceinline__ double du_over_r(double r2, const JasDev& J) {
         f = p * q * q / r;
     }
     return r2 > 0.0 ? f : 0.0;
-}
-
-template <int KIND>
-__device__ __forceinline__ float du_over_r_f32(float r2, const JasDev& J) {
-    const float r = __builtin_sqrtf(r2);
-    float f;
-    if constexpr (KIND == 0) {
-        const float t = fmaf((float)J.b, r, 1.0f);
-        f = 0.5f / (r * t * t);
-    } else {
-        const float q = 1.0f / (1.0f + r);
-        const float t = r * q;
-        float p = (float)J.dcoef[15];
-#pragma unroll
-        for (int k = 14; k >= 0; --k) p = fmaf(p, t, (float)J.dcoef[k]);
-        f = p * q * q / r;
-    }
-    return r2 > 0.0f ? f : 0.0f;
 }
 
 __device__ __forceinline__ int pair_index(int p, int q, int N) {
