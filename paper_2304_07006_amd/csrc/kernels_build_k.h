@@ -94,53 +94,50 @@ __global__ __launch_bounds__(256) void k_build_K_f64(const d4* __restrict__ pos,
     }
 }
 
-
-// Column-mapped variant (64*NH columns per workgroup):
-// Workgroup tile: 64 rows (g) x 64*NH pair columns; each wave owns 16 rows and
-// the 3 vector components of its 64*NH columns (12*NH accumulator blocks).
-// Tiles are numbered row-tile fastest, so workgroups resident at the same
-// time share one column strip of rho (read through L2), whatever XCD they
-// land on.  With colmap != nullptr, output column c < nmap is stored to
-// K[x][r][colmap[c]] (used to overwrite the occupied-occupied pairs of a
-// reduced-precision K with FP64 values); otherwise K has leading dim ldP.
-template <int KIND, int NH>
-__global__ __launch_bounds__(256) void k_build_K_f64_map(const d4* __restrict__ pos,
-                                                     const double* __restrict__ rho, int ldP,
-                                                     int ngp, int g0, int rows, int n_rt, JasDev J,
-                                                     double* __restrict__ K, const int* __restrict__ colmap,
-                                                     int nmap, int ldK, int seg_len) {
+// Occupied-occupied block of K in FP64, for the reduced-precision forms: the
+// same contraction as k_build_K_f64 over the gathered pair densities
+// rho_occ[g'][ldO] of the occupied pairs, one segment [blockIdx.y * seg_len,
+// ...) of the sum over g' per grid.y, written to part[seg][x][r][ldO].
+// Workgroup: 64 rows x 16 NBLK columns; each wave owns 16 rows and NBLK
+// 16-column blocks of all 3 components.  The host picks NBLK to minimise the
+// column padding (136 occupied pairs: 2 tiles of 80 columns).
+template <int KIND, int NBLK>
+__global__ __launch_bounds__(256) void k_build_K_occ(const d4* __restrict__ pos, const double* __restrict__ rho_occ,
+                                                     int ldO, int ngp, int g0, int rows, int n_rt, JasDev J,
+                                                     double* __restrict__ part, int seg_len) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int rt = blockIdx.x % n_rt;
     const int ct = blockIdx.x / n_rt;
-    // grid.y selects a segment [gs, ge) of the sum over g'; with several
-    // segments each writes its own slab K + seg * 3 * rows * ldK
     const int gs = blockIdx.y * seg_len, ge = min(ngp, gs + seg_len);
-    K += (size_t)blockIdx.y * 3 * rows * ldK;
     const int rloc0 = rt * kKRows + wave * kKRowsPerWave;   // first local row of this wave
     const int my = min(rloc0 + (lane & 15), rows - 1);      // row whose d^x this lane generates
     const d4 pg = pos[g0 + my];
     const int kq = lane >> 4;
-    const int col = ct * 64 * NH + 4 * (lane & 15);
+    const int col = ct * 16 * NBLK + (lane & 15);
 
-    d4 acc[3][4 * NH];
+    d4 acc[3][NBLK];
 #pragma unroll
     for (int x = 0; x < 3; ++x)
 #pragma unroll
-        for (int c = 0; c < 4 * NH; ++c) acc[x][c] = (d4){0.0, 0.0, 0.0, 0.0};
+        for (int c = 0; c < NBLK; ++c) acc[x][c] = (d4){0.0, 0.0, 0.0, 0.0};
 
-    const double* bp = rho + (size_t)(gs + kq) * ldP + col;
+    const double* bp = rho_occ + (size_t)(gs + kq) * ldO + col;
     const d4* pp = pos + gs + kq;
-    d4 b0 = *(const d4*)bp;
-    d4 b1 = NH == 2 ? *(const d4*)(bp + 64) : b0;
+    double b[NBLK];
+#pragma unroll
+    for (int c = 0; c < NBLK; ++c) b[c] = bp[16 * c];
     d4 pc = *pp;
     for (int kk = gs; kk < ge; kk += 4) {
-        const d4 cb0 = b0, cb1 = b1, cp = pc;
+        double cb[NBLK];
+#pragma unroll
+        for (int c = 0; c < NBLK; ++c) cb[c] = b[c];
+        const d4 cp = pc;
         if (kk + 4 < ge) {               // prefetch the next 4 grid columns
-            bp += (size_t)4 * ldP;
+            bp += (size_t)4 * ldO;
             pp += 4;
-            b0 = *(const d4*)bp;
-            if constexpr (NH == 2) b1 = *(const d4*)(bp + 64);
+#pragma unroll
+            for (int c = 0; c < NBLK; ++c) b[c] = bp[16 * c];
             pc = *pp;
         }
         const double dx = pg.x - cp.x, dy = pg.y - cp.y, dz = pg.z - cp.z;
@@ -148,21 +145,13 @@ __global__ __launch_bounds__(256) void k_build_K_f64_map(const d4* __restrict__ 
         const double f = du_over_r<KIND>(r2, J);
         const double ax = dx * f, ay = dy * f, az = dz * f;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            acc[0][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, cb0[c], acc[0][c], 0, 0, 0);
-            acc[1][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, cb0[c], acc[1][c], 0, 0, 0);
-            acc[2][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, cb0[c], acc[2][c], 0, 0, 0);
-        }
-        if constexpr (NH == 2) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                acc[0][4 + c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, cb1[c], acc[0][4 + c], 0, 0, 0);
-                acc[1][4 + c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, cb1[c], acc[1][4 + c], 0, 0, 0);
-                acc[2][4 + c] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, cb1[c], acc[2][4 + c], 0, 0, 0);
-            }
+        for (int c = 0; c < NBLK; ++c) {
+            acc[0][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, cb[c], acc[0][c], 0, 0, 0);
+            acc[1][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, cb[c], acc[1][c], 0, 0, 0);
+            acc[2][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, cb[c], acc[2][c], 0, 0, 0);
         }
     }
-    const size_t kstride = (size_t)rows * ldK;
+    double* out = part + (size_t)blockIdx.y * 3 * rows * ldO;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int r = rloc0 + (lane >> 4) + 4 * v;
@@ -170,20 +159,7 @@ __global__ __launch_bounds__(256) void k_build_K_f64_map(const d4* __restrict__ 
 #pragma unroll
             for (int x = 0; x < 3; ++x)
 #pragma unroll
-                for (int h = 0; h < NH; ++h) {
-                    const d4 val = {acc[x][4 * h + 0][v], acc[x][4 * h + 1][v], acc[x][4 * h + 2][v],
-                                    acc[x][4 * h + 3][v]};
-                    double* out = K + x * kstride + (size_t)r * ldK;
-                    if (colmap == nullptr) {
-                        *(d4*)(out + col + 64 * h) = val;
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int c = col + 64 * h + i;
-                            if (c < nmap) out[colmap[c]] = val[i];
-                        }
-                    }
-                }
+                for (int c = 0; c < NBLK; ++c) out[((size_t)x * rows + r) * ldO + col + 16 * c] = acc[x][c][v];
         }
     }
 }

@@ -76,7 +76,7 @@ constexpr int kOccSeg = 4;      // segments of the FP64 occupied-block sum over 
 
 struct Layout {
     int N, Ng, nocc, ldP, ngp, Npair, prec;
-    int form, ns, es, ldL, ldO, nOP, nsegK;
+    int form, ns, es, ldL, ldO, nOP, occNB, nsegK;
     bool bwd;
     size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, isocc, kidx, rhoR;
     size_t fixed;        // bytes before S (plus the Mpart remainder reserve)
@@ -89,6 +89,22 @@ struct Layout {
 int form_of(int prec) {
     prec &= 0xF;
     return prec == XTC_FP32 ? 1 : prec == XTC_BF16X3 ? 3 : prec == XTC_BF16X6 ? 6 : 0;
+}
+
+
+// 16-column blocks per wave of the FP64 occupied-block kernel: the count in
+// [1, 8] that pads nOP least (ties: more blocks, fewer workgroup columns).
+int occ_blocks(int nOP) {
+    int best = 4;
+    size_t best_cols = align_up((size_t)nOP, 64);
+    for (int nb = 1; nb <= 8; ++nb) {
+        const size_t cols = align_up((size_t)nOP, (size_t)16 * nb);
+        if (cols < best_cols || (cols == best_cols && nb > best)) {
+            best = nb;
+            best_cols = cols;
+        }
+    }
+    return best;
 }
 
 Layout make_layout(const xtc_problem* pb, int prec) {
@@ -105,7 +121,8 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.es = L.form == 1 ? 4 : 2;
     L.ldL = (int)align_up((size_t)L.ldP, kLpCols);
     L.nOP = pb->nocc * (pb->nocc + 1) / 2;
-    L.ldO = (int)align_up((size_t)L.nOP, 64);
+    L.occNB = occ_blocks(L.nOP);
+    L.ldO = (int)align_up((size_t)L.nOP, (size_t)16 * L.occNB);
     L.nsegK = (L.ngp + kSegK - 1) / kSegK;
     L.bwd = (prec & XTC_WITH_BACKWARD) != 0;
     const bool lp = L.form != 0;
@@ -310,6 +327,29 @@ void launch_build_lp(const Layout& L, int g0, int rows, const JasDev& J, void* w
                        at<float>(ws, L.Kpart), L.cap, L.ldP);
 }
 
+template <int KIND, int NB>
+void launch_build_occ_nb(const Layout& L, int g0, int rows, int n_rt, int nseg, int seg_len, const JasDev& J, void* ws,
+                         hipStream_t st) {
+    const dim3 grid(n_rt * (L.ldO / (16 * NB)), nseg);
+    hipLaunchKernelGGL((k_build_K_occ<KIND, NB>), grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho_occ),
+                       L.ldO, L.ngp, g0, rows, n_rt, J, at<double>(ws, L.Kocc), seg_len);
+}
+
+template <int KIND>
+void launch_build_occ(const Layout& L, int g0, int rows, int n_rt, int nseg, int seg_len, const JasDev& J, void* ws,
+                      hipStream_t st) {
+    switch (L.occNB) {
+        case 1: return launch_build_occ_nb<KIND, 1>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
+        case 2: return launch_build_occ_nb<KIND, 2>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
+        case 3: return launch_build_occ_nb<KIND, 3>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
+        case 4: return launch_build_occ_nb<KIND, 4>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
+        case 5: return launch_build_occ_nb<KIND, 5>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
+        case 6: return launch_build_occ_nb<KIND, 6>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
+        case 7: return launch_build_occ_nb<KIND, 7>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
+        default: return launch_build_occ_nb<KIND, 8>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
+    }
+}
+
 xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double* K, void* ws, hipStream_t st) {
     if (J.kind == 0) {
         if (L.form == 1) launch_build_lp<0, 1>(L, g0, rows, J, ws, st);
@@ -333,16 +373,10 @@ xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double
     const int n_rt = (rows + kKRows - 1) / kKRows;
     const int nseg = kOccSeg;
     const int seg_len = (int)align_up((size_t)((L.ngp + nseg - 1) / nseg), 4);
-    const dim3 grid(n_rt * (L.ldO / 64), nseg);
-    double* part = at<double>(ws, L.Kocc);
-    const int* nomap = nullptr;
-    if (J.kind == 0)
-        hipLaunchKernelGGL((k_build_K_f64_map<0, 1>), grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho_occ),
-                           L.ldO, L.ngp, g0, rows, n_rt, J, part, nomap, L.nOP, L.ldO, seg_len);
-    else
-        hipLaunchKernelGGL((k_build_K_f64_map<1, 1>), grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho_occ),
-                           L.ldO, L.ngp, g0, rows, n_rt, J, part, nomap, L.nOP, L.ldO, seg_len);
+    if (J.kind == 0) launch_build_occ<0>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
+    else launch_build_occ<1>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
     if ((s = launched("build_K_occ_f64")) != XTC_OK) return s;
+    double* part = at<double>(ws, L.Kocc);
     const size_t nel = (size_t)3 * rows * L.nOP;
     hipLaunchKernelGGL(k_reduce_occ, dim3((unsigned)std::min<size_t>((nel + 255) / 256, 8192)), dim3(256), 0, st, part,
                        nseg, rows, L.ldO, at<int>(ws, L.colmap), L.nOP, L.ldP, K);
