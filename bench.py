@@ -43,7 +43,7 @@ def kernel_sources_hash():
     profiles/ are only reported while it matches)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("xtc_device.h", "kernels_build_k.h", "kernels_lp.h", "kernels_prepare.h"):
+    for f in ("xtc_device.h", "kernels_build_k.h", "kernels_lp.h", "kernels_prepare.h", "xtc_api.hip"):
         with open(os.path.join(ROOT, "paper_2304_07006_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -60,6 +60,56 @@ def traffic_record(prec, workload, chunk):
     if not e or e.get("sources") != kernel_sources_hash():
         return None
     return e
+
+
+KBUILD_KERNELS = ("k_build_K_lp", "k_reduce_K", "k_build_K_occ", "k_reduce_occ", "k_build_K_f64")
+
+
+def traffic_from(fetch_dir, write_dir, workload, prec, chunk):
+    """Write the per-launch HBM bytes of xtc_build_K into
+    profiles/traffic_xtc_build_K.json from two counter runs of --probe
+    (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, --output-format csv).
+    The 1 GiB copy of the probe calibrates both counters."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if len(files) != 1:
+            raise SystemExit(f"expected one counter_collection.csv under {d}, found {len(files)}")
+        disp = {}
+        for row in csv.DictReader(open(files[0])):
+            if row["Counter_Name"] != counter:
+                continue
+            k = (row["Dispatch_Id"], row["Kernel_Name"])
+            disp[k] = disp.get(k, 0.0) + float(row["Counter_Value"])
+        copy = [v for (_, n), v in disp.items() if "copy" in n.lower() and "fill" not in n.lower()]
+        if len(copy) != 1:
+            raise SystemExit(f"{counter}: expected one calibration copy dispatch, found {len(copy)}")
+        factor = 2 ** 20 / copy[0]                   # counters are in KiB; the copy moves 2^30 bytes
+        out = {}
+        for (_, n), v in disp.items():
+            short = n.split("(")[0].replace("void ", "").split("::")[-1].split("<")[0]
+            if short in KBUILD_KERNELS:
+                out[short] = out.get(short, 0.0) + v * 1024 * factor
+        return out, factor
+
+    fetch, ff = per_kernel(fetch_dir, "FETCH_SIZE")
+    write, wf = per_kernel(write_dir, "WRITE_SIZE")
+    path = os.path.join(ROOT, "profiles", "traffic_xtc_build_K.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    rec[f"{workload}/{prec}/{chunk}"] = {
+        "bytes_per_launch": sum(fetch.values()) + sum(write.values()),
+        "sources": kernel_sources_hash(),
+        "fetch_factor": ff, "write_factor": wf,
+        "per_kernel_bytes": {k: {"fetch": fetch.get(k, 0.0), "write": write.get(k, 0.0)}
+                             for k in sorted(set(fetch) | set(write))},
+        "command": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o run "
+                   "-- python -u bench.py --probe; python bench.py --traffic-from <fetch dir> <write dir>",
+    }
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec[f"{workload}/{prec}/{chunk}"], indent=1))
 
 
 def f_alg(N, n, Ng):
@@ -150,7 +200,7 @@ def cpu_baseline(name, budget_rows):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="N128-occ16-Ng150k")
     ap.add_argument("--prec", default="bf16x3", choices=list(PEAK))
@@ -160,7 +210,14 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=300, help="grid points of the CPU oracle sample (0: skip)")
     ap.add_argument("--probe", action="store_true",
                     help="counter pass: one 1 GiB device copy (calibration) and one K-build launch, no JSON")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two --probe counter runs into profiles/traffic_xtc_build_K.json (no GPU)")
     args = ap.parse_args()
+    if args.traffic_from:
+        from paper_2304_07006_amd import inputs
+        wl = inputs.WORKLOADS[args.workload]
+        traffic_from(*args.traffic_from, args.workload, args.prec, args.chunk or default_chunk(wl.Ng, args.prec))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the grid-row sharding is described in the design notes). Run with --gpus 1.", file=sys.stderr)

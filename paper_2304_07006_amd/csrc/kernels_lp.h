@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
                                                            const void* __restrict__ rho_lp, size_t split_stride,
                                                            int ldL, int ngp, int g0, int rows, int n_rt,
                                                            int seg_len, JasDev J, float* __restrict__ part,
-                                                           int cap, int ncol) {
+                                                           int cap, int ncol, int n_ct, int nseg) {
     typedef typename Lp<FORM>::T T;
     constexpr int NS = Lp<FORM>::NS;
     constexpr int NB = 4;                          // 16-column blocks per wave
@@ -168,8 +168,25 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
     __shared__ __attribute__((aligned(16))) PTile sP1[kLpThreads / 64];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int rt = blockIdx.x % n_rt, ct = blockIdx.x / n_rt;
-    const int seg = blockIdx.y;
+    // Flat grid, row tile fastest, so that the ~32 workgroups resident on an
+    // XCD share one column strip of the operand through its L2 while they
+    // advance through g' together.  Column tiles with idle waves finish early
+    // and would stagger every later workgroup (and break that sharing), so
+    // they are dispatched last, after all full tiles of all segments.
+    const int n_full = ((n_ct - 1) * kLpCols + 7 * 64 < ncol) ? n_ct : n_ct - 1;
+    int rt, ct, seg;
+    {
+        const int id = blockIdx.x, nf = n_rt * n_full * nseg;
+        if (id < nf) {
+            rt = id % n_rt;
+            ct = (id / n_rt) % n_full;
+            seg = id / (n_rt * n_full);
+        } else {
+            rt = (id - nf) % n_rt;
+            seg = (id - nf) / n_rt;
+            ct = n_ct - 1;
+        }
+    }
     const int gs = seg * seg_len;
     const int ge = min(ngp, gs + seg_len);
     // generation role: one row, two consecutive g' per k-step.  Wave w covers

@@ -322,9 +322,9 @@ template <int KIND, int FORM>
 void launch_build_lp(const Layout& L, int g0, int rows, const JasDev& J, void* ws, hipStream_t st) {
     const int n_rt = (rows + kLpRows - 1) / kLpRows;
     const int n_ct = L.ldL / kLpCols;
-    hipLaunchKernelGGL((k_build_K_lp<KIND, FORM>), dim3(n_rt * n_ct, L.nsegK), dim3(kLpThreads), 0, st, at<d4>(ws, L.pos),
-                       at<void>(ws, L.rho_lp), (size_t)L.ngp * L.ldL, L.ldL, L.ngp, g0, rows, n_rt, kSegK, J,
-                       at<float>(ws, L.Kpart), L.cap, L.ldP);
+    hipLaunchKernelGGL((k_build_K_lp<KIND, FORM>), dim3(n_rt * n_ct * L.nsegK), dim3(kLpThreads), 0, st,
+                       at<d4>(ws, L.pos), at<void>(ws, L.rho_lp), (size_t)L.ngp * L.ldL, L.ldL, L.ngp, g0, rows, n_rt,
+                       kSegK, J, at<float>(ws, L.Kpart), L.cap, L.ldP, n_ct, L.nsegK);
 }
 
 template <int KIND, int NB>
