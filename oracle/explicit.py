@@ -160,6 +160,34 @@ def tier_a(xyz, w, phi, occ, jas):
                 V2=V2, h1=dh[:N, :N].copy())
 
 
+def spin_orbital_gamma_general(gamma):
+    """Per-spin spatial density gamma [N][N] (the same for both spins, as in the
+    closed-shell and spin-averaged equations) as a spin-orbital matrix."""
+    N = gamma.shape[0]
+    g = np.zeros((2 * N, 2 * N))
+    g[:N, :N] = gamma
+    g[N:, N:] = gamma
+    return g
+
+
+def tier_a_density(xyz, w, phi, gamma, jas):
+    """Tier A for a general (not necessarily idempotent) per-spin density gamma:
+    eq. dU for Delta U, the first form of eq. tcmf:1el for Delta h and
+    eq. tcmf:0el for the zero-body term, all on the explicit six-index L.  For a
+    correlated density the paper uses these single-determinant expressions as
+    an approximation (higher cumulants neglected); they are its definition of
+    the folded terms for such densities."""
+    N = phi.shape[0]
+    V = grid_intermediate(xyz, w, phi, jas)
+    L = spin_orbital_L(L_spatial(xyz, w, phi, jas, V))
+    g = spin_orbital_gamma_general(np.asarray(gamma, dtype=np.float64))
+    dU = delta_U_so(L, g)
+    dh = delta_h_so_from_L(L, g)
+    E0 = -float(np.sum(dh * g)) / 3.0
+    V2 = np.ascontiguousarray(dU[:N, :N, :N, :N].transpose(0, 2, 1, 3))
+    return dict(L_so=L, gamma_so=g, dU_so=dU, dh_so=dh, E0=E0, V2=V2, h1=dh[:N, :N].copy())
+
+
 # ---------------------------------------------------------------- step 6 --
 def _apply(det: int, creators, annihilators):
     """Apply a^P1 a^P2 ... a_Qk ... a_Q1 (creators listed left to right,

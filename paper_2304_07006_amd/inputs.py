@@ -220,6 +220,26 @@ def random_occ(N: int, nocc: int, seed: int) -> np.ndarray:
     return np.sort(rng.choice(N, size=nocc, replace=False)).astype(np.int32)
 
 
+def sa_occupations(n_double: int, n_single: int) -> tuple[np.ndarray, np.ndarray]:
+    """Spin-averaged density of a high-spin open-shell determinant in its
+    orbital basis: n_double doubly occupied orbitals (1 per spin) followed by
+    n_single singly occupied ones (1/2 per spin).  Returns (orbitals, n)."""
+    k = np.arange(n_double + n_single, dtype=np.int32)
+    n = np.concatenate([np.ones(n_double), np.full(n_single, 0.5)])
+    return k, n
+
+
+def natural_occupations(nact: int, seed: int) -> np.ndarray:
+    """Per-spin natural occupation numbers of a weakly correlated closed-shell
+    density: nact orbitals, the first half near 1 (1 - 10^U(-3,-1)), the
+    rest small (10^U(-4,-1.5)), in decreasing order."""
+    rng = np.random.default_rng(seed)
+    h = (nact + 1) // 2
+    hi = 1.0 - 10.0 ** rng.uniform(-3.0, -1.0, h)
+    lo = 10.0 ** rng.uniform(-4.0, -1.5, nact - h)
+    return np.concatenate([np.sort(hi)[::-1], np.sort(lo)[::-1]])
+
+
 def loss_weights(N: int, aux_seed: int):
     """Fixed symmetric one-body weights D [N][N] and 8-fold symmetric two-body
     weights G [N][N][N][N] (chemist order) for the differentiation loss

@@ -118,3 +118,11 @@ def test_loss_weights_symmetry():
     assert np.array_equal(D, D.T)
     for perm in [(1, 0, 2, 3), (0, 1, 3, 2), (2, 3, 0, 1)]:
         assert np.allclose(G, G.transpose(perm), atol=1e-15)
+
+
+def test_occupation_generators():
+    k, n = inputs.sa_occupations(3, 2)
+    assert list(k) == [0, 1, 2, 3, 4] and list(n) == [1.0, 1.0, 1.0, 0.5, 0.5]
+    m = inputs.natural_occupations(9, 5)
+    assert m.shape == (9,) and np.all(m > 0) and np.all(m < 1) and np.all(np.diff(m) <= 0)
+    assert np.array_equal(m, inputs.natural_occupations(9, 5))

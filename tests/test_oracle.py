@@ -133,6 +133,55 @@ def test_tier_a_equals_tier_b(tiny, tierA):
     assert abs(E0 - tierA["E0"]) < 1e-15
 
 
+def _random_density(N, seed):
+    """Symmetric, non-diagonal and not idempotent."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((N, N))
+    return 0.1 * (X + X.T) + np.diag(rng.uniform(0.0, 1.0, N))
+
+
+def test_tier_a_equals_tier_b_general_density(tiny):
+    """Appendix B with a correlated (non-idempotent, non-diagonal) density equals
+    eq. dU / tcmf:1el / tcmf:0el contracted on the explicit L."""
+    g = _random_density(tiny.N, 3)
+    A = ex.tier_a_density(tiny.xyz, tiny.w, tiny.phi, g, tiny.jastrow)
+    V2, h1, E0 = fb.closed_shell(tiny.xyz, tiny.w, tiny.phi, g, tiny.jastrow)
+    assert np.abs(V2 - A["V2"]).max() < 1e-15
+    assert np.abs(h1 - A["h1"]).max() < 2e-15
+    assert abs(E0 - A["E0"]) < 1e-14 * max(1.0, abs(A["E0"]))
+    # the determinant form of the zero-body term is the same cubic in gamma
+    assert abs(ex.zero_body_so(A["L_so"], A["gamma_so"]) - A["E0"]) < 1e-14 * max(1.0, abs(A["E0"]))
+    # and for a projector the general tier A is the determinant tier A
+    P = np.zeros((tiny.N, tiny.N))
+    P[tiny.occ, tiny.occ] = 1.0
+    Ad = ex.tier_a_density(tiny.xyz, tiny.w, tiny.phi, P, tiny.jastrow)
+    Ap = ex.tier_a(tiny.xyz, tiny.w, tiny.phi, tiny.occ, tiny.jastrow)
+    assert np.abs(Ad["V2"] - Ap["V2"]).max() < 1e-16 and abs(Ad["E0"] - Ap["E0"]) < 1e-16
+
+
+def test_natural_orbital_basis_is_covariant():
+    """Outputs for (phi, gamma) equal the outputs in gamma's natural-orbital basis
+    (phi' = U^T phi, gamma' = diag(n)) rotated back with U."""
+    p = inputs.make_problem(8, 2, 800, 2, "pair", "pade", seed=11)
+    g = _random_density(p.N, 4)
+    n, U = np.linalg.eigh(g)
+    V2, h1, E0 = fb.closed_shell(p.xyz, p.w, p.phi, g, p.jastrow)
+    V2n, h1n, E0n = fb.closed_shell(p.xyz, p.w, U.T @ p.phi, np.diag(n), p.jastrow)
+    V2b = np.einsum("pa,qb,rc,sd,abcd->pqrs", U, U, U, U, V2n, optimize=True)
+    assert np.abs(V2b - V2).max() < 1e-14
+    assert np.abs(U @ h1n @ U.T - h1).max() < 1e-14
+    assert abs(E0n - E0) < 1e-13 * max(1.0, abs(E0))
+
+
+def test_two_body_term_is_linear_in_the_density():
+    p = inputs.make_problem(8, 2, 700, 2, "pair", "pade", seed=12)
+    g1, g2 = _random_density(p.N, 5), _random_density(p.N, 6)
+    a = fb.closed_shell(p.xyz, p.w, p.phi, g1, p.jastrow)[0]
+    b = fb.closed_shell(p.xyz, p.w, p.phi, g2, p.jastrow)[0]
+    c = fb.closed_shell(p.xyz, p.w, p.phi, 0.3 * g1 + 0.7 * g2, p.jastrow)[0]
+    assert np.abs(c - (0.3 * a + 0.7 * b)).max() < 1e-15
+
+
 def test_spin_blocks(tiny, tierA):
     N = tiny.N
     dU = tierA["dU_so"]
