@@ -11,7 +11,8 @@
  *   closed-shell intermediates and two-body correction (Appendix B, eq. tcmf:2el,
  *   eq. tcmf:inter)    V2[p][q][r][s] = Delta U_pr^qs
  *   one-body correction (Appendix B)  h1[p][q] = Delta h_p^q
- *   zero-body term (Appendix B)       E0 = <Psi0|L|Psi0> = -(2/3) sum_k h1[k][k]
+ *   zero-body term (Appendix B)       E0 = <Psi0|L|Psi0> = -(2/3) sum_k n_k h1[k][k]
+ *   (k over the orbitals of the reference density, n_k their per-spin occupations)
  *
  * Conventions shared by every entry point
  *   - Orbitals are real.  p,q,r,s in [0,N).  A pair index P = pair(p,q), p <= q,
@@ -88,11 +89,23 @@ typedef struct {
     double coef[16];
 } xtc_jastrow;
 
-/* The problem: orbitals on a weighted grid and the occupied orbitals of a
- * closed-shell determinant (gamma = projector onto occ, per spin; the factor
- * two of spin integration is in the equations, Appendix B).
+/* The problem: orbitals on a weighted grid and the per-spin one-body density
+ * gamma of the reference, diagonal in the orbital basis:
+ *   gamma = sum_i occ_n[i] |occ[i]><occ[i]|   (per spin; the factor two of spin
+ *   integration is in the equations, Appendix B).
+ * occ_n == NULL means 1 for every listed orbital: the closed-shell determinant
+ * (gamma = projector onto occ).  Other values give the uses of the closed-shell
+ * equations with a non-idempotent density that the paper makes: the natural
+ * orbitals and occupations of a correlated density (eq. tcmf:1el and
+ * eq. tcmf:0el then hold approximately, higher cumulants neglected), and the
+ * spin-averaged approximation for an open-shell determinant (1 for doubly and
+ * 1/2 for singly occupied orbitals; Appendix B, closing remark; results
+ * section on the SA approximation).  A non-diagonal gamma is used through its
+ * natural orbitals (phi' = U^T phi, occ_n = eigenvalues); the outputs are
+ * then in that basis.
  *   xyz [Ng][3] bohr, w [Ng], phi [N][Ng] (orthonormal under w: not checked),
- *   occ [nocc] HOST int32, distinct, in [0,N). */
+ *   occ [nocc] HOST int32, distinct, in [0,N);
+ *   occ_n [nocc] HOST double, finite, or NULL. */
 typedef struct {
     int32_t N;
     int32_t Ng;
@@ -102,6 +115,7 @@ typedef struct {
     const double *w;
     const double *phi;
     const int32_t *occ;      /* HOST */
+    const double *occ_n;     /* HOST, or NULL (all 1) */
 } xtc_problem;
 
 /* Padded leading dimension of pair-indexed arrays: Npair rounded up to 128. */
@@ -146,12 +160,12 @@ xtc_status xtc_contract_2body(const xtc_problem *pb, const double *K,
 
 /* One- and zero-body corrections (Appendix B), as an FP64 grid reduction.
  * Substituting eq. tcmf:2el into the one-body equation of Appendix B gives,
- * per grid point, with k over occ, rb = sum_k rho_kk, kb = sum_k K_kk,
- * a = sum_k A_kk, b = sum_k B_kk:
+ * per grid point, with k over occ and n_k = occ_n (1 if NULL), rb = sum_k n_k rho_kk,
+ * kb = sum_k n_k K_kk, a = sum_k n_k A_kk, b = sum_k n_k B_kk:
  *   h1[p][q] += rho_pq a + K_pq.b + rb A_pq + kb.B_pq
- *              - 1/2 sum_k (rho_pk A_kq + K_pk.B_kq + rho_qk A_kp + K_qk.B_kp)
+ *              - 1/2 sum_k n_k (rho_pk A_kq + K_pk.B_kq + rho_qk A_kp + K_qk.B_kp)
  * With XTC_FINALIZE, write h1 (device [N][N] FP64, symmetric bitwise) and
- * E0 = -(2/3) sum_k h1[k][k] (device, one FP64).  The reduction is always
+ * E0 = -(2/3) sum_k n_k h1[k][k] (device, one FP64).  The reduction is always
  * FP64; `prec` names the arithmetic the workspace was prepared for.
  * h1 and E0 may be NULL unless XTC_FINALIZE is set. */
 xtc_status xtc_contract_1body_0body(const xtc_problem *pb, const double *K,

@@ -2,8 +2,8 @@
 //
 // Loss L = gE0 E0 + sum gh1 . h1 + sum gV2 . V2 (seeds given by the caller).
 // h1 and E0 are linear in V2 (Appendix B), so L = sum_{abcd} Gt[abcd] V2[abcd]
-// with the effective seed
-//   Gt = gV2 + G1,  G1[a,b,c,c] -= D'[a][b] (c in occ),  G1[a,c,c,d] += D'[a][d]/2 (c in occ),
+// with the effective seed (gamma = diag(n) on the orbitals of the density)
+//   Gt = gV2 + G1,  G1[a,b,c,c] -= n_c D'[a][b],  G1[a,c,c,d] += n_c D'[a][d] / 2,
 //   D' = gh1 - (2/3) gE0 gamma.
 // With V2[ab,cd] = -(M[P,R] + M[R,P]) (eq. tcmf:2el) the adjoint of the packed
 // accumulator is symmetric:
@@ -24,44 +24,40 @@ namespace xtc {
 constexpr int kMaxOccAdj = 24;   // occupied orbitals supported by the adjoint
 
 // ---------------------------------------------------------------- seeds --
-__device__ __forceinline__ bool occ_has(const OccList& occ, int k) {
-    for (int i = 0; i < occ.n; ++i)
-        if (occ.k[i] == k) return true;
-    return false;
-}
-
-// Effective seed Gt[a,b,c,d] (see the header comment).
+// Effective seed Gt[a,b,c,d] (see the header comment); occw[p] = n_p, 0 for
+// orbitals outside the density.
 __device__ __forceinline__ double seed_eff(const double* __restrict__ gV2, const double* __restrict__ gh1,
-                                           double gE0, const unsigned char* __restrict__ isocc, int N, int a,
+                                           double gE0, const double* __restrict__ occw, int N, int a,
                                            int b, int c, int d) {
     const size_t NN = (size_t)N * N;
     double v = gV2 ? gV2[((size_t)a * N + b) * NN + (size_t)c * N + d] : 0.0;
-    if (c == d && isocc[c]) {
+    if (c == d && occw[c] != 0.0) {
         double dp = gh1 ? gh1[(size_t)a * N + b] : 0.0;
-        if (a == b && isocc[a]) dp -= (2.0 / 3.0) * gE0;
-        v -= dp;
+        if (a == b) dp -= (2.0 / 3.0) * gE0 * occw[a];
+        v -= occw[c] * dp;
     }
-    if (b == c && isocc[b]) {
+    if (b == c && occw[b] != 0.0) {
         double dp = gh1 ? gh1[(size_t)a * N + d] : 0.0;
-        if (a == d && isocc[a]) dp -= (2.0 / 3.0) * gE0;
-        v += 0.5 * dp;
+        if (a == d) dp -= (2.0 / 3.0) * gE0 * occw[a];
+        v += 0.5 * occw[b] * dp;
     }
     return v;
 }
 
-__global__ void k_occ_flags(OccList occ, int N, unsigned char* __restrict__ isocc, int* __restrict__ kidx) {
+// occw[p] = n_p (0 outside the density), kidx[p] = position of p in occ or -1.
+__global__ void k_occ_flags(OccList occ, int N, double* __restrict__ occw, int* __restrict__ kidx) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     int idx = -1;
     for (int i = 0; i < occ.n; ++i)
         if (occ.k[i] == p) idx = i;
-    isocc[p] = idx >= 0;
+    occw[p] = idx >= 0 ? occ.w[idx] : 0.0;
     kidx[p] = idx;
 }
 
 // Gbar[P][R] for P, R < Npair; zero in the padding.
 __global__ __launch_bounds__(256) void k_make_gbar(const double* __restrict__ gV2, const double* __restrict__ gh1,
-                                                   double gE0, const unsigned char* __restrict__ isocc, int N,
+                                                   double gE0, const double* __restrict__ occw, int N,
                                                    int ldP, double* __restrict__ G) {
     const int R = blockIdx.x * blockDim.x + threadIdx.x;
     const int P = blockIdx.y;
@@ -82,7 +78,7 @@ __global__ __launch_bounds__(256) void k_make_gbar(const double* __restrict__ gV
         for (int i = 0; i < nab; ++i)
             for (int j = 0; j < ncd; ++j) {
                 const int a = ab[i][0], b = ab[i][1], c = cd[j][0], d = cd[j][1];
-                acc += seed_eff(gV2, gh1, gE0, isocc, N, a, b, c, d) + seed_eff(gV2, gh1, gE0, isocc, N, c, d, a, b);
+                acc += seed_eff(gV2, gh1, gE0, occw, N, a, b, c, d) + seed_eff(gV2, gh1, gE0, occw, N, c, d, a, b);
             }
     }
     G[(size_t)P * ldP + R] = -acc;
@@ -142,7 +138,7 @@ __global__ __launch_bounds__(256) void k_gemm_xg_f64(const double* __restrict__ 
 // Per grid point g (one workgroup at a time): with X^x = K^x[:, occ],
 // rho_o = rho[:, occ] and the half-weighted symmetric Abar', Bbar'^x
 // (off-diagonal packed entries counted half in each full-matrix slot),
-//   T^x[r][k] = -2 sum_s (Abar'[r][s] X^x[s][k] + Bbar'^x[r][s] rho_o[s][k])
+//   T^x[r][k] = -2 n_k sum_s (Abar'[r][s] X^x[s][k] + Bbar'^x[r][s] rho_o[s][k])
 // and Wbar^x = sum_R Abar_R K^x_R.  T goes to scratch [rows][3][N][nocc].
 __global__ __launch_bounds__(256) void k_adj_T(const double* __restrict__ rho_rows, const double* __restrict__ K,
                                                const double* __restrict__ Y, size_t ystride, int rows, int ldP,
@@ -209,9 +205,10 @@ __global__ __launch_bounds__(256) void k_adj_T(const double* __restrict__ rho_ro
 #pragma unroll
             for (int kk = 0; kk < kMaxOccAdj; ++kk) {
                 if (kk < n) {
-                    tg[(size_t)0 * N * n + r * n + kk] = -2.0 * t0[kk];
-                    tg[(size_t)1 * N * n + r * n + kk] = -2.0 * t1[kk];
-                    tg[(size_t)2 * N * n + r * n + kk] = -2.0 * t2[kk];
+                    const double m2n = -2.0 * occ.w[kk];
+                    tg[(size_t)0 * N * n + r * n + kk] = m2n * t0[kk];
+                    tg[(size_t)1 * N * n + r * n + kk] = m2n * t1[kk];
+                    tg[(size_t)2 * N * n + r * n + kk] = m2n * t2[kk];
                 }
             }
         }
@@ -219,13 +216,14 @@ __global__ __launch_bounds__(256) void k_adj_T(const double* __restrict__ rho_ro
     }
 }
 
-// Kbar^x_R = Cbar^x_R + Abar_R W^x + (Wt/2) Bbar^x_R + [a = b in occ] 2 Wbar^x
+// Kbar^x_R = Cbar^x_R + Abar_R W^x + (Wt/2) Bbar^x_R + [a = b in occ] 2 n_a Wbar^x
 //            + [b in occ] T^x[a][b] + [a in occ, a != b] T^x[b][a],   R = pair(a <= b)
 // (W, Wt from the per-point scalars S of the intermediates: S[0] = Wt/2, S[1..3] = W/2).
 // Written into Y slots 0..2 in place (Cbar there already).
 __global__ void k_adj_assemble(double* __restrict__ Y, size_t ystride, const double* __restrict__ S,
                                const double* __restrict__ T, const double* __restrict__ Wbar,
-                               const int* __restrict__ kidx, int rows, int ldP, int N, int nocc) {
+                               const int* __restrict__ kidx, const double* __restrict__ occw, int rows, int ldP,
+                               int N, int nocc) {
     const int Npair = N * (N + 1) / 2;
     const size_t n = (size_t)rows * Npair;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
@@ -242,7 +240,7 @@ __global__ void k_adj_assemble(double* __restrict__ Y, size_t ystride, const dou
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
             double v = Y[x * ystride + o] + ab * W[x] + hWt * Y[(4 + x) * ystride + o];
-            if (a == b && ka >= 0) v += 2.0 * Wbar[(size_t)g * 3 + x];
+            if (a == b && ka >= 0) v += 2.0 * occw[a] * Wbar[(size_t)g * 3 + x];
             if (kb >= 0) v += tg[(size_t)x * N * nocc + a * nocc + kb];
             if (ka >= 0 && a != b) v += tg[(size_t)x * N * nocc + b * nocc + ka];
             Y[x * ystride + o] = v;

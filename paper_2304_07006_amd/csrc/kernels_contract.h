@@ -13,10 +13,13 @@
 
 namespace xtc {
 
+// The orbitals of the reference density and their per-spin occupations:
+// gamma = sum_i w[i] |k[i]><k[i]| (w = 1: the closed-shell determinant).
 constexpr int kMaxOcc = 256;
 struct OccList {
     int32_t n;
     int32_t k[kMaxOcc];
+    double w[kMaxOcc];
 };
 
 // --------------------------------------------------------------------------
@@ -25,8 +28,9 @@ struct OccList {
 // point are gathered into LDS as [nocc][N][4]; each thread then owns 4x4
 // output blocks (r-block <= s-block) of the upper triangle and accumulates
 // Zt and Z over k with register blocking.
-// Per-point scalars S[g] = (sum_k rho_kk, sum_k K_kk (3), sum_k A_kk, sum_k B_kk (3))
-// feed the one-body reduction.
+// Every sum over k carries the occupation n_k of the reference density.
+// Per-point scalars S[g] = (sum_k n_k rho_kk, sum_k n_k K_kk (3), sum_k n_k A_kk,
+// sum_k n_k B_kk (3)) feed the one-body reduction.
 __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict__ rho_rows,
                                                        const double* __restrict__ K, int rows,
                                                        int ldP, int N, OccList occ,
@@ -54,7 +58,8 @@ __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict_
             double w0 = 0, w1 = 0, w2 = 0, wt = 0;
             for (int kk = 0; kk < n; ++kk) {           // every lane, same order
                 const d4 e = locc[kk * N + occ.k[kk]];
-                wt += e.x; w0 += e.y; w1 += e.z; w2 += e.w;
+                const double nk = occ.w[kk];
+                wt = fma(nk, e.x, wt); w0 = fma(nk, e.y, w0); w1 = fma(nk, e.z, w1); w2 = fma(nk, e.w, w2);
             }
             double a = 0, b0 = 0, b1 = 0, b2 = 0;
             for (int kk = lane; kk < n; kk += 64) {
@@ -63,11 +68,15 @@ __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict_
                 double zt = 0, z0 = 0, z1 = 0, z2 = 0;
                 for (int ll = 0; ll < n; ++ll) {
                     const d4 f = locc[ll * N + k];                  // (rho_kl, K_kl)
-                    zt += f.y * f.y + f.z * f.z + f.w * f.w;
-                    z0 += 2.0 * f.x * f.y; z1 += 2.0 * f.x * f.z; z2 += 2.0 * f.x * f.w;
+                    const double nl = occ.w[ll];
+                    zt = fma(nl, f.y * f.y + f.z * f.z + f.w * f.w, zt);
+                    z0 = fma(nl, 2.0 * f.x * f.y, z0); z1 = fma(nl, 2.0 * f.x * f.z, z1);
+                    z2 = fma(nl, 2.0 * f.x * f.w, z2);
                 }
-                a += 2.0 * (w0 * e.y + w1 * e.z + w2 * e.w) - zt;   // A_kk
-                b0 += wt * e.y - z0; b1 += wt * e.z - z1; b2 += wt * e.w - z2;   // B_kk
+                const double nk = occ.w[kk];
+                a = fma(nk, 2.0 * (w0 * e.y + w1 * e.z + w2 * e.w) - zt, a);   // n_k A_kk
+                b0 = fma(nk, wt * e.y - z0, b0); b1 = fma(nk, wt * e.z - z1, b1);
+                b2 = fma(nk, wt * e.w - z2, b2);                               // n_k B_kk
             }
 #pragma unroll
             for (int m = 32; m >= 1; m >>= 1) {
@@ -100,9 +109,10 @@ __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict_
             }
             for (int kk = 0; kk < n; ++kk) {
                 const d4* row = locc + kk * N;
+                const double nk = occ.w[kk];
                 d4 a[4], b[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) { a[i] = row[ri[i]]; b[i] = row[sj[i]]; }
+                for (int i = 0; i < 4; ++i) { a[i] = row[ri[i]]; b[i] = nk * row[sj[i]]; }
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -229,7 +239,7 @@ __global__ __launch_bounds__(256) void k_onebody_T1(const double* __restrict__ r
 }
 
 // One-body reduction, exchange term, partial over grid splits:
-//   E[split][p][q] = sum_{g in split} sum_k sum_c C_c[g][pair(p,k)] D_c[g][pair(k,q)]
+//   E[split][p][q] = sum_{g in split} sum_k n_k sum_c C_c[g][pair(p,k)] D_c[g][pair(k,q)]
 // Workgroup: a 64 x 64 block of (p,q), 4 x 4 per thread; the occupied columns
 // of C and rows of D for that block are staged in LDS per grid point.
 constexpr int kEBlk = 64;
@@ -263,7 +273,7 @@ __global__ __launch_bounds__(256) void k_onebody_E(const double* __restrict__ rh
                 const int k = occ.k[kk];
                 const int p = pb * kEBlk + j, q = qb * kEBlk + j;
                 cs[idx] = p < N ? Cg[pair_sym(p, k, N)] : 0.0;
-                ds[idx] = q < N ? Dg[pair_sym(k, q, N)] : 0.0;
+                ds[idx] = q < N ? occ.w[kk] * Dg[pair_sym(k, q, N)] : 0.0;
             }
             __syncthreads();
             for (int kk = 0; kk < n; ++kk) {
@@ -313,7 +323,7 @@ __global__ void k_onebody_accumulate(const double* __restrict__ T1, int nsplit_t
     h1acc[P] = accumulate ? h1acc[P] + v : v;
 }
 
-// h1[p][q] = h1acc[pair(p,q)] (symmetric bitwise); E0 = -(2/3) sum_k h1[k][k]
+// h1[p][q] = h1acc[pair(p,q)] (symmetric bitwise); E0 = -(2/3) sum_k n_k h1[k][k]
 // (Appendix B), summed in occ order by one thread.
 __global__ void k_onebody_finalize(const double* __restrict__ h1acc, int N, OccList occ,
                                    double* __restrict__ h1, double* __restrict__ E0) {
@@ -324,7 +334,7 @@ __global__ void k_onebody_finalize(const double* __restrict__ h1acc, int N, OccL
     }
     if (pq == 0) {
         double e = 0.0;
-        for (int kk = 0; kk < occ.n; ++kk) e += h1acc[pair_index(occ.k[kk], occ.k[kk], N)];
+        for (int kk = 0; kk < occ.n; ++kk) e = fma(occ.w[kk], h1acc[pair_index(occ.k[kk], occ.k[kk], N)], e);
         *E0 = -(2.0 / 3.0) * e;
     }
 }

@@ -18,7 +18,7 @@
 //   Mpart  [4*ceil(cap/kSegM)][ldL][ldL] f32  two-body partials    (prec != FP64)
 // and with XTC_WITH_BACKWARD in prec (the adjoint reuses M for Gbar):
 //   Kc [3][cap][ldP], Y [7][cap][ldP], T [cap][3][N][nocc], Wbar [cap][3],
-//   gpart [ceil(cap/32) * ngp/128][16], gacc [16], isocc [N], kidx [N]
+//   gpart [ceil(cap/32) * ngp/128][16], gacc [16], occw [N] f64, kidx [N]
 // ldL = ldP rounded up to 512.  The chunk capacity `cap` is the largest
 // multiple of 32 rows that fits in the bytes the caller passes, so every call
 // with the same ws_bytes agrees on it.
@@ -78,7 +78,7 @@ struct Layout {
     int N, Ng, nocc, ldP, ngp, Npair, prec;
     int form, ns, es, ldL, ldO, nOP, occNB, nsegK;
     bool bwd;
-    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, isocc, kidx, rhoR;
+    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, occw, kidx, rhoR;
     size_t fixed;        // bytes before S (plus the Mpart remainder reserve)
     size_t per_row;      // bytes per chunk row
     int cap;             // chunk rows that fit (multiple of kRowQuant)
@@ -137,7 +137,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.T1 = off;      off = align_up(off + (size_t)kT1Split * L.ldP * sizeof(double), kAlign);
     L.E = off;       off = align_up(off + (size_t)kESplitMax * L.N * L.N * sizeof(double), kAlign);
     L.gacc = off;    off = align_up(off + (L.bwd ? kGradMax * sizeof(double) : 0), kAlign);
-    L.isocc = off;   off = align_up(off + (L.bwd ? (size_t)L.N : 0), kAlign);
+    L.occw = off;    off = align_up(off + (L.bwd ? (size_t)L.N * sizeof(double) : 0), kAlign);
     L.kidx = off;    off = align_up(off + (L.bwd ? (size_t)L.N * sizeof(int) : 0), kAlign);
     L.rhoR = off;    off = align_up(off + (L.bwd && lp ? (size_t)L.ns * L.ngp * L.ldP * L.es : 0), kAlign);
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);   // one 32-row tile of partials
@@ -199,6 +199,7 @@ xtc_status check_problem(const xtc_problem* pb) {
         if (k < 0 || k >= pb->N) return fail(XTC_E_ARG, "occ[%d]=%d outside [0,N)", i, k);
         if (seen[k]) return fail(XTC_E_ARG, "occ[%d]=%d repeated", i, k);
         seen[k] = 1;
+        if (pb->occ_n && !std::isfinite(pb->occ_n[i])) return fail(XTC_E_ARG, "occ_n[%d] not finite", i);
     }
     if ((size_t)pb->nocc * pb->N * 4 * sizeof(double) > kLdsMax)
         return fail(XTC_E_UNSUPPORTED, "nocc*N=%d exceeds the on-chip staging of the intermediates",
@@ -262,7 +263,10 @@ xtc_status check_align(const void* p, const char* name) {
 OccList make_occ(const xtc_problem* pb) {
     OccList o{};
     o.n = pb->nocc;
-    for (int i = 0; i < pb->nocc; ++i) o.k[i] = pb->occ[i];
+    for (int i = 0; i < pb->nocc; ++i) {
+        o.k[i] = pb->occ[i];
+        o.w[i] = pb->occ_n ? pb->occ_n[i] : 1.0;
+    }
     return o;
 }
 
@@ -617,12 +621,12 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
     if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     const OccList occ = make_occ(pb);
-    hipLaunchKernelGGL(k_occ_flags, dim3((L.N + 255) / 256), dim3(256), 0, st, occ, L.N, at<unsigned char>(ws, L.isocc),
+    hipLaunchKernelGGL(k_occ_flags, dim3((L.N + 255) / 256), dim3(256), 0, st, occ, L.N, at<double>(ws, L.occw),
                        at<int>(ws, L.kidx));
     if ((s = launched("occ_flags")) != XTC_OK) return s;
     double* G = at<double>(ws, L.M);
     hipLaunchKernelGGL(k_make_gbar, dim3((L.ldP + 255) / 256, L.ldP), dim3(256), 0, st, gV2, gh1, gE0,
-                       at<unsigned char>(ws, L.isocc), L.N, L.ldP, G);
+                       at<double>(ws, L.occw), L.N, L.ldP, G);
     if ((s = launched("make_gbar")) != XTC_OK) return s;
     const size_t ystride = (size_t)L.cap * L.ldP;
     double* Kc = at<double>(ws, L.Kc);
@@ -658,7 +662,7 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
         const size_t nel = (size_t)rows * L.Npair;
         hipLaunchKernelGGL(k_adj_assemble, dim3((unsigned)std::min<size_t>((nel + 255) / 256, 16384)), dim3(256), 0, st,
                            Y, ystride, at<double>(ws, L.S), at<double>(ws, L.T), at<double>(ws, L.Wbar),
-                           at<int>(ws, L.kidx), rows, L.ldP, L.N, L.nocc);
+                           at<int>(ws, L.kidx), at<double>(ws, L.occw), rows, L.ldP, L.N, L.nocc);
         if ((s = launched("adj_assemble")) != XTC_OK) return s;
         const int n_it_pi = (rows + 31) / 32;
         int nblk_pi;

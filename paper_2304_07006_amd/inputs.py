@@ -88,6 +88,7 @@ class Problem:
     centres: np.ndarray  # [n_centres][3]
     jastrow: Jastrow
     meta: dict = field(default_factory=dict)
+    occ_n: np.ndarray | None = None   # per-spin occupations of occ (None: 1 each)
 
     @property
     def N(self) -> int:

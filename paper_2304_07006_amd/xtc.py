@@ -37,7 +37,8 @@ class XtcJastrow(ctypes.Structure):
 class XtcProblem(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("Ng", ctypes.c_int32), ("nocc", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("xyz", ctypes.c_void_p), ("w", ctypes.c_void_p),
-                ("phi", ctypes.c_void_p), ("occ", ctypes.POINTER(ctypes.c_int32))]
+                ("phi", ctypes.c_void_p), ("occ", ctypes.POINTER(ctypes.c_int32)),
+                ("occ_n", ctypes.POINTER(ctypes.c_double))]
 
 
 _SIGS = {
@@ -119,6 +120,7 @@ class DeviceProblem:
     phi: object
     occ_host: np.ndarray
     c: XtcProblem
+    occ_n_host: np.ndarray | None = None
 
     @property
     def N(self):
@@ -129,15 +131,21 @@ class DeviceProblem:
         return self.c.Ng
 
 
-def device_problem(xyz, w, phi, occ, device="cuda") -> DeviceProblem:
+def device_problem(xyz, w, phi, occ, device="cuda", occ_n=None) -> DeviceProblem:
+    """occ: orbitals of the reference density; occ_n: their per-spin
+    occupations (None: 1 each, the closed-shell determinant)."""
     import torch
     t_xyz = torch.as_tensor(np.ascontiguousarray(xyz, dtype=np.float64)).to(device)
     t_w = torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64)).to(device)
     t_phi = torch.as_tensor(np.ascontiguousarray(phi, dtype=np.float64)).to(device)
     occ_h = np.ascontiguousarray(occ, dtype=np.int32)
+    occ_n_h = None if occ_n is None else np.ascontiguousarray(occ_n, dtype=np.float64)
+    if occ_n_h is not None and occ_n_h.shape != occ_h.shape:
+        raise ValueError("occ_n must have one entry per occupied orbital")
     c = XtcProblem(int(phi.shape[0]), int(phi.shape[1]), int(len(occ_h)), 0, t_xyz.data_ptr(), t_w.data_ptr(),
-                   t_phi.data_ptr(), occ_h.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
-    return DeviceProblem(t_xyz, t_w, t_phi, occ_h, c)
+                   t_phi.data_ptr(), occ_h.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                   None if occ_n_h is None else occ_n_h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return DeviceProblem(t_xyz, t_w, t_phi, occ_h, c, occ_n_h)
 
 
 def _stream(stream=None):
@@ -250,7 +258,8 @@ class Pass:
 
 def forward(problem, prec="fp64", chunk_rows=None, device="cuda", jastrow=None):
     """V2, h1, E0 (torch tensors on the device) for an inputs.Problem."""
-    dp = device_problem(problem.xyz, problem.w, problem.phi, problem.occ, device)
+    dp = device_problem(problem.xyz, problem.w, problem.phi, problem.occ, device,
+                        getattr(problem, "occ_n", None))
     ps = Pass(dp, PRECISIONS[prec] if isinstance(prec, str) else prec, chunk_rows, device)
     V2, h1, E0 = ps.run(make_jastrow(jastrow or problem.jastrow))
     return V2, h1, E0

@@ -76,6 +76,16 @@ def test_bad_problem(lib, mut, expect):
     assert xtc.last_error()
 
 
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_bad_occupation_numbers(lib, bad):
+    c, keep = _problem(occ=(0, 1))
+    occ_n = np.array([1.0, bad])
+    c.occ_n = occ_n.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.xtc_workspace_size(ctypes.byref(c), 0, 50) == 0
+    assert _call_build(lib, c, _jas(), nbytes=1 << 30) == xtc.XTC_E_ARG
+    assert "occ_n" in xtc.last_error()
+
+
 def test_bad_jastrow_and_range(lib):
     c, keep = _problem()
     n = lib.xtc_workspace_size(ctypes.byref(c), 0, 50)

@@ -1,0 +1,119 @@
+"""GPU parity for references with occupation numbers (gamma = sum_k n_k |k><k|
+per spin): natural orbitals of a correlated density and the spin-averaged
+open-shell density, against the Appendix-B oracle with the same gamma."""
+import numpy as np
+import pytest
+
+from paper_2304_07006_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_ABS = 1e-11
+TOL_2BODY_LP, TOL_1BODY_LP, TOL_0BODY_LP = 1e-6, 1e-6, 1e-8
+
+
+def _note(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def _gamma(p):
+    g = np.zeros((p.N, p.N))
+    g[p.occ, p.occ] = p.occ_n
+    return g
+
+
+def _run(problem, prec="fp64", chunk_rows=None):
+    from paper_2304_07006_amd import xtc
+    V2, h1, E0 = xtc.forward(problem, prec=prec, chunk_rows=chunk_rows)
+    return V2.cpu().numpy(), h1.cpu().numpy(), float(E0.cpu().numpy()[0])
+
+
+def _natural(N=32, nact=10, Ng=2500, seed=41):
+    occ = inputs.random_occ(N, nact, seed=seed)
+    p = inputs.make_problem(N, nact, Ng, 2, "chain", "pade", seed=seed, occ=occ)
+    p.occ_n = inputs.natural_occupations(nact, seed)
+    return p
+
+
+def test_natural_occupations_fp64(torch_cuda):
+    from oracle import factorised as fb
+    p = _natural()
+    _note("case: N32 natural occupations (10 orbitals) fp64, chunk 900")
+    V2o, h1o, E0o = fb.closed_shell(p.xyz, p.w, p.phi, _gamma(p), p.jastrow)
+    V2, h1, E0 = _run(p, chunk_rows=900)
+    assert np.abs(V2 - V2o).max() < TOL_ABS
+    assert np.abs(h1 - h1o).max() < TOL_ABS
+    assert abs(E0 - E0o) < TOL_ABS
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "bf16x6"])
+def test_spin_averaged_open_shell(torch_cuda, prec):
+    """Spin-averaged density of a high-spin open-shell determinant: 3 doubly
+    and 2 singly occupied orbitals (n = 1, 1, 1, 1/2, 1/2), 16-term power Jastrow."""
+    from oracle import factorised as fb
+    k, n = inputs.sa_occupations(3, 2)
+    p = inputs.make_problem(24, 5, 1800, 6, "chain", "power16", seed=43, occ=k)
+    p.occ_n = n
+    _note(f"case: N24 SA open shell {prec}")
+    V2o, h1o, E0o = fb.closed_shell(p.xyz, p.w, p.phi, _gamma(p), p.jastrow)
+    V2, h1, E0 = _run(p, prec=prec, chunk_rows=700)
+    e = (np.abs(V2 - V2o).max(), np.abs(h1 - h1o).max(), abs(E0 - E0o))
+    _note(f"  max |err| V2 {e[0]:.2e} h1 {e[1]:.2e} E0 {e[2]:.2e}")
+    if prec == "fp64":
+        assert max(e) < TOL_ABS
+    else:
+        assert e[0] < TOL_2BODY_LP and e[1] < TOL_1BODY_LP and e[2] < TOL_0BODY_LP
+
+
+def test_unit_occupations_are_the_determinant(torch_cuda):
+    """occ_n = 1 reproduces the closed-shell determinant bitwise."""
+    p = inputs.make_problem(24, 4, 1200, 2, "chain", "pade", seed=44)
+    _note("case: N24 unit occupations vs none, fp64 and bf16x3")
+    for prec in ("fp64", "bf16x3"):
+        p.occ_n = None
+        a = _run(p, prec=prec, chunk_rows=500)
+        p.occ_n = np.ones(p.nocc)
+        b = _run(p, prec=prec, chunk_rows=500)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_mid_natural_occupations_reduced_forms(torch_cuda):
+    """N=64 on a 3001-point grid, 12 natural orbitals, split-BF16 against the oracle."""
+    from oracle import factorised as fb
+    p = inputs.make_workload("N64-occ8-Ng50k", Ng=3001)
+    p.occ = np.arange(12, dtype=np.int32)
+    p.occ_n = inputs.natural_occupations(12, 45)
+    _note("case: N64 Ng3001 natural occupations bf16x3")
+    V2o, h1o, E0o = fb.closed_shell(p.xyz, p.w, p.phi, _gamma(p), p.jastrow)
+    V2, h1, E0 = _run(p, prec="bf16x3", chunk_rows=1000)
+    e = (np.abs(V2 - V2o).max(), np.abs(h1 - h1o).max(), abs(E0 - E0o))
+    _note(f"  max |err| V2 {e[0]:.2e} h1 {e[1]:.2e} E0 {e[2]:.2e}")
+    assert e[0] < TOL_2BODY_LP and e[1] < TOL_1BODY_LP and e[2] < TOL_0BODY_LP
+
+
+def test_gradient_with_occupations(torch_cuda):
+    """Adjoint with occupation numbers against the oracle's exact gradient."""
+    from oracle import gradient as og
+    from paper_2304_07006_amd import xtc
+    torch = torch_cuda
+    occ = inputs.random_occ(12, 4, seed=46)
+    p = inputs.make_problem(12, 4, 900, 3, "chain", "power16", seed=46, occ=occ)
+    p.occ_n = np.array([1.0, 0.93, 0.5, 0.04])
+    coef = np.array(p.jastrow.coef)
+    D, G = inputs.loss_weights(12, 46)
+    _note("case: backward N12 occupations (1, .93, .5, .04)")
+    go = og.exact_gradient(p.xyz, p.w, p.phi, _gamma(p), coef, D, G)
+    dp = xtc.device_problem(p.xyz, p.w, p.phi, p.occ, occ_n=p.occ_n)
+    gg = xtc.backward(dp, list(coef), torch.as_tensor(G).cuda(), torch.as_tensor(D).cuda(), 1.0, "fp64", 256)
+    gg = gg.cpu().numpy()
+    scale = np.abs(go).max()
+    _note(f"  max |dg| {np.abs(gg - go).max():.3e}  scale {scale:.3e}")
+    assert np.abs(gg - go).max() < 1e-10 * max(1.0, scale)
