@@ -121,10 +121,33 @@ def f_kbuild(N, rows, Ng):
     return 6 * rows * Ng * (N * (N + 1) // 2)
 
 
+def apply_density(problem, spec):
+    """Reference density of the workload: 'closed' (the closed-shell determinant
+    of the workload), 'sa:ND,NS' (spin-averaged open shell, ND doubly and NS
+    singly occupied orbitals) or 'natural:NACT' (NACT natural orbitals with
+    correlated occupation numbers).  Returns a short label."""
+    import numpy as np
+    from paper_2304_07006_amd import inputs
+    if spec == "closed":
+        return "closed-shell determinant"
+    kind, _, arg = spec.partition(":")
+    if kind == "sa":
+        nd, ns = (int(x) for x in arg.split(","))
+        problem.occ, problem.occ_n = inputs.sa_occupations(nd, ns)
+        return f"spin-averaged open shell ({nd} doubly, {ns} singly occupied)"
+    if kind == "natural":
+        nact = int(arg)
+        problem.occ = np.arange(nact, dtype=np.int32)
+        problem.occ_n = inputs.natural_occupations(nact, 2000)
+        return f"{nact} natural orbitals with correlated occupations"
+    raise SystemExit(f"unknown --density {spec}")
+
+
 def run_gpu(problem, prec, steps, warmup, chunk):
     import torch
     from paper_2304_07006_amd import xtc
-    dp = xtc.device_problem(problem.xyz, problem.w, problem.phi, problem.occ)
+    dp = xtc.device_problem(problem.xyz, problem.w, problem.phi, problem.occ,
+                            occ_n=getattr(problem, "occ_n", None))
     ps = xtc.Pass(dp, xtc.PRECISIONS[prec], chunk)
     jas = xtc.make_jastrow(problem.jastrow)
     stream = torch.cuda.current_stream()
@@ -208,6 +231,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=None,
                     help="grid rows per chunk (default: Ng/10 for FP64, Ng/20 for the reduced forms: equal launches)")
     ap.add_argument("--cpu-rows", type=int, default=300, help="grid points of the CPU oracle sample (0: skip)")
+    ap.add_argument("--density", default="closed",
+                    help="reference density: closed | sa:ND,NS | natural:NACT (see apply_density)")
     ap.add_argument("--probe", action="store_true",
                     help="counter pass: one 1 GiB device copy (calibration) and one K-build launch, no JSON")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -231,6 +256,8 @@ def main():
         sys.exit(1)
     wl = inputs.WORKLOADS[args.workload]
     problem = inputs.make_workload(args.workload)
+    density = apply_density(problem, args.density)
+    nref = len(problem.occ)
     chunk = args.chunk or default_chunk(wl.Ng, args.prec)
     if args.probe:
         probe(problem, args.prec, chunk)
@@ -238,7 +265,7 @@ def main():
     print(f"[bench] {args.workload} prec={args.prec} chunk={chunk} warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
     r = run_gpu(problem, args.prec, args.steps, args.warmup, chunk)
-    F = f_alg(wl.N, wl.nocc, wl.Ng)
+    F = f_alg(wl.N, nref, wl.Ng)
     forms = {args.prec: {"s_per_step": r["sec"], "gflops": F / r["sec"] / 1e9}}
     if args.compare != "none" and args.compare != args.prec:
         cchunk = default_chunk(wl.Ng, args.compare)
@@ -266,7 +293,7 @@ def main():
     print(f"[bench] step {r['sec']:.3f} s; K build {nl} launches, avg {tot_t / nl * 1e3:.1f} ms, "
           f"{achieved:.1f} TFLOP/s", file=sys.stderr, flush=True)
     cpu = None
-    if args.cpu_rows > 0:
+    if args.cpu_rows > 0 and args.density == "closed":
         print(f"[bench] CPU oracle sample: {args.cpu_rows} grid points", file=sys.stderr, flush=True)
         cpu = cpu_baseline(args.workload, args.cpu_rows)
     out = {
@@ -282,8 +309,8 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[args.prec],
         "data": "synthetic",
-        "config": {"workload": args.workload, "N": wl.N, "nocc": wl.nocc, "Ng": wl.Ng, "prec": args.prec,
-                   "chunk_rows": chunk, "jastrow": wl.jastrow_kind, "F_alg_flop": F,
+        "config": {"workload": args.workload, "N": wl.N, "nocc": nref, "Ng": wl.Ng, "prec": args.prec,
+                   "chunk_rows": chunk, "jastrow": wl.jastrow_kind, "density": density, "F_alg_flop": F,
                    "workspace_bytes": r["ws_bytes"]},
         "roofline": {"bound": "mfma", "kernel": "xtc_build_K", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,

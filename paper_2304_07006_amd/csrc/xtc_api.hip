@@ -92,16 +92,19 @@ int form_of(int prec) {
 }
 
 
-// 16-column blocks per wave of the FP64 occupied-block kernel: the count in
-// [1, 8] that pads nOP least (ties: more blocks, fewer workgroup columns).
+// 16-column blocks per wave of the FP64 occupied-block kernel, in [1, 7]
+// (8 needs more than 256 registers):
+// the count minimising padded columns x (1 + 1/(2 nb)), i.e. the MFMA work
+// plus the FP64 generation of the d tile, which each wave repeats for its
+// nb blocks (measured at 136 pairs: 3 blocks < 5 < 4 < 6 in time).
 int occ_blocks(int nOP) {
-    int best = 4;
-    size_t best_cols = align_up((size_t)nOP, 64);
-    for (int nb = 1; nb <= 8; ++nb) {
-        const size_t cols = align_up((size_t)nOP, (size_t)16 * nb);
-        if (cols < best_cols || (cols == best_cols && nb > best)) {
+    int best = 1;
+    double best_cost = 1e300;
+    for (int nb = 1; nb <= 7; ++nb) {
+        const double cost = (double)align_up((size_t)nOP, (size_t)16 * nb) * (1.0 + 0.5 / nb);
+        if (cost < best_cost) {
             best = nb;
-            best_cols = cols;
+            best_cost = cost;
         }
     }
     return best;
@@ -349,8 +352,7 @@ void launch_build_occ(const Layout& L, int g0, int rows, int n_rt, int nseg, int
         case 4: return launch_build_occ_nb<KIND, 4>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
         case 5: return launch_build_occ_nb<KIND, 5>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
         case 6: return launch_build_occ_nb<KIND, 6>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
-        case 7: return launch_build_occ_nb<KIND, 7>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
-        default: return launch_build_occ_nb<KIND, 8>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
+        default: return launch_build_occ_nb<KIND, 7>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
     }
 }
 
