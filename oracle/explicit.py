@@ -188,6 +188,30 @@ def tier_a_density(xyz, w, phi, gamma, jas):
     return dict(L_so=L, gamma_so=g, dU_so=dU, dh_so=dh, E0=E0, V2=V2, h1=dh[:N, :N].copy())
 
 
+def tier_a_open_shell(xyz, w, phi, occ_a, occ_b, jas):
+    """Tier A for an open-shell determinant: alpha orbitals occ_a, beta occ_b
+    (same spatial orbitals), on the explicit spin-orbital L.  Spin blocks
+    V2[s][t][p,q,r,u] = Delta U_so[(p s),(r t),(q s),(u t)], h1[s] the
+    (s, s) block of Delta h_so, and the zero-body term."""
+    N = phi.shape[0]
+    V = grid_intermediate(xyz, w, phi, jas)
+    L = spin_orbital_L(L_spatial(xyz, w, phi, jas, V))
+    g = np.zeros((2 * N, 2 * N))
+    for k in occ_a:
+        g[k, k] = 1.0
+    for k in occ_b:
+        g[N + k, N + k] = 1.0
+    dU = delta_U_so(L, g)
+    dh = delta_h_so_from_L(L, g)
+    E0 = zero_body_so(L, g)
+    sl = (slice(0, N), slice(N, 2 * N))
+    V2 = [[np.ascontiguousarray(dU[sl[s], sl[t], sl[s], sl[t]].transpose(0, 2, 1, 3)) for t in range(2)]
+          for s in range(2)]
+    h1 = [dh[sl[s], sl[s]].copy() for s in range(2)]
+    occ_so = [int(k) for k in occ_a] + [N + int(k) for k in occ_b]
+    return dict(L_so=L, gamma_so=g, dU_so=dU, dh_so=dh, E0=E0, V2=V2, h1=h1, occ_so=occ_so)
+
+
 # ---------------------------------------------------------------- step 6 --
 def _apply(det: int, creators, annihilators):
     """Apply a^P1 a^P2 ... a_Qk ... a_Q1 (creators listed left to right,

@@ -76,6 +76,56 @@ def closed_shell(xyz, w, phi, gamma, jas, block=512, grad=None, return_f=False):
     return V2, h1, E0
 
 
+def intermediates_spin(rho, K, g_tau, g_tot):
+    """Appendix A (restricted open shell) intermediates of spin tau:
+    W = V_t^u sum_rho gamma^rho, W~ = rho_t^u sum_rho gamma^rho (total density, no
+    factor two), X^tau, Y^tau, Z~^tau, Z^tau with the density of spin tau."""
+    W = np.einsum("xitu,tu->xi", K, g_tot)
+    X = np.einsum("xits,tu->xius", K, g_tau)
+    Zt = np.einsum("xiru,xius->irs", K, X)
+    A = np.einsum("xi,xirs->irs", W, K) - Zt
+    Wt = np.einsum("itu,tu->i", rho, g_tot)
+    Y = np.einsum("xiru,tu->xirt", K, g_tau)
+    Z = np.einsum("iru,xius->xirs", rho, X) + np.einsum("xirt,its->xirs", Y, rho)
+    B = 0.5 * Wt[None, :, None, None] * K - Z
+    return A, B
+
+
+def open_shell(xyz, w, phi, gamma_a, gamma_b, jas, block=512, grad=None):
+    """Restricted open-shell working equations (Appendix A): same spatial
+    orbitals and Jastrow for both spins, spin-specific densities.
+
+    Returns V2[s][t] [N]^4 for (s, t) in {a, b}^2 (V2[s][t][p,q,r,s'] =
+    [Delta U_pr^qs']^{st}), h1[s] [N][N] and E0, with
+      [Delta U]^{st}[pq, rs] = -(f^t(pq, rs) + f^s(rs, pq)),
+      f^t(pq, rs) = sum_i rho_pq A^t_rs + V_pq . B^t_rs,
+      [Delta h]^s = -1/2 (sum_t [Delta U_pr^qs]^{st} g^t_rs - [Delta U_pr^sq]^{ss} g^s_rs),
+      E0 = -1/3 sum_s [Delta h]^s . g^s."""
+    N, Ng = phi.shape
+    ga, gb = _as_gamma(gamma_a, N), _as_gamma(gamma_b, N)
+    gs = (ga, gb)
+    gtot = ga + gb
+    f = [np.zeros((N * N, N * N)), np.zeros((N * N, N * N))]
+    for i0 in range(0, Ng, block):
+        rows = slice(i0, min(Ng, i0 + block))
+        K = grid_K(xyz, w, phi, jas, rows, grad)
+        rho = w[rows, None, None] * phi[:, rows].T[:, :, None] * phi[:, rows].T[:, None, :]
+        nb = rho.shape[0]
+        for t in range(2):
+            A, B = intermediates_spin(rho, K, gs[t], gtot)
+            f[t] += rho.reshape(nb, -1).T @ A.reshape(nb, -1)
+            for x in range(3):
+                f[t] += K[x].reshape(nb, -1).T @ B[x].reshape(nb, -1)
+    V2 = [[-(f[t] + f[s].T).reshape(N, N, N, N) for t in range(2)] for s in range(2)]
+    h1 = []
+    for s in range(2):
+        h = sum(np.einsum("pqrs,rs->pq", V2[s][t], gs[t]) for t in range(2))
+        h = h - np.einsum("psrq,rs->pq", V2[s][s], gs[s])
+        h1.append(-0.5 * h)
+    E0 = -sum(float(np.einsum("pq,pq->", h1[s], gs[s])) for s in range(2)) / 3.0
+    return V2, h1, E0
+
+
 def one_body_from_V2(V2, gamma):
     """Appendix B: Delta h_p^q = -1/2 (2 Delta U_pr^qs g^r_s - Delta U_pr^sq g^r_s),
     with Delta U_pr^qs = V2[p,q,r,s] and Delta U_pr^sq = V2[p,s,r,q]."""

@@ -182,6 +182,56 @@ def test_two_body_term_is_linear_in_the_density():
     assert np.abs(c - (0.3 * a + 0.7 * b)).max() < 1e-15
 
 
+@pytest.fixture(scope="module")
+def open_shell(tiny):
+    occ_a, occ_b = [0, 1, 2], [0, 1]
+    A = ex.tier_a_open_shell(tiny.xyz, tiny.w, tiny.phi, occ_a, occ_b, tiny.jastrow)
+    ga, gb = np.zeros((tiny.N, tiny.N)), np.zeros((tiny.N, tiny.N))
+    ga[occ_a, occ_a] = 1.0
+    gb[occ_b, occ_b] = 1.0
+    B = fb.open_shell(tiny.xyz, tiny.w, tiny.phi, ga, gb, tiny.jastrow)
+    return A, B
+
+
+def test_open_shell_appendix_a_equals_tier_a(open_shell):
+    """Appendix A (restricted open shell) against eq. dU / tcmf:1el and the
+    determinant zero-body term on the explicit spin-orbital L."""
+    A, (V2, h1, E0) = open_shell
+    for s in range(2):
+        for t in range(2):
+            assert np.abs(V2[s][t] - A["V2"][s][t]).max() < 1e-16
+        assert np.abs(h1[s] - A["h1"][s]).max() < 1e-16
+    assert abs(E0 - A["E0"]) < 1e-16
+    assert np.abs(V2[0][0] - V2[1][1]).max() > 1e-4        # the spin blocks do differ
+
+
+def test_open_shell_determinant_brute_force(open_shell):
+    A, _ = open_shell
+    res = ex.determinant_check(A["L_so"], A["dU_so"], A["dh_so"], A["E0"], A["occ_so"])
+    for side in ("ket", "bra"):
+        for lvl in (0, 1, 2):
+            assert res[side][lvl] < 1e-15, (side, lvl, res[side][lvl])
+        assert res[side][3] > 1e-7
+
+
+def test_open_shell_closed_limit_and_spin_swap(tiny):
+    g = np.zeros((tiny.N, tiny.N))
+    g[tiny.occ, tiny.occ] = 1.0
+    V2c, h1c, E0c = fb.closed_shell(tiny.xyz, tiny.w, tiny.phi, g, tiny.jastrow)
+    V2, h1, E0 = fb.open_shell(tiny.xyz, tiny.w, tiny.phi, g, g, tiny.jastrow)
+    for s in range(2):
+        assert np.abs(h1[s] - h1c).max() < 1e-17
+        for t in range(2):
+            assert np.abs(V2[s][t] - V2c).max() < 1e-17
+    assert abs(E0 - E0c) < 1e-16
+    ga, gb = _random_density(tiny.N, 7), _random_density(tiny.N, 8)
+    a = fb.open_shell(tiny.xyz, tiny.w, tiny.phi, ga, gb, tiny.jastrow)
+    b = fb.open_shell(tiny.xyz, tiny.w, tiny.phi, gb, ga, tiny.jastrow)
+    assert np.abs(a[0][0][1] - b[0][1][0]).max() < 1e-16 and np.abs(a[1][0] - b[1][1]).max() < 1e-16
+    assert np.abs(a[0][0][1] - a[0][1][0].transpose(2, 3, 0, 1)).max() < 1e-17
+    assert abs(a[2] - b[2]) < 1e-15
+
+
 def test_spin_blocks(tiny, tierA):
     N = tiny.N
     dU = tierA["dU_so"]
