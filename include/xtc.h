@@ -105,7 +105,22 @@ typedef struct {
  * then in that basis.
  *   xyz [Ng][3] bohr, w [Ng], phi [N][Ng] (orthonormal under w: not checked),
  *   occ [nocc] HOST int32, distinct, in [0,N);
- *   occ_n [nocc] HOST double, finite, or NULL. */
+ *   occ_n [nocc] HOST double, finite, or NULL.
+ *
+ * Open shell (restricted open-shell working equations, Appendix A): with
+ * occ_n_beta != NULL the alpha and beta densities differ,
+ *   gamma^a = sum_i occ_n[i] |occ[i]><occ[i]|,  gamma^b = sum_i occ_n_beta[i] |occ[i]><occ[i]|
+ * (same spatial orbitals and Jastrow for both spins; list every orbital that
+ * either spin occupies, with 0 where one spin leaves it empty).  The outputs
+ * are then spin-resolved:
+ *   V2 [3][N][N][N][N]: blocks [Delta U]^{aa}, [Delta U]^{ab}, [Delta U]^{bb}
+ *      (V2[1][p][q][r][s] = [Delta U_pr^qs]^{ab}: pq alpha, rs beta; the
+ *      (b, a) block is V2[1][r][s][p][q]),
+ *   h1 [2][N][N]: [Delta h]^a, [Delta h]^b,
+ *   E0 = -1/3 sum_s [Delta h]^s . gamma^s.
+ * Intermediates W and W~ use the total density, Z~ and Z that of each spin;
+ * the two-body GEMM runs once per spin.  xtc_backward supports the closed
+ * shell only (XTC_E_UNSUPPORTED here). */
 typedef struct {
     int32_t N;
     int32_t Ng;
@@ -116,6 +131,7 @@ typedef struct {
     const double *phi;
     const int32_t *occ;      /* HOST */
     const double *occ_n;     /* HOST, or NULL (all 1) */
+    const double *occ_n_beta;  /* HOST, or NULL (closed shell / spin-averaged) */
 } xtc_problem;
 
 /* Padded leading dimension of pair-indexed arrays: Npair rounded up to 128. */

@@ -13,13 +13,16 @@
 
 namespace xtc {
 
-// The orbitals of the reference density and their per-spin occupations:
-// gamma = sum_i w[i] |k[i]><k[i]| (w = 1: the closed-shell determinant).
-constexpr int kMaxOcc = 256;
+// The orbitals of the reference density with the occupations of one spin
+// channel, w[i] (gamma^s = sum_i w[i] |k[i]><k[i]|), and of both spins
+// together, wt[i] (closed shell: wt = 2 w).  128 entries cover every problem
+// the on-chip staging of the intermediates admits (nocc * N <= 5120).
+constexpr int kMaxOcc = 128;
 struct OccList {
     int32_t n;
     int32_t k[kMaxOcc];
     double w[kMaxOcc];
+    double wt[kMaxOcc];
 };
 
 // --------------------------------------------------------------------------
@@ -28,9 +31,10 @@ struct OccList {
 // point are gathered into LDS as [nocc][N][4]; each thread then owns 4x4
 // output blocks (r-block <= s-block) of the upper triangle and accumulates
 // Zt and Z over k with register blocking.
-// Every sum over k carries the occupation n_k of the reference density.
-// Per-point scalars S[g] = (sum_k n_k rho_kk, sum_k n_k K_kk (3), sum_k n_k A_kk,
-// sum_k n_k B_kk (3)) feed the one-body reduction.
+// One spin channel s per launch: Z~ and Z carry the occupations n_k of that
+// spin, W and W~ those of the total density.  Per-point scalars
+// S[g] = (W~/2, W/2 (3), sum_k n_k A_kk, sum_k n_k B_kk (3)) feed the one-body
+// reduction.
 __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict__ rho_rows,
                                                        const double* __restrict__ K, int rows,
                                                        int ldP, int N, OccList occ,
@@ -55,12 +59,16 @@ __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict_
             // wave 0: W, Wt and the per-point scalars of the one-body reduction,
             // lanes over occupied k, then a fixed-pattern butterfly sum.
             const int lane = threadIdx.x;
+            // W = sum_k wt_k K_kk and W~ = sum_k wt_k rho_kk over the total
+            // density (Appendix A; 2 gamma for the closed shell, Appendix B);
+            // w0..w2 = W/2, wt = W~/2
             double w0 = 0, w1 = 0, w2 = 0, wt = 0;
             for (int kk = 0; kk < n; ++kk) {           // every lane, same order
                 const d4 e = locc[kk * N + occ.k[kk]];
-                const double nk = occ.w[kk];
+                const double nk = occ.wt[kk];
                 wt = fma(nk, e.x, wt); w0 = fma(nk, e.y, w0); w1 = fma(nk, e.z, w1); w2 = fma(nk, e.w, w2);
             }
+            wt *= 0.5; w0 *= 0.5; w1 *= 0.5; w2 *= 0.5;
             double a = 0, b0 = 0, b1 = 0, b2 = 0;
             for (int kk = lane; kk < n; kk += 64) {
                 const int k = occ.k[kk];
@@ -198,10 +206,12 @@ __global__ __launch_bounds__(256) void k_gemm2b_f64(const double* __restrict__ r
         }
 }
 
-// V2[p][q][r][s] = -(M[P][R] + M[R][P]); all eight index symmetries hold
-// bitwise because both terms are read for every ordering.
-__global__ __launch_bounds__(256) void k_finalize_V2(const double* __restrict__ M, int ldP, int N,
-                                                     double* __restrict__ V2) {
+// V2[p][q][r][s] = -(M2[P][R] + M1[R][P]).  Closed shell: M1 = M2 = M, and all
+// eight index symmetries hold bitwise because both terms are read for every
+// ordering.  Open shell, spins (s, t) of (pq, rs): M2 = M^t, M1 = M^s
+// (Appendix A, [Delta U]^{st}[pq, rs] = -(f^t(pq, rs) + f^s(rs, pq))).
+__global__ __launch_bounds__(256) void k_finalize_V2(const double* __restrict__ M1, const double* __restrict__ M2,
+                                                     int ldP, int N, double* __restrict__ V2) {
     const int p = blockIdx.y, q = blockIdx.z;
     const int pq = p * N + q;
     const int P = pair_sym(p, q, N);
@@ -209,18 +219,21 @@ __global__ __launch_bounds__(256) void k_finalize_V2(const double* __restrict__ 
     for (int rs = blockIdx.x * blockDim.x + threadIdx.x; rs < NN; rs += gridDim.x * blockDim.x) {
         const int r = rs / N, s = rs % N;
         const int R = pair_sym(r, s, N);
-        V2[(size_t)pq * NN + rs] = -(M[(size_t)P * ldP + R] + M[(size_t)R * ldP + P]);
+        V2[(size_t)pq * NN + rs] = -(M2[(size_t)P * ldP + R] + M1[(size_t)R * ldP + P]);
     }
 }
 
 // --------------------------------------------------------------------------
 // One-body reduction, term 1 (diagonal-sum terms), partial over grid splits:
 //   T1[split][P] = sum_{g in split} rho_P a + K_P.b + rb A_P + kb.B_P
+// with rb = W~/2, kb = W/2 and (a, b) = sum_k n_k (A_kk, B_kk) of this channel,
+// or, when S2 (the other spin channel) is given, the mean over both channels
+// (Appendix A: the sum over the spin tau of [Delta U]^{s tau} gamma^tau).
 __global__ __launch_bounds__(256) void k_onebody_T1(const double* __restrict__ rho_rows,
                                                     const double* __restrict__ K,
                                                     const double* __restrict__ D, size_t dstride,
-                                                    const double* __restrict__ S, int rows, int ldP,
-                                                    int Npair, double* __restrict__ T1) {
+                                                    const double* __restrict__ S, const double* __restrict__ S2,
+                                                    int rows, int ldP, int Npair, double* __restrict__ T1) {
     const int P = blockIdx.x * blockDim.x + threadIdx.x;
     const int split = blockIdx.y, nsplit = gridDim.y;
     if (P >= Npair) return;
@@ -229,9 +242,15 @@ __global__ __launch_bounds__(256) void k_onebody_T1(const double* __restrict__ r
     double acc = 0.0;
     for (int g = gb; g < ge; ++g) {
         const double* s = S + (size_t)g * 8;
+        double ab[4] = {s[4], s[5], s[6], s[7]};
+        if (S2) {
+            const double* s2 = S2 + (size_t)g * 8;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ab[i] = 0.5 * (ab[i] + s2[4 + i]);
+        }
         const size_t o = (size_t)g * ldP + P;
-        acc = fma(rho_rows[o], s[4], acc);
-        acc = fma(K[o], s[5], fma(K[kstride + o], s[6], fma(K[2 * kstride + o], s[7], acc)));
+        acc = fma(rho_rows[o], ab[0], acc);
+        acc = fma(K[o], ab[1], fma(K[kstride + o], ab[2], fma(K[2 * kstride + o], ab[3], acc)));
         acc = fma(D[o], s[0], acc);
         acc = fma(D[dstride + o], s[1], fma(D[2 * dstride + o], s[2], fma(D[3 * dstride + o], s[3], acc)));
     }
@@ -323,19 +342,28 @@ __global__ void k_onebody_accumulate(const double* __restrict__ T1, int nsplit_t
     h1acc[P] = accumulate ? h1acc[P] + v : v;
 }
 
-// h1[p][q] = h1acc[pair(p,q)] (symmetric bitwise); E0 = -(2/3) sum_k n_k h1[k][k]
-// (Appendix B), summed in occ order by one thread.
-__global__ void k_onebody_finalize(const double* __restrict__ h1acc, int N, OccList occ,
-                                   double* __restrict__ h1, double* __restrict__ E0) {
+// h1[p][q] = h1acc[pair(p,q)] (symmetric bitwise) for one spin channel, or for
+// both (h1acc2, h1 + N^2) in the open-shell form.  E0 = -(2/3) sum_k n_k h1[k][k]
+// (Appendix B), or -(1/3) sum_s sum_k n^s_k h1^s[k][k] (Appendix A), summed in
+// occ order by one thread.
+__global__ void k_onebody_finalize(const double* __restrict__ h1acc, const double* __restrict__ h1acc2, int N,
+                                   OccList occ, OccList occ2, double* __restrict__ h1, double* __restrict__ E0) {
     const int pq = blockIdx.x * blockDim.x + threadIdx.x;
     if (pq < N * N) {
         const int p = pq / N, q = pq % N;
         h1[pq] = h1acc[pair_sym(p, q, N)];
+        if (h1acc2) h1[N * N + pq] = h1acc2[pair_sym(p, q, N)];
     }
     if (pq == 0) {
         double e = 0.0;
         for (int kk = 0; kk < occ.n; ++kk) e = fma(occ.w[kk], h1acc[pair_index(occ.k[kk], occ.k[kk], N)], e);
-        *E0 = -(2.0 / 3.0) * e;
+        if (h1acc2) {
+            for (int kk = 0; kk < occ2.n; ++kk)
+                e = fma(occ2.w[kk], h1acc2[pair_index(occ2.k[kk], occ2.k[kk], N)], e);
+            *E0 = -(1.0 / 3.0) * e;
+        } else {
+            *E0 = -(2.0 / 3.0) * e;
+        }
     }
 }
 

@@ -76,7 +76,7 @@ constexpr int kOccSeg = 4;      // segments of the FP64 occupied-block sum over 
 
 struct Layout {
     int N, Ng, nocc, ldP, ngp, Npair, prec;
-    int form, ns, es, ldL, ldO, nOP, occNB, nsegK;
+    int form, ns, es, ldL, ldO, nOP, occNB, nsegK, nspin;
     bool bwd;
     size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, occw, kidx, rhoR;
     size_t fixed;        // bytes before S (plus the Mpart remainder reserve)
@@ -115,6 +115,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.N = pb->N;
     L.Ng = pb->Ng;
     L.nocc = pb->nocc;
+    L.nspin = pb->occ_n_beta ? 2 : 1;
     L.prec = prec;
     L.ldP = pair_ld(pb->N);
     L.Npair = pb->N * (pb->N + 1) / 2;
@@ -135,8 +136,8 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.rho_lp = off;  off = align_up(off + (lp ? (size_t)L.ns * L.ngp * L.ldL * L.es : 0), kAlign);
     L.rho_occ = off; off = align_up(off + (lp ? (size_t)L.ngp * L.ldO * sizeof(double) : 0), kAlign);
     L.colmap = off;  off = align_up(off + (lp ? (size_t)L.ldO * sizeof(int) : 0), kAlign);
-    L.M = off;       off = align_up(off + (size_t)L.ldP * L.ldP * sizeof(double), kAlign);
-    L.h1acc = off;   off = align_up(off + (size_t)L.ldP * sizeof(double), kAlign);
+    L.M = off;       off = align_up(off + (size_t)L.nspin * L.ldP * L.ldP * sizeof(double), kAlign);
+    L.h1acc = off;   off = align_up(off + (size_t)L.nspin * L.ldP * sizeof(double), kAlign);
     L.T1 = off;      off = align_up(off + (size_t)kT1Split * L.ldP * sizeof(double), kAlign);
     L.E = off;       off = align_up(off + (size_t)kESplitMax * L.N * L.N * sizeof(double), kAlign);
     L.gacc = off;    off = align_up(off + (L.bwd ? kGradMax * sizeof(double) : 0), kAlign);
@@ -146,7 +147,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);   // one 32-row tile of partials
     const size_t mslab = (size_t)4 * L.ldL * L.ldL * sizeof(float);       // one partial per component
     L.fixed = off + (lp ? mslab : 0) + (L.bwd ? gslab : 0) + 14 * kAlign;
-    L.per_row = (size_t)8 * sizeof(double) + (size_t)4 * L.ldP * sizeof(double);
+    L.per_row = (size_t)L.nspin * (8 * sizeof(double) + (size_t)4 * L.ldP * sizeof(double));
     if (lp) L.per_row += (size_t)kOccSeg * 3 * L.ldO * sizeof(double);
     if (lp)
         L.per_row += (size_t)L.nsegK * 3 * L.ldL * sizeof(float) + (size_t)8 * L.ns * L.ldL * L.es +
@@ -169,8 +170,8 @@ void place_chunk(Layout& L, size_t bytes) {
     L.nsegM = lp ? 4 * (int)((cap + kSegM - 1) / kSegM) : 0;
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);
     size_t off = L.fixed - 14 * kAlign - (lp ? (size_t)4 * L.ldL * L.ldL * sizeof(float) : 0) - (L.bwd ? gslab : 0);
-    L.S = off;       off = align_up(off + (size_t)cap * 8 * sizeof(double), kAlign);
-    L.D = off;       off = align_up(off + (size_t)4 * cap * L.ldP * sizeof(double), kAlign);
+    L.S = off;       off = align_up(off + (size_t)L.nspin * cap * 8 * sizeof(double), kAlign);
+    L.D = off;       off = align_up(off + (size_t)L.nspin * 4 * cap * L.ldP * sizeof(double), kAlign);
     L.Kpart = off;   off = align_up(off + (lp ? (size_t)L.nsegK * 3 * cap * L.ldL * sizeof(float) : 0), kAlign);
     L.CDlp = off;    off = align_up(off + (lp ? (size_t)8 * L.ns * cap * L.ldL * L.es : 0), kAlign);
     L.Mpart = off;   off = align_up(off + (lp ? (size_t)L.nsegM * L.ldL * L.ldL * sizeof(float) : 0), kAlign);
@@ -203,6 +204,8 @@ xtc_status check_problem(const xtc_problem* pb) {
         if (seen[k]) return fail(XTC_E_ARG, "occ[%d]=%d repeated", i, k);
         seen[k] = 1;
         if (pb->occ_n && !std::isfinite(pb->occ_n[i])) return fail(XTC_E_ARG, "occ_n[%d] not finite", i);
+        if (pb->occ_n_beta && !std::isfinite(pb->occ_n_beta[i]))
+            return fail(XTC_E_ARG, "occ_n_beta[%d] not finite", i);
     }
     if ((size_t)pb->nocc * pb->N * 4 * sizeof(double) > kLdsMax)
         return fail(XTC_E_UNSUPPORTED, "nocc*N=%d exceeds the on-chip staging of the intermediates",
@@ -263,12 +266,22 @@ xtc_status check_align(const void* p, const char* name) {
     return XTC_OK;
 }
 
-OccList make_occ(const xtc_problem* pb) {
+// Occupations of spin channel `spin` (0 alpha, 1 beta) and of the total
+// density.  Closed shell (occ_n_beta NULL): one channel, total = 2 n.
+OccList make_occ(const xtc_problem* pb, int spin = 0) {
     OccList o{};
     o.n = pb->nocc;
     for (int i = 0; i < pb->nocc; ++i) {
+        const double na = pb->occ_n ? pb->occ_n[i] : 1.0;
         o.k[i] = pb->occ[i];
-        o.w[i] = pb->occ_n ? pb->occ_n[i] : 1.0;
+        if (pb->occ_n_beta) {
+            const double nb = pb->occ_n_beta[i];
+            o.w[i] = spin == 0 ? na : nb;
+            o.wt[i] = na + nb;
+        } else {
+            o.w[i] = na;
+            o.wt[i] = 2.0 * na;
+        }
     }
     return o;
 }
@@ -302,9 +315,14 @@ xtc_status run_intermediates(const Layout& L, const xtc_problem* pb, const doubl
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return fail(XTC_E_HIP, "intermediates LDS attribute: %s", hipGetErrorString(e));
     }
-    hipLaunchKernelGGL(k_intermediates, dim3(blocks), dim3(256), lds, st, rho_rows, K, rows, L.ldP, L.N,
-                       make_occ(pb), at<double>(ws, L.D), dstride, at<double>(ws, L.S));
-    return launched("intermediates");
+    for (int sp = 0; sp < L.nspin; ++sp) {
+        hipLaunchKernelGGL(k_intermediates, dim3(blocks), dim3(256), lds, st, rho_rows, K, rows, L.ldP, L.N,
+                           make_occ(pb, sp), at<double>(ws, L.D) + (size_t)sp * 4 * dstride, dstride,
+                           at<double>(ws, L.S) + (size_t)sp * L.cap * 8);
+        xtc_status s;
+        if ((s = launched("intermediates")) != XTC_OK) return s;
+    }
+    return XTC_OK;
 }
 
 // ---------------------------------------------------------------- reduced precision
@@ -397,13 +415,9 @@ xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int acc
     const size_t comp_bytes = (size_t)L.ns * split_stride * L.es;
     char* cd = at<char>(ws, L.CDlp);
     const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
-    const double* D = at<double>(ws, L.D);
     for (int c = 0; c < 4; ++c) {
         const double* src = c == 0 ? rho_rows : K + (size_t)(c - 1) * rows * L.ldP;
         if ((s = pack_any(L.form, src, rows, L.ldP, L.ldP, n8, L.ldL, cd + c * comp_bytes, split_stride, st)) != XTC_OK)
-            return s;
-        if ((s = pack_any(L.form, D + (size_t)c * L.cap * L.ldP, rows, L.ldP, L.ldP, n8, L.ldL,
-                          cd + (4 + c) * comp_bytes, split_stride, st)) != XTC_OK)
             return s;
     }
     const int n_pt = L.ldL / 128, n_rt = L.ldL / 256;
@@ -412,21 +426,31 @@ xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int acc
     const void* C = cd;
     const void* Dl = cd + 4 * comp_bytes;
     float* part = at<float>(ws, L.Mpart);
-    if (L.form == 1)
-        hipLaunchKernelGGL((k_gemm2b_lp<1>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt, kSegM,
-                           nseg_r, part);
-    else if (L.form == 3)
-        hipLaunchKernelGGL((k_gemm2b_lp<3>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt, kSegM,
-                           nseg_r, part);
-    else
-        hipLaunchKernelGGL((k_gemm2b_lp<6>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt, kSegM,
-                           nseg_r, part);
-    if ((s = launched("gemm_2body_lp")) != XTC_OK) return s;
-    const size_t n = (size_t)L.ldP * L.ldP;
-    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
-    hipLaunchKernelGGL(k_reduce_M, dim3(blocks), dim3(256), 0, st, part, 4 * nseg_r, L.ldL, L.ldP, at<double>(ws, L.M),
-                       accumulate);
-    return launched("reduce_M");
+    // one spin channel at a time: its D into the operand buffer, GEMM, reduction into M^s
+    for (int sp = 0; sp < L.nspin; ++sp) {
+        const double* D = at<double>(ws, L.D) + (size_t)sp * 4 * L.cap * L.ldP;
+        for (int c = 0; c < 4; ++c) {
+            if ((s = pack_any(L.form, D + (size_t)c * L.cap * L.ldP, rows, L.ldP, L.ldP, n8, L.ldL,
+                              cd + (4 + c) * comp_bytes, split_stride, st)) != XTC_OK)
+                return s;
+        }
+        if (L.form == 1)
+            hipLaunchKernelGGL((k_gemm2b_lp<1>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt,
+                               kSegM, nseg_r, part);
+        else if (L.form == 3)
+            hipLaunchKernelGGL((k_gemm2b_lp<3>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt,
+                               kSegM, nseg_r, part);
+        else
+            hipLaunchKernelGGL((k_gemm2b_lp<6>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt,
+                               kSegM, nseg_r, part);
+        if ((s = launched("gemm_2body_lp")) != XTC_OK) return s;
+        const size_t n = (size_t)L.ldP * L.ldP;
+        const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
+        hipLaunchKernelGGL(k_reduce_M, dim3(blocks), dim3(256), 0, st, part, 4 * nseg_r, L.ldL, L.ldP,
+                           at<double>(ws, L.M) + (size_t)sp * L.ldP * L.ldP, accumulate);
+        if ((s = launched("reduce_M")) != XTC_OK) return s;
+    }
+    return XTC_OK;
 }
 
 xtc_status split_rows_any(int form, const double* src, size_t n, void* dst, size_t split_stride, hipStream_t st) {
@@ -548,16 +572,29 @@ xtc_status xtc_contract_2body(const xtc_problem* pb, const double* K, int32_t g0
     } else {
         const int n_t = L.ldP / 128;
         const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
-        hipLaunchKernelGGL(k_gemm2b_f64, dim3(n_t * n_t), dim3(256), 0, st, rho_rows, K, at<double>(ws, L.D),
-                           (size_t)L.cap * L.ldP, rows, L.ldP, n_t, at<double>(ws, L.M),
-                           (flags & XTC_RESET) ? 0 : 1);
-        if ((s = launched("gemm_2body")) != XTC_OK) return s;
+        const size_t dstride = (size_t)L.cap * L.ldP;
+        for (int sp = 0; sp < L.nspin; ++sp) {
+            hipLaunchKernelGGL(k_gemm2b_f64, dim3(n_t * n_t), dim3(256), 0, st, rho_rows, K,
+                               at<double>(ws, L.D) + (size_t)sp * 4 * dstride, dstride, rows, L.ldP, n_t,
+                               at<double>(ws, L.M) + (size_t)sp * L.ldP * L.ldP, (flags & XTC_RESET) ? 0 : 1);
+            if ((s = launched("gemm_2body")) != XTC_OK) return s;
+        }
     }
     if (flags & XTC_FINALIZE) {
         const int NN = L.N * L.N;
-        hipLaunchKernelGGL(k_finalize_V2, dim3((NN + 255) / 256, L.N, L.N), dim3(256), 0, st, at<double>(ws, L.M),
-                           L.ldP, L.N, V2);
+        const size_t N4 = (size_t)NN * NN;
+        const double* Ma = at<double>(ws, L.M);
+        const double* Mb = Ma + (size_t)L.ldP * L.ldP;
+        const dim3 grid((NN + 255) / 256, L.N, L.N);
+        // closed shell: V2 = block (a, a); open shell: blocks (a, a), (a, b), (b, b)
+        hipLaunchKernelGGL(k_finalize_V2, grid, dim3(256), 0, st, Ma, Ma, L.ldP, L.N, V2);
         if ((s = launched("finalize_V2")) != XTC_OK) return s;
+        if (L.nspin == 2) {
+            hipLaunchKernelGGL(k_finalize_V2, grid, dim3(256), 0, st, Ma, Mb, L.ldP, L.N, V2 + N4);
+            if ((s = launched("finalize_V2")) != XTC_OK) return s;
+            hipLaunchKernelGGL(k_finalize_V2, grid, dim3(256), 0, st, Mb, Mb, L.ldP, L.N, V2 + 2 * N4);
+            if ((s = launched("finalize_V2")) != XTC_OK) return s;
+        }
     }
     return XTC_OK;
 }
@@ -582,25 +619,32 @@ xtc_status xtc_contract_1body_0body(const xtc_problem* pb, const double* K, int3
     const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
     const size_t dstride = (size_t)L.cap * L.ldP;
     const int nsplit_t1 = std::min(kT1Split, rows);
-    hipLaunchKernelGGL(k_onebody_T1, dim3((L.Npair + 255) / 256, nsplit_t1), dim3(256), 0, st, rho_rows, K,
-                       at<double>(ws, L.D), dstride, at<double>(ws, L.S), rows, L.ldP, L.Npair,
-                       at<double>(ws, L.T1));
-    if ((s = launched("onebody_T1")) != XTC_OK) return s;
     const int nbk = (L.N + kEBlk - 1) / kEBlk;
     int nsplit_e = std::max(1, std::min(kESplitMax, 1024 / (nbk * nbk)));
     nsplit_e = std::min(nsplit_e, rows);
     const size_t lds = (size_t)2 * L.nocc * kEBlk * sizeof(double);
-    hipLaunchKernelGGL(k_onebody_E, dim3(nbk * nbk, nsplit_e), dim3(256), lds, st, rho_rows, K,
-                       at<double>(ws, L.D), dstride, rows, L.ldP, L.N, make_occ(pb), at<double>(ws, L.E));
-    if ((s = launched("onebody_E")) != XTC_OK) return s;
-    hipLaunchKernelGGL(k_onebody_accumulate, dim3((L.Npair + 255) / 256), dim3(256), 0, st, at<double>(ws, L.T1),
-                       nsplit_t1, at<double>(ws, L.E), nsplit_e, L.ldP, L.N, at<double>(ws, L.h1acc),
-                       (flags & XTC_RESET) ? 0 : 1);
-    if ((s = launched("onebody_accumulate")) != XTC_OK) return s;
+    const double* S = at<double>(ws, L.S);
+    const size_t sstride = (size_t)L.cap * 8;
+    // per spin channel (T1 and E are scratch of one channel at a time)
+    for (int sp = 0; sp < L.nspin; ++sp) {
+        const double* Ds = at<double>(ws, L.D) + (size_t)sp * 4 * dstride;
+        hipLaunchKernelGGL(k_onebody_T1, dim3((L.Npair + 255) / 256, nsplit_t1), dim3(256), 0, st, rho_rows, K, Ds,
+                           dstride, S + sp * sstride, L.nspin == 2 ? S + (1 - sp) * sstride : nullptr, rows, L.ldP,
+                           L.Npair, at<double>(ws, L.T1));
+        if ((s = launched("onebody_T1")) != XTC_OK) return s;
+        hipLaunchKernelGGL(k_onebody_E, dim3(nbk * nbk, nsplit_e), dim3(256), lds, st, rho_rows, K, Ds, dstride,
+                           rows, L.ldP, L.N, make_occ(pb, sp), at<double>(ws, L.E));
+        if ((s = launched("onebody_E")) != XTC_OK) return s;
+        hipLaunchKernelGGL(k_onebody_accumulate, dim3((L.Npair + 255) / 256), dim3(256), 0, st,
+                           at<double>(ws, L.T1), nsplit_t1, at<double>(ws, L.E), nsplit_e, L.ldP, L.N,
+                           at<double>(ws, L.h1acc) + (size_t)sp * L.ldP, (flags & XTC_RESET) ? 0 : 1);
+        if ((s = launched("onebody_accumulate")) != XTC_OK) return s;
+    }
     if (flags & XTC_FINALIZE) {
         const int NN = L.N * L.N;
-        hipLaunchKernelGGL(k_onebody_finalize, dim3((NN + 255) / 256), dim3(256), 0, st, at<double>(ws, L.h1acc),
-                           L.N, make_occ(pb), h1, E0);
+        const double* ha = at<double>(ws, L.h1acc);
+        hipLaunchKernelGGL(k_onebody_finalize, dim3((NN + 255) / 256), dim3(256), 0, st, ha,
+                           L.nspin == 2 ? ha + L.ldP : nullptr, L.N, make_occ(pb, 0), make_occ(pb, 1), h1, E0);
         if ((s = launched("onebody_finalize")) != XTC_OK) return s;
     }
     return XTC_OK;
@@ -618,6 +662,7 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
     if (!gcoef) return fail(XTC_E_ARG, "gcoef is NULL");
     if (!std::isfinite(gE0)) return fail(XTC_E_ARG, "gE0 not finite");
     if (pb->nocc > kMaxOccAdj) return fail(XTC_E_UNSUPPORTED, "the adjoint supports nocc <= %d", kMaxOccAdj);
+    if (pb->occ_n_beta) return fail(XTC_E_UNSUPPORTED, "the adjoint covers the closed-shell equations only");
     Layout L = make_layout(pb, prec);
     place_chunk(L, ws_bytes);
     if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;

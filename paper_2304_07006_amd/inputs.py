@@ -88,7 +88,8 @@ class Problem:
     centres: np.ndarray  # [n_centres][3]
     jastrow: Jastrow
     meta: dict = field(default_factory=dict)
-    occ_n: np.ndarray | None = None   # per-spin occupations of occ (None: 1 each)
+    occ_n: np.ndarray | None = None       # per-spin occupations of occ (None: 1 each)
+    occ_n_beta: np.ndarray | None = None  # open shell: beta occupations (occ_n is then alpha)
 
     @property
     def N(self) -> int:
@@ -228,6 +229,16 @@ def sa_occupations(n_double: int, n_single: int) -> tuple[np.ndarray, np.ndarray
     k = np.arange(n_double + n_single, dtype=np.int32)
     n = np.concatenate([np.ones(n_double), np.full(n_single, 0.5)])
     return k, n
+
+
+def open_shell_occupations(n_double: int, n_single: int) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """High-spin open-shell determinant in its orbital basis: n_double doubly
+    occupied orbitals then n_single alpha-only ones.  Returns (orbitals,
+    alpha occupations, beta occupations)."""
+    k = np.arange(n_double + n_single, dtype=np.int32)
+    na = np.ones(n_double + n_single)
+    nb = np.concatenate([np.ones(n_double), np.zeros(n_single)])
+    return k, na, nb
 
 
 def natural_occupations(nact: int, seed: int) -> np.ndarray:

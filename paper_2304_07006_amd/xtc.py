@@ -38,7 +38,7 @@ class XtcProblem(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("Ng", ctypes.c_int32), ("nocc", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("xyz", ctypes.c_void_p), ("w", ctypes.c_void_p),
                 ("phi", ctypes.c_void_p), ("occ", ctypes.POINTER(ctypes.c_int32)),
-                ("occ_n", ctypes.POINTER(ctypes.c_double))]
+                ("occ_n", ctypes.POINTER(ctypes.c_double)), ("occ_n_beta", ctypes.POINTER(ctypes.c_double))]
 
 
 _SIGS = {
@@ -121,6 +121,11 @@ class DeviceProblem:
     occ_host: np.ndarray
     c: XtcProblem
     occ_n_host: np.ndarray | None = None
+    occ_n_beta_host: np.ndarray | None = None
+
+    @property
+    def open_shell(self):
+        return self.occ_n_beta_host is not None
 
     @property
     def N(self):
@@ -131,21 +136,25 @@ class DeviceProblem:
         return self.c.Ng
 
 
-def device_problem(xyz, w, phi, occ, device="cuda", occ_n=None) -> DeviceProblem:
+def device_problem(xyz, w, phi, occ, device="cuda", occ_n=None, occ_n_beta=None) -> DeviceProblem:
     """occ: orbitals of the reference density; occ_n: their per-spin
-    occupations (None: 1 each, the closed-shell determinant)."""
+    occupations (None: 1 each, the closed-shell determinant); occ_n_beta: the
+    beta occupations of an open-shell reference (then occ_n is alpha)."""
     import torch
     t_xyz = torch.as_tensor(np.ascontiguousarray(xyz, dtype=np.float64)).to(device)
     t_w = torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64)).to(device)
     t_phi = torch.as_tensor(np.ascontiguousarray(phi, dtype=np.float64)).to(device)
     occ_h = np.ascontiguousarray(occ, dtype=np.int32)
     occ_n_h = None if occ_n is None else np.ascontiguousarray(occ_n, dtype=np.float64)
-    if occ_n_h is not None and occ_n_h.shape != occ_h.shape:
-        raise ValueError("occ_n must have one entry per occupied orbital")
+    occ_b_h = None if occ_n_beta is None else np.ascontiguousarray(occ_n_beta, dtype=np.float64)
+    for a in (occ_n_h, occ_b_h):
+        if a is not None and a.shape != occ_h.shape:
+            raise ValueError("occupations must have one entry per listed orbital")
+    dptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     c = XtcProblem(int(phi.shape[0]), int(phi.shape[1]), int(len(occ_h)), 0, t_xyz.data_ptr(), t_w.data_ptr(),
-                   t_phi.data_ptr(), occ_h.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                   None if occ_n_h is None else occ_n_h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
-    return DeviceProblem(t_xyz, t_w, t_phi, occ_h, c, occ_n_h)
+                   t_phi.data_ptr(), occ_h.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), dptr(occ_n_h),
+                   dptr(occ_b_h))
+    return DeviceProblem(t_xyz, t_w, t_phi, occ_h, c, occ_n_h, occ_b_h)
 
 
 def _stream(stream=None):
@@ -228,8 +237,10 @@ class Pass:
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.K = torch.empty((3, self.chunk, self.ldP), dtype=torch.float64, device=device)
         N = dp.N
-        self.V2 = torch.empty((N, N, N, N), dtype=torch.float64, device=device)
-        self.h1 = torch.empty((N, N), dtype=torch.float64, device=device)
+        # open shell: spin blocks (aa, ab, bb) of V2 and (a, b) of h1
+        ns = (3, 2) if dp.open_shell else None
+        self.V2 = torch.empty(((ns[0],) if ns else ()) + (N, N, N, N), dtype=torch.float64, device=device)
+        self.h1 = torch.empty(((ns[1],) if ns else ()) + (N, N), dtype=torch.float64, device=device)
         self.E0 = torch.empty((1,), dtype=torch.float64, device=device)
 
     def chunks(self):
@@ -259,7 +270,7 @@ class Pass:
 def forward(problem, prec="fp64", chunk_rows=None, device="cuda", jastrow=None):
     """V2, h1, E0 (torch tensors on the device) for an inputs.Problem."""
     dp = device_problem(problem.xyz, problem.w, problem.phi, problem.occ, device,
-                        getattr(problem, "occ_n", None))
+                        getattr(problem, "occ_n", None), getattr(problem, "occ_n_beta", None))
     ps = Pass(dp, PRECISIONS[prec] if isinstance(prec, str) else prec, chunk_rows, device)
     V2, h1, E0 = ps.run(make_jastrow(jastrow or problem.jastrow))
     return V2, h1, E0

@@ -86,6 +86,20 @@ def test_bad_occupation_numbers(lib, bad):
     assert "occ_n" in xtc.last_error()
 
 
+def test_bad_beta_occupations_and_open_shell_adjoint(lib):
+    c, keep = _problem(occ=(0, 1))
+    nb = np.array([1.0, float("nan")])
+    c.occ_n_beta = nb.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.xtc_workspace_size(ctypes.byref(c), 0, 50) == 0
+    assert "occ_n_beta" in xtc.last_error()
+    nb[1] = 0.0
+    j = _jas(kind=1, ncoef=2)
+    j.coef[0], j.coef[1] = 0.5, 0.1
+    st = lib.xtc_backward(ctypes.byref(c), ctypes.byref(j), xtc.XTC_WITH_BACKWARD, None, None, 1.0,
+                          ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000), 1 << 30, None)
+    assert st == xtc.XTC_E_UNSUPPORTED and "closed-shell" in xtc.last_error()
+
+
 def test_bad_jastrow_and_range(lib):
     c, keep = _problem()
     n = lib.xtc_workspace_size(ctypes.byref(c), 0, 50)

@@ -1,6 +1,8 @@
-"""GPU parity for references with occupation numbers (gamma = sum_k n_k |k><k|
-per spin): natural orbitals of a correlated density and the spin-averaged
-open-shell density, against the Appendix-B oracle with the same gamma."""
+"""GPU parity for other reference densities: occupation numbers (gamma = sum_k
+n_k |k><k| per spin; natural orbitals of a correlated density, the
+spin-averaged open-shell density) against the Appendix-B oracle, and the
+spin-resolved open-shell equations against Appendix A and the explicit
+spin-orbital L."""
 import numpy as np
 import pytest
 
@@ -117,3 +119,68 @@ def test_gradient_with_occupations(torch_cuda):
     scale = np.abs(go).max()
     _note(f"  max |dg| {np.abs(gg - go).max():.3e}  scale {scale:.3e}")
     assert np.abs(gg - go).max() < 1e-10 * max(1.0, scale)
+
+
+def _gammas(p):
+    ga, gb = np.zeros((p.N, p.N)), np.zeros((p.N, p.N))
+    ga[p.occ, p.occ] = p.occ_n
+    gb[p.occ, p.occ] = p.occ_n_beta
+    return ga, gb
+
+
+def _run_open(problem, prec="fp64", chunk_rows=None):
+    V2, h1, E0 = _run(problem, prec, chunk_rows)
+    assert V2.shape == (3,) + (problem.N,) * 4 and h1.shape == (2, problem.N, problem.N)
+    return V2, h1, E0
+
+
+def _compare_open(V2, h1, E0, ref):
+    V2o, h1o, E0o = ref
+    blocks = [V2o[0][0], V2o[0][1], V2o[1][1]]
+    e = (max(np.abs(V2[i] - blocks[i]).max() for i in range(3)),
+         max(np.abs(h1[s] - h1o[s]).max() for s in range(2)), abs(E0 - E0o))
+    _note(f"  max |err| V2 {e[0]:.2e} h1 {e[1]:.2e} E0 {e[2]:.2e}")
+    return e
+
+
+def test_open_shell_tiny_against_explicit_L(torch_cuda):
+    """Open-shell determinant (3 alpha, 2 beta), N=8, against the explicit
+    spin-orbital L (eq. dU, eq. tcmf:1el, determinant zero-body term)."""
+    from oracle import explicit as ex
+    p = inputs.make_workload("N8-occ2-Ng2k")
+    p.occ, p.occ_n, p.occ_n_beta = inputs.open_shell_occupations(2, 1)
+    _note("case: N8 open shell (2 doubly, 1 singly occupied) fp64 vs explicit L")
+    A = ex.tier_a_open_shell(p.xyz, p.w, p.phi, [0, 1, 2], [0, 1], p.jastrow)
+    V2, h1, E0 = _run_open(p, chunk_rows=700)
+    e = _compare_open(V2, h1, E0, (A["V2"], A["h1"], A["E0"]))
+    assert max(e) < TOL_ABS
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_open_shell_against_appendix_a(torch_cuda, prec):
+    from oracle import factorised as fb
+    k, na, nb = inputs.open_shell_occupations(3, 2)
+    p = inputs.make_problem(24, 5, 1800, 6, "chain", "power16", seed=47, occ=k)
+    p.occ_n, p.occ_n_beta = na, nb
+    _note(f"case: N24 open shell (3 doubly, 2 singly) {prec}")
+    ref = fb.open_shell(p.xyz, p.w, p.phi, *_gammas(p), p.jastrow)
+    V2, h1, E0 = _run_open(p, prec=prec, chunk_rows=700)
+    e = _compare_open(V2, h1, E0, ref)
+    if prec == "fp64":
+        assert max(e) < TOL_ABS
+    else:
+        assert e[0] < TOL_2BODY_LP and e[1] < TOL_1BODY_LP and e[2] < TOL_0BODY_LP
+
+
+def test_open_shell_with_equal_spins_is_the_closed_shell(torch_cuda):
+    p = inputs.make_problem(16, 3, 1000, 2, "chain", "pade", seed=48)
+    _note("case: N16 open-shell form with equal spin densities vs closed shell")
+    p.occ_n = np.array([1.0, 0.9, 0.3])
+    V2c, h1c, E0c = _run(p, chunk_rows=400)
+    p.occ_n_beta = p.occ_n.copy()
+    V2, h1, E0 = _run_open(p, chunk_rows=400)
+    for i in range(3):
+        assert np.abs(V2[i] - V2c).max() < 1e-15
+    for s in range(2):
+        assert np.abs(h1[s] - h1c).max() < 1e-15
+    assert abs(E0 - E0c) < 1e-14
