@@ -112,9 +112,11 @@ def traffic_from(fetch_dir, write_dir, workload, prec, chunk):
     print(json.dumps(rec[f"{workload}/{prec}/{chunk}"], indent=1))
 
 
-def f_alg(N, n, Ng):
+def f_alg(N, n, Ng, nspin=1):
+    """Algorithmic flops; the spin-resolved open-shell equations need the
+    intermediates and the two-body contraction once per spin."""
     P = N * (N + 1) // 2
-    return 6 * Ng * Ng * P + 8 * Ng * P * P + (18 * n + 10) * Ng * P
+    return 6 * Ng * Ng * P + nspin * (8 * Ng * P * P + (18 * n + 10) * Ng * P)
 
 
 def f_kbuild(N, rows, Ng):
@@ -124,8 +126,9 @@ def f_kbuild(N, rows, Ng):
 def apply_density(problem, spec):
     """Reference density of the workload: 'closed' (the closed-shell determinant
     of the workload), 'sa:ND,NS' (spin-averaged open shell, ND doubly and NS
-    singly occupied orbitals) or 'natural:NACT' (NACT natural orbitals with
-    correlated occupation numbers).  Returns a short label."""
+    singly occupied orbitals), 'open:ND,NS' (the same determinant with the
+    spin-resolved open-shell equations) or 'natural:NACT' (NACT natural
+    orbitals with correlated occupation numbers).  Returns a short label."""
     import numpy as np
     from paper_2304_07006_amd import inputs
     if spec == "closed":
@@ -135,6 +138,10 @@ def apply_density(problem, spec):
         nd, ns = (int(x) for x in arg.split(","))
         problem.occ, problem.occ_n = inputs.sa_occupations(nd, ns)
         return f"spin-averaged open shell ({nd} doubly, {ns} singly occupied)"
+    if kind == "open":
+        nd, ns = (int(x) for x in arg.split(","))
+        problem.occ, problem.occ_n, problem.occ_n_beta = inputs.open_shell_occupations(nd, ns)
+        return f"open shell, spin-resolved ({nd} doubly, {ns} singly occupied)"
     if kind == "natural":
         nact = int(arg)
         problem.occ = np.arange(nact, dtype=np.int32)
@@ -265,7 +272,8 @@ def main():
     print(f"[bench] {args.workload} prec={args.prec} chunk={chunk} warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
     r = run_gpu(problem, args.prec, args.steps, args.warmup, chunk)
-    F = f_alg(wl.N, nref, wl.Ng)
+    nspin = 2 if getattr(problem, "occ_n_beta", None) is not None else 1
+    F = f_alg(wl.N, nref, wl.Ng, nspin)
     forms = {args.prec: {"s_per_step": r["sec"], "gflops": F / r["sec"] / 1e9}}
     if args.compare != "none" and args.compare != args.prec:
         cchunk = default_chunk(wl.Ng, args.compare)
