@@ -126,6 +126,23 @@ def open_shell(xyz, w, phi, gamma_a, gamma_b, jas, block=512, grad=None):
     return V2, h1, E0
 
 
+def frozen_core(V2, h1, E0, core, active):
+    """Closed-shell frozen-core folding of a zero-, one- and two-body operator
+    (the xTC-FC scheme of the results section: the corrections are computed
+    with all electrons, then the standard frozen-core equations are applied),
+    with V2[p,q,r,s] = (pq|rs) and a doubly occupied core:
+      E  = E0 + 2 sum_c h1[c,c] + sum_{c,d} (2 (cc|dd) - (cd|dc)),
+      h[p,q] = h1[p,q] + sum_c (2 (pq|cc) - (pc|cq)),   p, q active,
+      V = V2 restricted to the active orbitals."""
+    c = np.asarray(core, dtype=int)
+    a = np.asarray(active, dtype=int)
+    E = E0 + 2.0 * float(np.trace(h1[np.ix_(c, c)]))
+    E += float(np.sum(2.0 * np.einsum("ccdd->cd", V2[np.ix_(c, c, c, c)]) - np.einsum("cddc->cd", V2[np.ix_(c, c, c, c)])))
+    h = h1[np.ix_(a, a)].copy()
+    h += 2.0 * np.einsum("pqcc->pq", V2[np.ix_(a, a, c, c)]) - np.einsum("pccq->pq", V2[np.ix_(a, c, c, a)])
+    return V2[np.ix_(a, a, a, a)].copy(), h, E
+
+
 def one_body_from_V2(V2, gamma):
     """Appendix B: Delta h_p^q = -1/2 (2 Delta U_pr^qs g^r_s - Delta U_pr^sq g^r_s),
     with Delta U_pr^qs = V2[p,q,r,s] and Delta U_pr^sq = V2[p,s,r,q]."""

@@ -232,6 +232,56 @@ def test_open_shell_closed_limit_and_spin_swap(tiny):
     assert abs(a[2] - b[2]) < 1e-15
 
 
+def test_frozen_core_folding_is_exact_in_determinant_space(tiny, tierA):
+    """Between determinants that share a doubly occupied core, the operator
+    E0 + dh + dU equals the folded active-space operator E + h + V (frozen-core
+    equations), element by element: checked on every pair of two-electron
+    active-space determinants (and a planted error is caught)."""
+    N = tiny.N
+    core, act = [0], list(range(1, N))
+    V2f, hf, Ef = fb.frozen_core(tierA["V2"], tierA["h1"], tierA["E0"], core, act)
+
+    def so_ops(V2, h1):
+        n = V2.shape[0]
+        dU = np.zeros((2 * n,) * 4)
+        dh = np.zeros((2 * n, 2 * n))
+        for s1 in (0, 1):
+            dh[s1 * n:(s1 + 1) * n, s1 * n:(s1 + 1) * n] = h1
+            for s2 in (0, 1):
+                a, b = s1 * n, s2 * n
+                dU[a:a + n, b:b + n, a:a + n, b:b + n] = V2.transpose(0, 2, 1, 3)
+        return dU, dh
+
+    dU, dh = so_ops(tierA["V2"], tierA["h1"])
+    dUa, dha = so_ops(V2f, hf)
+    na = len(act)
+    full_of = {}                                     # active spin-orbital -> full spin-orbital
+    for s1 in (0, 1):
+        for i, p in enumerate(act):
+            full_of[s1 * na + i] = s1 * N + p
+    core_bits = sum(1 << (s1 * N + c) for s1 in (0, 1) for c in core)
+    dets = [(1 << x) | (1 << y) for x, y in itertools.combinations(range(2 * na), 2)]
+    to_full = lambda d: core_bits | sum(1 << full_of[k] for k in range(2 * na) if (d >> k) & 1)
+    worst = 0.0
+    for bra in dets[::3]:
+        ket_f = ex._folded_on(to_full(bra), tierA["E0"], dh, dU, 2 * N)
+        ket_a = ex._folded_on(bra, Ef, dha, dUa, 2 * na)
+        for d, v in ket_a.items():
+            worst = max(worst, abs(ket_f.get(to_full(d), 0.0) - v))
+        for d, v in ket_f.items():
+            if d & core_bits == core_bits:
+                back = sum(1 << k for k in range(2 * na) if (d >> full_of[k]) & 1)
+                worst = max(worst, abs(ket_a.get(back, 0.0) - v))
+    assert worst < 1e-15
+    # the core terms matter: dropping the exchange part breaks the identity
+    bad = hf + 0.5 * np.einsum("pccq->pq", tierA["V2"][np.ix_(act, core, core, act)])
+    _, dhb = so_ops(V2f, bad)
+    d0 = dets[0]
+    a = ex._folded_on(d0, Ef, dhb, dUa, 2 * na)
+    f = ex._folded_on(to_full(d0), tierA["E0"], dh, dU, 2 * N)
+    assert max(abs(f.get(to_full(k), 0.0) - v) for k, v in a.items()) > 1e-6
+
+
 def test_spin_blocks(tiny, tierA):
     N = tiny.N
     dU = tierA["dU_so"]
