@@ -6,8 +6,14 @@ At coincident points (r12 == 0 exactly) the paper is silent; the gradient of
 an isotropic function is taken as zero there (it is bounded by max u').
 
 Supported forms (parameters are plain Python values):
-* Pade:  u = r / (2 (1 + b r)),        u' = 1 / (2 (1 + b r)^2)
-* power: u = sum_k c_k t^k, t = r/(1+r), u' = sum_k k c_k t^(k-1) / (1 + r)^2
+* Pade:  u = r / (2 (1 + b r)),        u' = 1 / (2 (1 + b r)^2),  u'' = -b / (1 + b r)^3
+* power: u = sum_k c_k t^k, t = r/(1+r), u' = sum_k k c_k t^(k-1) / (1 + r)^2,
+         u'' = sum_k k (k-1) c_k t^(k-2) / (1 + r)^4 - 2 sum_k k c_k t^(k-1) / (1 + r)^3
+
+The two-body TC integrals (Theory, definition of K) need the scalar
+  S(r1, r2) = laplacian_1 u + |grad_1 u|^2 = u'' + 2 u'/r + u'^2,
+which is symmetric in the two points; at coincident points it is taken as
+zero, like the gradient (the 2u'/r term is integrable but not finite there).
 """
 from __future__ import annotations
 
@@ -63,3 +69,26 @@ def grad1_basis(xa: np.ndarray, xb: np.ndarray, k: int) -> np.ndarray:
     with np.errstate(divide="ignore", invalid="ignore"):
         f = np.where(r > 0.0, up / np.where(r > 0.0, r, 1.0), 0.0)
     return np.moveaxis(d * f[:, :, None], 2, 0)
+
+
+def d2u_dr2(r, kind: str, b: float = 1.0, coef=()):
+    r = np.asarray(r, dtype=np.float64)
+    if kind == "pade":
+        return -b / (1.0 + b * r) ** 3
+    if kind == "power":
+        t = r / (1.0 + r)
+        s2 = sum((k + 1) * k * c * t ** (k - 1) for k, c in enumerate(coef) if k >= 1)
+        s1 = sum((k + 1) * c * t ** k for k, c in enumerate(coef))
+        return s2 / (1.0 + r) ** 4 - 2.0 * s1 / (1.0 + r) ** 3
+    raise ValueError(kind)
+
+
+def scalar_kernel(xa: np.ndarray, xb: np.ndarray, jas) -> np.ndarray:
+    """S = laplacian_1 u + |grad_1 u|^2 for all pairs, [len(xa)][len(xb)]; 0 at r == 0."""
+    d = xa[:, None, :] - xb[None, :, :]
+    r = np.sqrt(np.sum(d * d, axis=2))
+    up = du_dr(r, jas.kind, jas.b, jas.coef)
+    upp = d2u_dr2(r, jas.kind, jas.b, jas.coef)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        S = np.where(r > 0.0, upp + 2.0 * up / np.where(r > 0.0, r, 1.0) + up * up, 0.0)
+    return S

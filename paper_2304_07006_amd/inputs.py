@@ -143,21 +143,39 @@ def basis_values(xyz: np.ndarray, centres: np.ndarray, per_centre: int,
         raise ValueError("functions per centre must be a multiple of 4 (m/4 s + m/4 p shells)")
     ns = per_centre // 4
     lo, hi = math.log(ALPHA_RANGE[0]), math.log(ALPHA_RANGE[1])
-    rows, shells = [], []
-    for c, R in enumerate(centres):
-        d = xyz - R
+    shells = []
+    for c in range(len(centres)):
+        for _ in range(ns):
+            shells.append(("s", c, math.exp(rng.uniform(lo, hi))))
+        for _ in range(ns):
+            shells.append(("p", c, math.exp(rng.uniform(lo, hi))))
+    return eval_shells(xyz, centres, shells), shells
+
+
+def eval_shells(xyz: np.ndarray, centres: np.ndarray, shells) -> np.ndarray:
+    """Values of the shells' functions at xyz, [N][len(xyz)] (s: one function,
+    p: x, y, z)."""
+    rows = []
+    for kind, c, a in shells:
+        d = xyz - centres[c]
         r2 = np.sum(d * d, axis=1)
-        for _ in range(ns):
-            a = math.exp(rng.uniform(lo, hi))
+        if kind == "s":
             rows.append((2.0 * a / math.pi) ** 0.75 * np.exp(-a * r2))
-            shells.append(("s", c, a))
-        for _ in range(ns):
-            a = math.exp(rng.uniform(lo, hi))
+        else:
             g = (128.0 * a ** 5 / math.pi ** 3) ** 0.25 * np.exp(-a * r2)
             for ax in range(3):
                 rows.append(d[:, ax] * g)
-            shells.append(("p", c, a))
-    return np.ascontiguousarray(np.array(rows)), shells
+    return np.ascontiguousarray(np.array(rows))
+
+
+def lowdin_matrix(chi: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """X = S^{-1/2} with S = chi diag(w) chi^T (FP64, input preparation)."""
+    S = (chi * w) @ chi.T
+    S = 0.5 * (S + S.T)
+    lam, U = np.linalg.eigh(S)
+    if lam[0] <= 0:
+        raise ValueError("grid overlap matrix is not positive definite")
+    return (U * lam ** -0.5) @ U.T
 
 
 def orthonormalise_inputs(chi: np.ndarray, w: np.ndarray) -> np.ndarray:
@@ -165,13 +183,34 @@ def orthonormalise_inputs(chi: np.ndarray, w: np.ndarray) -> np.ndarray:
 
     Input preparation only: phi = S^{-1/2} chi with S = chi diag(w) chi^T, in FP64.
     """
-    S = (chi * w) @ chi.T
-    S = 0.5 * (S + S.T)
-    lam, U = np.linalg.eigh(S)
-    if lam[0] <= 0:
-        raise ValueError("grid overlap matrix is not positive definite")
-    X = (U * lam ** -0.5) @ U.T
-    return np.ascontiguousarray(X @ chi)
+    return np.ascontiguousarray(lowdin_matrix(chi, w) @ chi)
+
+
+def basis_gradients(xyz: np.ndarray, centres: np.ndarray, shells) -> np.ndarray:
+    """Analytic gradients of the raw functions of basis_values, [3][N][Ng]
+    (same order: per shell one s function or the x, y, z components of a p shell)."""
+    out = []
+    for kind, c, a in shells:
+        d = xyz - centres[c]
+        e = np.exp(-a * np.sum(d * d, axis=1))
+        if kind == "s":
+            g = (2.0 * a / math.pi) ** 0.75 * e
+            out.append(-2.0 * a * d.T * g)                      # grad of N e^{-a r^2}
+        else:
+            g = (128.0 * a ** 5 / math.pi ** 3) ** 0.25 * e
+            for ax in range(3):
+                gr = -2.0 * a * d[:, ax] * d.T * g              # d_ax * grad(e) part
+                gr[ax] += g                                     # grad(d_ax) e part
+                out.append(gr)
+    return np.ascontiguousarray(np.moveaxis(np.array(out), 1, 0))
+
+
+def orbital_gradients(p: "Problem") -> np.ndarray:
+    """grad phi on the grid, [3][N][Ng]: the Loewdin transform of the analytic
+    basis gradients (phi = X chi, so grad phi = X grad chi)."""
+    X = lowdin_matrix(p.chi, p.w)
+    dchi = basis_gradients(p.xyz, p.centres, p.meta["shells"])
+    return np.ascontiguousarray(np.einsum("ij,xjg->xig", X, dchi))
 
 
 def make_jastrow(kind: str, aux_seed: int) -> Jastrow:

@@ -100,6 +100,16 @@ def test_bad_beta_occupations_and_open_shell_adjoint(lib):
     assert st == xtc.XTC_E_UNSUPPORTED and "closed-shell" in xtc.last_error()
 
 
+@pytest.mark.parametrize("core,act", [([0], [0, 1]), ([9], [1]), ([], []), ([-1], [2])])
+def test_frozen_core_validation(lib, core, act):
+    c = np.array(core, dtype=np.int32)
+    a = np.array(act, dtype=np.int32)
+    ip = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    f = ctypes.c_void_p(0x1000)
+    st = lib.xtc_frozen_core(8, f, f, f, len(c), ip(c), len(a), ip(a), f, f, f, None)
+    assert st == xtc.XTC_E_ARG and xtc.last_error()
+
+
 def test_bad_jastrow_and_range(lib):
     c, keep = _problem()
     n = lib.xtc_workspace_size(ctypes.byref(c), 0, 50)

@@ -184,3 +184,22 @@ def test_open_shell_with_equal_spins_is_the_closed_shell(torch_cuda):
     for s in range(2):
         assert np.abs(h1[s] - h1c).max() < 1e-15
     assert abs(E0 - E0c) < 1e-14
+
+
+def test_frozen_core_folding(torch_cuda):
+    """xtc_frozen_core on the GPU outputs against the oracle's frozen-core
+    equations applied to the oracle's outputs (xTC-FC)."""
+    from oracle import factorised as fb
+    from paper_2304_07006_amd import xtc
+    p = inputs.make_problem(24, 4, 1500, 6, "chain", "pade", seed=49)
+    core, act = [0, 1], list(range(2, 24))
+    _note("case: N24 frozen core (2 core, 22 active) fp64")
+    V2o, h1o, E0o = fb.closed_shell(p.xyz, p.w, p.phi, p.occ, p.jastrow)
+    Vf, hf, Ef = fb.frozen_core(V2o, h1o, E0o, core, act)
+    V2, h1, E0 = xtc.forward(p, prec="fp64", chunk_rows=600)
+    Vg, hg, Eg = xtc.frozen_core(V2, h1, E0, core, act)
+    Vg, hg, Eg = Vg.cpu().numpy(), hg.cpu().numpy(), float(Eg.cpu().numpy()[0])
+    assert np.array_equal(Vg, V2.cpu().numpy()[np.ix_(act, act, act, act)])
+    assert np.abs(Vg - Vf).max() < TOL_ABS
+    assert np.abs(hg - hf).max() < TOL_ABS
+    assert abs(Eg - Ef) < TOL_ABS

@@ -126,3 +126,19 @@ def test_occupation_generators():
     m = inputs.natural_occupations(9, 5)
     assert m.shape == (9,) and np.all(m > 0) and np.all(m < 1) and np.all(np.diff(m) <= 0)
     assert np.array_equal(m, inputs.natural_occupations(9, 5))
+
+
+def test_orbital_gradients_match_finite_differences():
+    p = inputs.make_problem(8, 2, 40, 2, "pair", "pade", seed=3)
+    dchi = inputs.basis_gradients(p.xyz, p.centres, p.meta["shells"])
+    h = 1e-5
+    for ax in range(3):
+        e = np.zeros(3)
+        e[ax] = h
+        fd = (inputs.eval_shells(p.xyz + e, p.centres, p.meta["shells"])
+              - inputs.eval_shells(p.xyz - e, p.centres, p.meta["shells"])) / (2 * h)
+        assert np.abs(fd - dchi[ax]).max() < 1e-8
+    dphi = inputs.orbital_gradients(p)
+    X = inputs.lowdin_matrix(p.chi, p.w)
+    assert np.abs(X @ p.chi - p.phi).max() < 1e-13
+    assert np.abs(dphi - np.einsum("ij,xjg->xig", X, dchi)).max() == 0.0

@@ -282,6 +282,62 @@ def test_frozen_core_folding_is_exact_in_determinant_space(tiny, tierA):
     assert max(abs(f.get(to_full(k), 0.0) - v) for k, v in a.items()) > 1e-6
 
 
+# ------------------------------------------- two-body TC integrals (K) --
+@pytest.mark.parametrize("jas", [J("pade", 1.0, ()), J("pade", 0.4, ()),
+                                 J("power", 0.0, (0.5, -0.1, 0.07, 0.02))])
+def test_scalar_kernel_is_laplacian_plus_gradient_squared(jas):
+    """S = lap_1 u + |grad_1 u|^2 against a 3-D finite-difference stencil of u(|r1 - r2|)."""
+    rng = np.random.default_rng(9)
+    x1 = rng.normal(size=(12, 3))
+    x2 = x1 + rng.normal(size=(12, 3)) * 0.8
+    S = np.diag(oj.scalar_kernel(x1, x2, jas))
+    h = 1e-4
+    u = lambda a: oj.u_of_r(np.linalg.norm(a - x2, axis=1), jas.kind, jas.b, jas.coef)
+    lap = np.zeros(12)
+    g2 = np.zeros(12)
+    for ax in range(3):
+        e = np.zeros(3)
+        e[ax] = h
+        up, um, u0 = u(x1 + e), u(x1 - e), u(x1)
+        lap += (up - 2 * u0 + um) / h ** 2
+        g2 += ((up - um) / (2 * h)) ** 2
+    assert np.abs(S - (lap + g2)).max() < 1e-6 * max(1.0, np.abs(S).max())
+    r = np.linspace(0.05, 6.0, 50)
+    d2 = oj.d2u_dr2(r, jas.kind, jas.b, jas.coef)
+    fd = (oj.du_dr(r + 1e-6, jas.kind, jas.b, jas.coef) - oj.du_dr(r - 1e-6, jas.kind, jas.b, jas.coef)) / 2e-6
+    assert np.abs(d2 - fd).max() < 1e-7
+
+
+@pytest.fixture(scope="module")
+def tc_case():
+    p = inputs.make_problem(8, 2, 80, 2, "pair", "power16", seed=13)
+    return p, inputs.orbital_gradients(p)
+
+
+def test_tc_two_body_factorised_equals_definition(tc_case):
+    from oracle import tc2
+    p, dphi = tc_case
+    Ka = tc2.tc_two_body_explicit(p.xyz, p.w, p.phi, dphi, p.jastrow)
+    Kb = tc2.tc_two_body(p.xyz, p.w, p.phi, dphi, p.jastrow, block=33)
+    assert np.abs(Ka - Kb).max() < 1e-15 * max(1.0, np.abs(Ka).max()) * 10
+    # electron-swap symmetry of the definition; no p <-> q symmetry (non-hermitian)
+    assert np.abs(Ka - Ka.transpose(2, 3, 0, 1)).max() < 2e-15
+    assert np.abs(Ka - Ka.transpose(1, 0, 3, 2)).max() > 1e-4
+
+
+def test_tc_two_body_linear_and_quadratic_parts(tc_case):
+    """K(2c) - 2 K(c) = 2 K_quad(c): only |grad u|^2 is quadratic in u."""
+    from oracle import tc2
+    p, dphi = tc_case
+    c = np.array(p.jastrow.coef)
+    J1 = J("power", 0.0, tuple(c))
+    J2 = J("power", 0.0, tuple(2 * c))
+    K1 = tc2.tc_two_body(p.xyz, p.w, p.phi, dphi, J1)
+    K2 = tc2.tc_two_body(p.xyz, p.w, p.phi, dphi, J2)
+    Q = tc2.quadratic_part(p.xyz, p.w, p.phi, J1)
+    assert np.abs((K2 - 2 * K1) - 2 * Q).max() < 1e-14 * max(1.0, np.abs(K2).max())
+
+
 def test_spin_blocks(tiny, tierA):
     N = tiny.N
     dU = tierA["dU_so"]
