@@ -69,8 +69,9 @@ typedef enum {
 typedef enum { XTC_FP64 = 0, XTC_FP32 = 1, XTC_BF16X3 = 2, XTC_BF16X6 = 3 } xtc_prec;
 
 /* OR-ed into prec: lay the workspace out for xtc_backward as well (extra
- * per-row buffers).  Every call on that workspace must pass the same value. */
-enum { XTC_WITH_BACKWARD = 0x10 };
+ * per-row buffers), and for xtc_tc_2body (its accumulators and chunk
+ * buffers).  Every call on that workspace must pass the same value. */
+enum { XTC_WITH_BACKWARD = 0x10, XTC_WITH_TC2 = 0x20 };
 
 /* flags of the contraction calls */
 enum {
@@ -222,6 +223,41 @@ xtc_status xtc_backward(const xtc_problem *pb, const xtc_jastrow *jas, int32_t p
 size_t xtc_lowdin_workspace_size(int32_t N, int32_t Ng);
 xtc_status xtc_lowdin(int32_t N, int32_t Ng, const double *chi, const double *w, double *phi,
                       double *lambda, void *ws, size_t ws_bytes, void *stream);
+
+/* Two-body transcorrelated integrals on the grid (Theory, definition of K):
+ *   K_pr^qs = 1/2 <pr| P^1_2 (lap_1 u + (grad_1 u)^2 + 2 grad_1 u . grad_1) |qs>
+ * with both electrons on the grid, written as K2[p][q][r][s] = K_pr^qs
+ * (p, q electron 1; the order of V2).  With rho_pq = w phi_p phi_q,
+ * S(g,g') = lap_1 u + |grad_1 u|^2 (0 at coincident points),
+ * F_R(g) = sum_g' S(g,g') rho_R(g'), the grid intermediate K of the same rows
+ * (as written by xtc_build_K) and rhog_pq = w phi_p grad phi_q:
+ *   K2[pq][rs] = A[P][R] + B[pq][R] + B[rs][P],
+ *   A = sum_g rho_P F_R,  B[pq][R] = sum_g rhog_pq . K_R,
+ * accumulated chunk by chunk like xtc_contract_2body (XTC_RESET, XTC_FINALIZE)
+ * into FP64 accumulators in the workspace.  K2 satisfies
+ * K2[p][q][r][s] = K2[r][s][p][q] but not the p <-> q symmetry (the integrals
+ * are not hermitian).  F, A and B are computed in FP64 in every form (K follows
+ * prec).  Needs xtc_prepare with prec | XTC_WITH_TC2.
+ * dphi: device [3][N][Ng], the gradients of the orbitals on the grid;
+ * K: device [3][g1-g0][ldP]; K2: device [N]^4, may be NULL unless XTC_FINALIZE. */
+xtc_status xtc_tc_2body(const xtc_problem *pb, const xtc_jastrow *jas, const double *dphi,
+                        const double *K, int32_t g0, int32_t g1, int32_t prec, int32_t flags,
+                        double *K2, void *ws, size_t ws_bytes, void *stream);
+
+/* Frozen-core folding of the closed-shell outputs (xTC-FC, results section:
+ * the corrections are computed with all electrons and the standard frozen-core
+ * equations are applied afterwards).  With (pq|rs) = V2[p][q][r][s] and the
+ * core orbitals c doubly occupied:
+ *   E_fc      = E0 + 2 sum_c h1[c][c] + sum_{c,d} (2 (cc|dd) - (cd|dc))
+ *   h1_act[i][j] = h1[a_i][a_j] + sum_c (2 (a_i a_j|cc) - (a_i c|c a_j))
+ *   V2_act[i][j][k][l] = V2[a_i][a_j][a_k][a_l]
+ * V2 [N]^4, h1 [N][N], E0 [1]: device, as written by the contraction calls;
+ * core [ncore], act [nact]: HOST int32, disjoint, in [0,N), ncore >= 0,
+ * nact >= 1, each at most 256; V2_act [nact]^4, h1_act [nact][nact],
+ * E_fc [1]: device outputs.  Deterministic; no workspace. */
+xtc_status xtc_frozen_core(int32_t N, const double *V2, const double *h1, const double *E0,
+                           int32_t ncore, const int32_t *core, int32_t nact, const int32_t *act,
+                           double *V2_act, double *h1_act, double *E_fc, void *stream);
 
 /* Message for the last non-OK status returned on the calling thread. */
 const char *xtc_last_error(void);

@@ -19,6 +19,9 @@
 // and with XTC_WITH_BACKWARD in prec (the adjoint reuses M for Gbar):
 //   Kc [3][cap][ldP], Y [7][cap][ldP], T [cap][3][N][nocc], Wbar [cap][3],
 //   gpart [ceil(cap/32) * ngp/128][16], gacc [16], occw [N] f64, kidx [N]
+// and with XTC_WITH_TC2 (two-body TC integrals; ldN = N^2 rounded up to 128):
+//   Atc [ldP][ldP], Btc [ldN][ldP] FP64 accumulators, Ftc [cap][ldP],
+//   Rg [3][cap][ldN] (w phi grad phi of the chunk)
 // ldL = ldP rounded up to 512.  The chunk capacity `cap` is the largest
 // multiple of 32 rows that fits in the bytes the caller passes, so every call
 // with the same ws_bytes agrees on it.
@@ -34,6 +37,8 @@
 #include "../../include/xtc.h"
 #include "kernels_build_k.h"
 #include "kernels_contract.h"
+#include "kernels_fc.h"
+#include "kernels_tc2.h"
 #include "kernels_lp.h"
 #include "kernels_bwd.h"
 #include "kernels_lowdin.h"
@@ -76,14 +81,15 @@ constexpr int kOccSeg = 4;      // segments of the FP64 occupied-block sum over 
 
 struct Layout {
     int N, Ng, nocc, ldP, ngp, Npair, prec;
-    int form, ns, es, ldL, ldO, nOP, occNB, nsegK, nspin;
+    int form, ns, es, ldL, ldO, nOP, occNB, nsegK, nspin, ldN;
+    bool tc2;
     bool bwd;
-    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, occw, kidx, rhoR;
+    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, occw, kidx, rhoR, Atc, Btc;
     size_t fixed;        // bytes before S (plus the Mpart remainder reserve)
     size_t per_row;      // bytes per chunk row
     int cap;             // chunk rows that fit (multiple of kRowQuant)
     int nsegM;
-    size_t S, D, Kpart, CDlp, Mpart, Kocc, Kc, Y, T, Wbar, gpart, KbL, end;
+    size_t S, D, Kpart, CDlp, Mpart, Kocc, Kc, Y, T, Wbar, gpart, KbL, Ftc, Rg, end;
 };
 
 int form_of(int prec) {
@@ -129,6 +135,8 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.ldO = (int)align_up((size_t)L.nOP, (size_t)16 * L.occNB);
     L.nsegK = (L.ngp + kSegK - 1) / kSegK;
     L.bwd = (prec & XTC_WITH_BACKWARD) != 0;
+    L.tc2 = (prec & XTC_WITH_TC2) != 0;
+    L.ldN = (int)align_up((size_t)pb->N * pb->N, 128);
     const bool lp = L.form != 0;
     size_t off = 0;
     L.pos = off;     off = align_up(off + (size_t)L.ngp * 4 * sizeof(double), kAlign);
@@ -144,14 +152,17 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.occw = off;    off = align_up(off + (L.bwd ? (size_t)L.N * sizeof(double) : 0), kAlign);
     L.kidx = off;    off = align_up(off + (L.bwd ? (size_t)L.N * sizeof(int) : 0), kAlign);
     L.rhoR = off;    off = align_up(off + (L.bwd && lp ? (size_t)L.ns * L.ngp * L.ldP * L.es : 0), kAlign);
+    L.Atc = off;     off = align_up(off + (L.tc2 ? (size_t)L.ldP * L.ldP * sizeof(double) : 0), kAlign);
+    L.Btc = off;     off = align_up(off + (L.tc2 ? (size_t)L.ldN * L.ldP * sizeof(double) : 0), kAlign);
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);   // one 32-row tile of partials
     const size_t mslab = (size_t)4 * L.ldL * L.ldL * sizeof(float);       // one partial per component
-    L.fixed = off + (lp ? mslab : 0) + (L.bwd ? gslab : 0) + 14 * kAlign;
+    L.fixed = off + (lp ? mslab : 0) + (L.bwd ? gslab : 0) + 16 * kAlign;
     L.per_row = (size_t)L.nspin * (8 * sizeof(double) + (size_t)4 * L.ldP * sizeof(double));
     if (lp) L.per_row += (size_t)kOccSeg * 3 * L.ldO * sizeof(double);
     if (lp)
         L.per_row += (size_t)L.nsegK * 3 * L.ldL * sizeof(float) + (size_t)8 * L.ns * L.ldL * L.es +
                      (mslab + kSegM - 1) / kSegM;
+    if (L.tc2) L.per_row += (size_t)L.ldP * sizeof(double) + (size_t)3 * L.ldN * sizeof(double);
     if (L.bwd)
         L.per_row += (size_t)10 * L.ldP * sizeof(double) + (size_t)3 * L.N * L.nocc * sizeof(double) +
                      3 * sizeof(double) + (gslab + 31) / 32 + (lp ? (size_t)3 * L.ns * L.ldP * L.es : 0);
@@ -169,7 +180,7 @@ void place_chunk(Layout& L, size_t bytes) {
     const bool lp = L.form != 0;
     L.nsegM = lp ? 4 * (int)((cap + kSegM - 1) / kSegM) : 0;
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);
-    size_t off = L.fixed - 14 * kAlign - (lp ? (size_t)4 * L.ldL * L.ldL * sizeof(float) : 0) - (L.bwd ? gslab : 0);
+    size_t off = L.fixed - 16 * kAlign - (lp ? (size_t)4 * L.ldL * L.ldL * sizeof(float) : 0) - (L.bwd ? gslab : 0);
     L.S = off;       off = align_up(off + (size_t)L.nspin * cap * 8 * sizeof(double), kAlign);
     L.D = off;       off = align_up(off + (size_t)L.nspin * 4 * cap * L.ldP * sizeof(double), kAlign);
     L.Kpart = off;   off = align_up(off + (lp ? (size_t)L.nsegK * 3 * cap * L.ldL * sizeof(float) : 0), kAlign);
@@ -183,6 +194,8 @@ void place_chunk(Layout& L, size_t bytes) {
     L.Wbar = off;    off = align_up(off + (b ? (size_t)cap * 3 * sizeof(double) : 0), kAlign);
     L.gpart = off;   off = align_up(off + (b ? (size_t)((cap + 31) / 32) * gslab : 0), kAlign);
     L.KbL = off;     off = align_up(off + (b && lp ? (size_t)3 * L.ns * cap * L.ldP * L.es : 0), kAlign);
+    L.Ftc = off;     off = align_up(off + (L.tc2 ? (size_t)cap * L.ldP * sizeof(double) : 0), kAlign);
+    L.Rg = off;      off = align_up(off + (L.tc2 ? (size_t)3 * cap * L.ldN * sizeof(double) : 0), kAlign);
     L.end = off;
     if (L.end > bytes) L.cap = 0;   // cannot happen by construction; refuse rather than overrun
 }
@@ -215,7 +228,7 @@ xtc_status check_problem(const xtc_problem* pb) {
 
 xtc_status check_prec(int prec) {
     const int base = prec & 0xF;
-    if ((prec & ~(0xF | XTC_WITH_BACKWARD)) ||
+    if ((prec & ~(0xF | XTC_WITH_BACKWARD | XTC_WITH_TC2)) ||
         (base != XTC_FP64 && base != XTC_FP32 && base != XTC_BF16X3 && base != XTC_BF16X6))
         return fail(XTC_E_ARG, "prec=%d unknown", prec);
     return XTC_OK;
@@ -234,6 +247,7 @@ xtc_status check_jastrow(const xtc_jastrow* j, JasDev* out) {
         for (int k = 0; k < j->ncoef; ++k) {
             if (!std::isfinite(j->coef[k])) return fail(XTC_E_ARG, "coef[%d] not finite", k);
             d.dcoef[k] = (k + 1) * j->coef[k];
+            if (k >= 1) d.d2coef[k - 1] = (k + 1) * k * j->coef[k];
         }
         d.ncoef = j->ncoef;
     } else {
@@ -773,6 +787,92 @@ LowdinLayout lowdin_layout(int N, int Ng) {
     return L;
 }
 }  // namespace
+
+xtc_status xtc_tc_2body(const xtc_problem* pb, const xtc_jastrow* jas, const double* dphi, const double* K,
+                        int32_t g0, int32_t g1, int32_t prec, int32_t flags, double* K2, void* ws, size_t ws_bytes,
+                        void* stream) {
+    xtc_status s;
+    JasDev J;
+    if ((s = check_problem(pb)) != XTC_OK) return s;
+    if ((s = check_prec(prec)) != XTC_OK) return s;
+    if ((s = check_jastrow(jas, &J)) != XTC_OK) return s;
+    if (!(prec & XTC_WITH_TC2)) return fail(XTC_E_ARG, "prec must carry XTC_WITH_TC2");
+    if (!dphi || !K) return fail(XTC_E_ARG, "dphi or K is NULL");
+    if ((s = check_align(K, "K")) != XTC_OK) return s;
+    if (flags & ~(XTC_RESET | XTC_FINALIZE)) return fail(XTC_E_ARG, "flags=%d unknown bits", flags);
+    if ((flags & XTC_FINALIZE) && !K2) return fail(XTC_E_ARG, "K2 is NULL with XTC_FINALIZE");
+    Layout L = make_layout(pb, prec);
+    place_chunk(L, ws_bytes);
+    if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
+    if ((s = check_range(L, g0, g1)) != XTC_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int rows = g1 - g0;
+    // F for the chunk rows: scalar kernel S against all g' (FP64)
+    double* F = at<double>(ws, L.Ftc);
+    const int n_rt = (rows + kKRows - 1) / kKRows;
+    const dim3 gF(n_rt * (L.ldP / 128));
+    if (J.kind == 0)
+        hipLaunchKernelGGL((k_build_F_f64<0, 8>), gF, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
+                           L.ldP, L.ngp, g0, rows, n_rt, J, F);
+    else
+        hipLaunchKernelGGL((k_build_F_f64<1, 8>), gF, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
+                           L.ldP, L.ngp, g0, rows, n_rt, J, F);
+    if ((s = launched("build_F")) != XTC_OK) return s;
+    double* Rg = at<double>(ws, L.Rg);
+    const size_t xs = (size_t)L.cap * L.ldN;
+    const size_t nrg = (size_t)rows * L.ldN;
+    hipLaunchKernelGGL(k_rhog, dim3((unsigned)std::min<size_t>((nrg + 255) / 256, 16384)), dim3(256), 0, st, pb->w,
+                       pb->phi, dphi, L.N, L.Ng, g0, rows, L.ldN, xs, Rg);
+    if ((s = launched("rhog")) != XTC_OK) return s;
+    const int acc = (flags & XTC_RESET) ? 0 : 1;
+    const int nP = L.ldP / 128, nN = L.ldN / 128;
+    const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
+    hipLaunchKernelGGL(k_gemm_tn_f64, dim3(nP * nP), dim3(256), 0, st, rho_rows, (size_t)0, L.ldP, F, (size_t)0, L.ldP,
+                       1, rows, nP, at<double>(ws, L.Atc), L.ldP, acc);
+    if ((s = launched("gemm_tc_A")) != XTC_OK) return s;
+    hipLaunchKernelGGL(k_gemm_tn_f64, dim3(nN * nP), dim3(256), 0, st, Rg, xs, L.ldN, K, (size_t)rows * L.ldP, L.ldP,
+                       3, rows, nN, at<double>(ws, L.Btc), L.ldP, acc);
+    if ((s = launched("gemm_tc_B")) != XTC_OK) return s;
+    if (flags & XTC_FINALIZE) {
+        const int NN = L.N * L.N;
+        hipLaunchKernelGGL(k_finalize_K2, dim3((NN + 255) / 256, L.N, L.N), dim3(256), 0, st, at<double>(ws, L.Atc),
+                           L.ldP, at<double>(ws, L.Btc), L.N, K2);
+        if ((s = launched("finalize_K2")) != XTC_OK) return s;
+    }
+    return XTC_OK;
+}
+
+xtc_status xtc_frozen_core(int32_t N, const double* V2, const double* h1, const double* E0, int32_t ncore,
+                           const int32_t* core, int32_t nact, const int32_t* act, double* V2_act, double* h1_act,
+                           double* E_fc, void* stream) {
+    if (N < 1 || N > kMaxN) return fail(XTC_E_ARG, "N=%d outside [1,%d]", N, kMaxN);
+    if (ncore < 0 || ncore > kMaxFcList || nact < 1 || nact > kMaxFcList || ncore + nact > N)
+        return fail(XTC_E_ARG, "ncore=%d, nact=%d invalid for N=%d", ncore, nact, N);
+    if (!V2 || !h1 || !E0 || !act || (ncore > 0 && !core) || !V2_act || !h1_act || !E_fc)
+        return fail(XTC_E_ARG, "NULL argument");
+    std::vector<char> seen(N, 0);
+    IdxList c{}, a{};
+    c.n = ncore;
+    a.n = nact;
+    for (int i = 0; i < ncore + nact; ++i) {
+        const int k = i < ncore ? core[i] : act[i - ncore];
+        if (k < 0 || k >= N) return fail(XTC_E_ARG, "orbital %d outside [0,N)", k);
+        if (seen[k]) return fail(XTC_E_ARG, "orbital %d listed twice (core and active must be disjoint)", k);
+        seen[k] = 1;
+        if (i < ncore) c.k[i] = k;
+        else a.k[i - ncore] = k;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    xtc_status s;
+    hipLaunchKernelGGL(k_fc_onebody, dim3((nact * nact + 255) / 256), dim3(256), 0, st, V2, h1, N, c, a, h1_act);
+    if ((s = launched("fc_onebody")) != XTC_OK) return s;
+    hipLaunchKernelGGL(k_fc_energy, dim3(1), dim3(64), 0, st, V2, h1, E0, N, c, E_fc);
+    if ((s = launched("fc_energy")) != XTC_OK) return s;
+    const size_t total = (size_t)nact * nact * nact * nact;
+    hipLaunchKernelGGL(k_fc_gather, dim3((unsigned)std::min<size_t>((total + 255) / 256, 65536)), dim3(256), 0, st, V2,
+                       N, a, V2_act);
+    return launched("fc_gather");
+}
 
 size_t xtc_lowdin_workspace_size(int32_t N, int32_t Ng) {
     if (N < 1 || N > kMaxN || Ng < 1) {

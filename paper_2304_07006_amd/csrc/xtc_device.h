@@ -21,6 +21,7 @@ struct JasDev {
     int32_t ncoef;
     double b;
     double dcoef[16];
+    double d2coef[16];   // (k+2)(k+1) coef[k+1]: u''(t) as a Horner polynomial
     // the same parameters rounded to FP32 (reduced-precision forms; kernel
     // arguments, so they stay in scalar registers)
     float fb;

@@ -20,6 +20,7 @@ XTC_OK, XTC_E_ARG, XTC_E_WORKSPACE, XTC_E_HIP, XTC_E_UNSUPPORTED = 0, -1, -2, -3
 XTC_FP64, XTC_FP32, XTC_BF16X3, XTC_BF16X6 = 0, 1, 2, 3
 XTC_RESET, XTC_FINALIZE = 1, 2
 XTC_WITH_BACKWARD = 0x10
+XTC_WITH_TC2 = 0x20
 PRECISIONS = {"fp64": XTC_FP64, "fp32": XTC_FP32, "bf16x3": XTC_BF16X3, "bf16x6": XTC_BF16X6}
 
 
@@ -42,6 +43,13 @@ class XtcProblem(ctypes.Structure):
 
 
 _SIGS = {
+    "xtc_tc_2body": (ctypes.c_int, [ctypes.POINTER(XtcProblem), ctypes.POINTER(XtcJastrow), ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "xtc_frozen_core": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
     "xtc_pair_ld": (ctypes.c_int32, [ctypes.c_int32]),
     "xtc_last_error": (ctypes.c_char_p, []),
     "xtc_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(XtcProblem), ctypes.c_int32, ctypes.c_int32]),
@@ -274,6 +282,49 @@ def forward(problem, prec="fp64", chunk_rows=None, device="cuda", jastrow=None):
     ps = Pass(dp, PRECISIONS[prec] if isinstance(prec, str) else prec, chunk_rows, device)
     V2, h1, E0 = ps.run(make_jastrow(jastrow or problem.jastrow))
     return V2, h1, E0
+
+
+def tc_two_body(problem, dphi, prec="fp64", chunk_rows=None, device="cuda", jastrow=None, stream=None):
+    """Two-body TC integrals K2[p][q][r][s] = K_pr^qs (xtc_tc_2body) for an
+    inputs.Problem; dphi [3][N][Ng] host or device.  Builds K chunk by chunk."""
+    import torch
+    dp = device_problem(problem.xyz, problem.w, problem.phi, problem.occ, device)
+    p = (PRECISIONS[prec] if isinstance(prec, str) else prec) | XTC_WITH_TC2
+    chunk = min(dp.Ng, chunk_rows or dp.Ng)
+    L = load()
+    ws = torch.empty(xtc_workspace_size(dp, p, chunk), dtype=torch.uint8, device=device)
+    xtc_prepare(dp, p, chunk, ws, stream)
+    ldP = xtc_pair_ld(dp.N)
+    Kbuf = torch.empty((3 * chunk * ldP,), dtype=torch.float64, device=device)
+    dphi_t = torch.as_tensor(np.ascontiguousarray(dphi, dtype=np.float64)).to(device)
+    N = dp.N
+    K2 = torch.empty((N, N, N, N), dtype=torch.float64, device=device)
+    jas = make_jastrow(jastrow or problem.jastrow)
+    ch = [(g0, min(dp.Ng, g0 + chunk)) for g0 in range(0, dp.Ng, chunk)]
+    for i, (g0, g1) in enumerate(ch):
+        flags = (XTC_RESET if i == 0 else 0) | (XTC_FINALIZE if i == len(ch) - 1 else 0)
+        K = Kbuf[:3 * (g1 - g0) * ldP]
+        xtc_build_K(dp, jas, g0, g1, p, K, ws, stream)
+        _check(L.xtc_tc_2body(ctypes.byref(dp.c), ctypes.byref(jas), _ptr(dphi_t), _ptr(K), g0, g1, p, flags,
+                              _ptr(K2), _ptr(ws), ws.numel(), _stream(stream)))
+    return K2
+
+
+def frozen_core(V2, h1, E0, core, active, stream=None):
+    """Frozen-core folding (xtc_frozen_core) of closed-shell outputs on the device:
+    returns (V2_act, h1_act, E_fc)."""
+    import torch
+    N = h1.shape[0]
+    c = np.ascontiguousarray(core, dtype=np.int32)
+    a = np.ascontiguousarray(active, dtype=np.int32)
+    na = len(a)
+    V = torch.empty((na,) * 4, dtype=torch.float64, device=V2.device)
+    h = torch.empty((na, na), dtype=torch.float64, device=V2.device)
+    E = torch.empty((1,), dtype=torch.float64, device=V2.device)
+    ip = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    _check(load().xtc_frozen_core(N, _ptr(V2), _ptr(h1), _ptr(E0), len(c), ip(c), na, ip(a), _ptr(V), _ptr(h),
+                                  _ptr(E), _stream(stream)))
+    return V, h, E
 
 
 def power_jastrow(coef) -> XtcJastrow:
