@@ -207,6 +207,22 @@ def probe(problem, prec, chunk):
     print(f"[probe] copy 1 GiB + build_K {prec} rows=0..{chunk}", file=sys.stderr, flush=True)
 
 
+def run_tc2(problem, prec, chunk, steps, warmup):
+    """Two-body TC integrals pass (xtc_build_K + xtc_tc_2body over all chunks)."""
+    import torch
+    from paper_2304_07006_amd import inputs, xtc
+    dphi = inputs.orbital_gradients(problem)
+    xtc.tc_two_body(problem, dphi, prec, chunk)            # builds the library state once
+    for _ in range(warmup):
+        xtc.tc_two_body(problem, dphi, prec, chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        K2 = xtc.tc_two_body(problem, dphi, prec, chunk)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, K2
+
+
 def cpu_baseline(name, budget_rows):
     """The oracle (Appendix-B equations, numpy FP64) on the same workload's
     orbitals and generator, on a reduced grid of `budget_rows` points."""
@@ -240,6 +256,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=300, help="grid points of the CPU oracle sample (0: skip)")
     ap.add_argument("--density", default="closed",
                     help="reference density: closed | sa:ND,NS | natural:NACT (see apply_density)")
+    ap.add_argument("--tc2", action="store_true",
+                    help="time the two-body TC integrals (K build + xtc_tc_2body) instead of the xTC folding")
     ap.add_argument("--probe", action="store_true",
                     help="counter pass: one 1 GiB device copy (calibration) and one K-build launch, no JSON")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -268,6 +286,23 @@ def main():
     chunk = args.chunk or default_chunk(wl.Ng, args.prec)
     if args.probe:
         probe(problem, args.prec, chunk)
+        return
+    if args.tc2:
+        P = wl.N * (wl.N + 1) // 2
+        Ftc = 6 * wl.Ng ** 2 * P + 2 * wl.Ng ** 2 * P + 2 * wl.Ng * P * P + 6 * wl.Ng * wl.N ** 2 * P
+        sec, K2 = run_tc2(problem, args.prec, chunk, args.steps, args.warmup)
+        line = {"metric": "two-body TC integrals GFLOP/s (K build + F = S rho + A, B contractions)",
+                "value": Ftc / sec / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": DTYPE[args.prec] + "+f64", "data": "synthetic",
+                "config": {"workload": args.workload, "N": wl.N, "Ng": wl.Ng, "prec": args.prec,
+                           "chunk_rows": chunk, "F_flop": Ftc}}
+        if args.compare != "none" and args.compare != args.prec:
+            sec_c, K2c = run_tc2(problem, args.compare, default_chunk(wl.Ng, args.compare), 1, 0)
+            line["forms"] = {args.compare: {"s_per_step": sec_c,
+                                            "max_abs_err": (K2 - K2c).abs().max().item(),
+                                            "max_abs": K2c.abs().max().item()}}
+        print(json.dumps(line), flush=True)
         return
     print(f"[bench] {args.workload} prec={args.prec} chunk={chunk} warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
