@@ -134,6 +134,34 @@ __device__ __forceinline__ float du_over_r_fast(float r2, const JasDev& J) {
     return r2 > 0.0f ? f : 0.0f;
 }
 
+// S = u'' + 2 u'/r + u'^2 in FP32 (the scalar kernel of the two-body TC
+// integrals), same reciprocal / reciprocal square root scheme; 0 at r^2 == 0.
+template <int KIND>
+__device__ __forceinline__ float scalar_S_fast(float r2, const JasDev& J) {
+    const float rs = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * rs;
+    float up, upp;
+    if constexpr (KIND == 0) {
+        const float it = __builtin_amdgcn_rcpf(fmaf(J.fb, r, 1.0f));
+        up = 0.5f * it * it;
+        upp = -J.fb * it * it * it;
+    } else {
+        const float q = __builtin_amdgcn_rcpf(1.0f + r);
+        const float t = r * q;
+        float p1 = J.fdcoef[15], p2 = J.fd2coef[15];
+#pragma unroll
+        for (int k = 14; k >= 0; --k) {
+            p1 = fmaf(p1, t, J.fdcoef[k]);
+            p2 = fmaf(p2, t, J.fd2coef[k]);
+        }
+        const float q2 = q * q;
+        up = p1 * q2;
+        upp = q2 * (p2 * q2 - 2.0f * p1 * q);
+    }
+    const float s = upp + 2.0f * up * rs + up * up;
+    return r2 > 0.0f ? s : 0.0f;
+}
+
 // K build, reduced precision, one segment [seg*seg_len, ...) of the sum over g'.
 // Workgroup: 512 threads = 8 waves, tile 32 grid rows x 512 pair columns; each
 // wave owns all 32 rows x 64 columns x 3 components (2 x 4 blocks x 3 = 24 FP32
@@ -143,8 +171,10 @@ __device__ __forceinline__ float du_over_r_fast(float r2, const JasDev& J) {
 // The d^x tile (32 rows x 32 g' x 3 components, already split) is generated
 // once per k-step by all 512 threads into LDS (double buffered) and shared by
 // the eight waves: generation is amortised over 512 columns.
+// NC = 1 builds F = S rho instead (the scalar kernel of the two-body TC
+// integrals, one component), with the same tiling.
 constexpr int kLpThreads = 512;
-template <int KIND, int FORM>
+template <int KIND, int FORM, int NC = 3>
 __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict__ pos,
                                                            const void* __restrict__ rho_lp, size_t split_stride,
                                                            int ldL, int ngp, int g0, int rows, int n_rt,
@@ -156,7 +186,7 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
     // two generation buffers as distinct arrays, so the compiler can prove the
     // writes of the next k-step do not alias the reads of the current one
     constexpr int kARow = LpARow<FORM>::v;
-    typedef T ATile[3][NS][kLpRows][kARow];
+    typedef T ATile[NC][NS][kLpRows][kARow];
     __shared__ __attribute__((aligned(16))) ATile sA0;
     __shared__ __attribute__((aligned(16))) ATile sA1;
     // positions of the 32 g' of one k-step as x[], y[], z[], pad[] (double
@@ -202,9 +232,9 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
     // to generate the shared tiles: no operand loads, MFMAs or stores
     const bool active = ct * kLpCols + wave * 64 < ncol;
 
-    f4 acc[3][2][NB];
+    f4 acc[NC][2][NB];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -225,17 +255,21 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
     };
     auto gen = [&](const PTile& P, ATile& W) {
         const dbl2 px = *(const dbl2*)&P[0][gk], py = *(const dbl2*)&P[1][gk], pz = *(const dbl2*)&P[2][gk];
-        float a[3][2];
+        float a[NC][2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const float dx = (float)(pr.x - px[j]), dy = (float)(pr.y - py[j]), dz = (float)(pr.z - pz[j]);
-            const float f = du_over_r_fast<KIND>(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), J);
-            a[0][j] = dx * f;
-            a[1][j] = dy * f;
-            a[2][j] = dz * f;
+            if constexpr (NC == 3) {
+                const float f = du_over_r_fast<KIND>(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), J);
+                a[0][j] = dx * f;
+                a[1][j] = dy * f;
+                a[2][j] = dz * f;
+            } else {
+                a[0][j] = scalar_S_fast<KIND>(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), J);
+            }
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < NC; ++c) {
             if constexpr (FORM == 1) {
                 W[c][0][grow][gk] = a[c][0];
                 W[c][0][grow][gk + 1] = a[c][1];
@@ -303,9 +337,9 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
             gen(PR, W);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                float av[3][8];
+                float av[NC][8];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
+                for (int c = 0; c < NC; ++c) {
                     const f4 x0 = *(const f4*)&R[c][0][16 * h + l16][8 * lk];
                     const f4 x1 = *(const f4*)&R[c][0][16 * h + l16][8 * lk + 4];
 #pragma unroll
@@ -317,7 +351,7 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
                     for (int b = 0; b < NB; ++b) {
                         const float be = e < 4 ? bv[b][0][e] : bv[b][1][e - 4];
 #pragma unroll
-                        for (int c = 0; c < 3; ++c)
+                        for (int c = 0; c < NC; ++c)
                             acc[c][h][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][e], be, acc[c][h][b], 0, 0, 0);
                     }
             }
@@ -325,9 +359,9 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
             gen(PR, W);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                bf8 av[3][NS];
+                bf8 av[NC][NS];
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
+                for (int c = 0; c < NC; ++c)
 #pragma unroll
                     for (int s = 0; s < NS; ++s) av[c][s] = *(const bf8*)&R[c][s][16 * h + l16][8 * lk];
 #pragma unroll
@@ -335,7 +369,7 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
 #pragma unroll
-                        for (int c = 0; c < 3; ++c)
+                        for (int c = 0; c < NC; ++c)
                             acc[c][h][b] = mma_bf16(av[c][Terms<FORM>::a[t]], bv[b][Terms<FORM>::b[t]], acc[c][h][b]);
             }
         }
@@ -345,12 +379,12 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
         // instruction order: operand reads (and the three position reads of the
         // generation) first, then every MFMA paired with generation VALU work
         // for the next k-step
-        constexpr int kMfmaHalf = (FORM == 1 ? 8 : (FORM == 3 ? 3 : 6)) * 3 * NB;
+        constexpr int kMfmaHalf = (FORM == 1 ? 8 : (FORM == 3 ? 3 : 6)) * NC * NB;
         constexpr int kValuPer = FORM == 1 ? 1 : 2;
         __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 3 * NS * (FORM == 1 ? 2 : 1), 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, NC * NS * (FORM == 1 ? 2 : 1), 0);
 #pragma unroll
             for (int i = 0; i < kMfmaHalf; ++i) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -392,7 +426,7 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
     }
 
     const size_t cstride = (size_t)cap * ldL;
-    float* out = part + (size_t)seg * 3 * cstride;
+    float* out = part + (size_t)seg * NC * cstride;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -400,7 +434,7 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
             const int r = rt * kLpRows + 16 * h + 4 * lk + v;
             if (r < rows) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
+                for (int c = 0; c < NC; ++c)
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
                         out[c * cstride + (size_t)r * ldL + col0 + 16 * b] = acc[c][h][b][v];
@@ -408,10 +442,10 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
         }
 }
 
-// K[c][r][P] = sum_s part[s][c][r][P] in FP64 (fixed order), for r < rows, P < ldP.
+// K[c][r][P] = sum_s part[s][c][r][P] in FP64 (fixed order), for c < nc, r < rows, P < ldP.
 __global__ void k_reduce_K(const float* __restrict__ part, int nseg, int cap, int ldL, int rows, int ldP,
-                           double* __restrict__ K) {
-    const size_t n = (size_t)3 * rows * ldP;
+                           double* __restrict__ K, int nc) {
+    const size_t n = (size_t)nc * rows * ldP;
     const size_t cstride = (size_t)cap * ldL;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const int P = (int)(i % ldP);
@@ -419,7 +453,7 @@ __global__ void k_reduce_K(const float* __restrict__ part, int nseg, int cap, in
         const int r = (int)(cr % rows), c = (int)(cr / rows);
         const size_t o = c * cstride + (size_t)r * ldL + P;
         double s = 0.0;
-        for (int q = 0; q < nseg; ++q) s += (double)part[(size_t)q * 3 * cstride + o];
+        for (int q = 0; q < nseg; ++q) s += (double)part[(size_t)q * nc * cstride + o];
         K[i] = s;
     }
 }
@@ -432,10 +466,12 @@ __global__ void k_reduce_K(const float* __restrict__ part, int nseg, int cap, in
 template <int FORM>
 __global__ __launch_bounds__(256) void k_gemm2b_lp(const void* __restrict__ Clp, const void* __restrict__ Dlp,
                                                    size_t split_stride, int rows32, int ldL, int n_pt,
-                                                   int seg_len, int nseg_r, float* __restrict__ part) {
+                                                   int seg_len, int nseg_r, float* __restrict__ part, int ldP) {
     constexpr int NS = Lp<FORM>::NS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int pt = blockIdx.x % n_pt, rt = blockIdx.x / n_pt;
+    // only P, R < ldP are read by the reduction: tiles entirely beyond it do nothing
+    if (pt * 128 >= ldP || rt * 256 >= ldP) return;
     const int comp = blockIdx.y / nseg_r, sg = blockIdx.y % nseg_r;
     const int gs = sg * seg_len, ge = min(rows32, gs + seg_len);
     const int l16 = lane & 15, lk = lane >> 4;

@@ -254,7 +254,10 @@ xtc_status check_jastrow(const xtc_jastrow* j, JasDev* out) {
         return fail(XTC_E_ARG, "jastrow kind=%d unknown", j->kind);
     }
     d.fb = (float)d.b;
-    for (int k = 0; k < 16; ++k) d.fdcoef[k] = (float)d.dcoef[k];
+    for (int k = 0; k < 16; ++k) {
+        d.fdcoef[k] = (float)d.dcoef[k];
+        d.fd2coef[k] = (float)d.d2coef[k];
+    }
     *out = d;
     return XTC_OK;
 }
@@ -357,11 +360,11 @@ xtc_status pack_any(int form, const double* src, int nrows, int ld_src, int ncol
     }
 }
 
-template <int KIND, int FORM>
+template <int KIND, int FORM, int NC = 3>
 void launch_build_lp(const Layout& L, int g0, int rows, const JasDev& J, void* ws, hipStream_t st) {
     const int n_rt = (rows + kLpRows - 1) / kLpRows;
     const int n_ct = L.ldL / kLpCols;
-    hipLaunchKernelGGL((k_build_K_lp<KIND, FORM>), dim3(n_rt * n_ct * L.nsegK), dim3(kLpThreads), 0, st,
+    hipLaunchKernelGGL((k_build_K_lp<KIND, FORM, NC>), dim3(n_rt * n_ct * L.nsegK), dim3(kLpThreads), 0, st,
                        at<d4>(ws, L.pos), at<void>(ws, L.rho_lp), (size_t)L.ngp * L.ldL, L.ldL, L.ngp, g0, rows, n_rt,
                        kSegK, J, at<float>(ws, L.Kpart), L.cap, L.ldP, n_ct, L.nsegK);
 }
@@ -403,7 +406,7 @@ xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double
     const size_t n = (size_t)3 * rows * L.ldP;
     const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
     hipLaunchKernelGGL(k_reduce_K, dim3(blocks), dim3(256), 0, st, at<float>(ws, L.Kpart), L.nsegK, L.cap, L.ldL,
-                       rows, L.ldP, K);
+                       rows, L.ldP, K, 3);
     if ((s = launched("reduce_K")) != XTC_OK) return s;
     // occupied-occupied pairs in FP64, written over the reduced-precision values:
     // kOccSeg segments of the sum over g' (enough workgroups to fill the chip),
@@ -450,13 +453,13 @@ xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int acc
         }
         if (L.form == 1)
             hipLaunchKernelGGL((k_gemm2b_lp<1>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt,
-                               kSegM, nseg_r, part);
+                               kSegM, nseg_r, part, L.ldP);
         else if (L.form == 3)
             hipLaunchKernelGGL((k_gemm2b_lp<3>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt,
-                               kSegM, nseg_r, part);
+                               kSegM, nseg_r, part, L.ldP);
         else
             hipLaunchKernelGGL((k_gemm2b_lp<6>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt,
-                               kSegM, nseg_r, part);
+                               kSegM, nseg_r, part, L.ldP);
         if ((s = launched("gemm_2body_lp")) != XTC_OK) return s;
         const size_t n = (size_t)L.ldP * L.ldP;
         const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
@@ -807,16 +810,34 @@ xtc_status xtc_tc_2body(const xtc_problem* pb, const xtc_jastrow* jas, const dou
     if ((s = check_range(L, g0, g1)) != XTC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     const int rows = g1 - g0;
-    // F for the chunk rows: scalar kernel S against all g' (FP64)
+    // F for the chunk rows: scalar kernel S against all g', in the arithmetic of
+    // prec (reduced forms: the K-build kernel with one component, segment
+    // partials in the K-build partial buffer, FP64 reduction)
     double* F = at<double>(ws, L.Ftc);
-    const int n_rt = (rows + kKRows - 1) / kKRows;
-    const dim3 gF(n_rt * (L.ldP / 128));
-    if (J.kind == 0)
-        hipLaunchKernelGGL((k_build_F_f64<0, 8>), gF, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
-                           L.ldP, L.ngp, g0, rows, n_rt, J, F);
-    else
-        hipLaunchKernelGGL((k_build_F_f64<1, 8>), gF, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
-                           L.ldP, L.ngp, g0, rows, n_rt, J, F);
+    if (L.form == 0) {
+        const int n_rt = (rows + kKRows - 1) / kKRows;
+        const dim3 gF(n_rt * (L.ldP / 128));
+        if (J.kind == 0)
+            hipLaunchKernelGGL((k_build_F_f64<0, 8>), gF, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
+                               L.ldP, L.ngp, g0, rows, n_rt, J, F);
+        else
+            hipLaunchKernelGGL((k_build_F_f64<1, 8>), gF, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
+                               L.ldP, L.ngp, g0, rows, n_rt, J, F);
+    } else {
+        if (J.kind == 0) {
+            if (L.form == 1) launch_build_lp<0, 1, 1>(L, g0, rows, J, ws, st);
+            else if (L.form == 3) launch_build_lp<0, 3, 1>(L, g0, rows, J, ws, st);
+            else launch_build_lp<0, 6, 1>(L, g0, rows, J, ws, st);
+        } else {
+            if (L.form == 1) launch_build_lp<1, 1, 1>(L, g0, rows, J, ws, st);
+            else if (L.form == 3) launch_build_lp<1, 3, 1>(L, g0, rows, J, ws, st);
+            else launch_build_lp<1, 6, 1>(L, g0, rows, J, ws, st);
+        }
+        if ((s = launched("build_F_lp")) != XTC_OK) return s;
+        const size_t n = (size_t)rows * L.ldP;
+        hipLaunchKernelGGL(k_reduce_K, dim3((unsigned)std::min<size_t>((n + 255) / 256, 16384)), dim3(256), 0, st,
+                           at<float>(ws, L.Kpart), L.nsegK, L.cap, L.ldL, rows, L.ldP, F, 1);
+    }
     if ((s = launched("build_F")) != XTC_OK) return s;
     double* Rg = at<double>(ws, L.Rg);
     const size_t xs = (size_t)L.cap * L.ldN;

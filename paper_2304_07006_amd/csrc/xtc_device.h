@@ -26,6 +26,7 @@ struct JasDev {
     // arguments, so they stay in scalar registers)
     float fb;
     float fdcoef[16];
+    float fd2coef[16];
 };
 
 // u'(r)/r for the electron-electron Jastrow, from r^2; exactly 0 at r^2 == 0
