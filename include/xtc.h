@@ -73,6 +73,14 @@ typedef enum { XTC_FP64 = 0, XTC_FP32 = 1, XTC_BF16X3 = 2, XTC_BF16X6 = 3 } xtc_
  * buffers).  Every call on that workspace must pass the same value. */
 enum { XTC_WITH_BACKWARD = 0x10, XTC_WITH_TC2 = 0x20 };
 
+/* OR-ed into the prec of xtc_build_K only (other calls reject it): in the
+ * reduced forms, keep the occupied-occupied pairs of K in the reduced
+ * arithmetic instead of recomputing them in FP64.  For passes that need no
+ * FP64 zero-body term, such as the TC integrals of xtc_tc_2body, whose
+ * accuracy the reduced form sets anyway; an E0 computed from such K carries
+ * the reduced form's error.  No effect in XTC_FP64. */
+enum { XTC_K_REDUCED_OCC = 0x40 };
+
 /* flags of the contraction calls */
 enum {
     XTC_RESET = 1,       /* zero the accumulator before adding this chunk           */
@@ -156,7 +164,7 @@ xtc_status xtc_prepare(const xtc_problem *pb, int32_t prec, int32_t chunk_rows,
  * K: device [3][g1-g0][ldP] FP64 (columns >= Npair written as 0).
  * The gradient is taken with respect to the first argument of u (the
  * electron sitting on grid point g).  In the reduced forms the occupied-
- * occupied pairs are recomputed in FP64.
+ * occupied pairs are recomputed in FP64 (unless prec has XTC_K_REDUCED_OCC).
  * Errors: XTC_E_ARG for !(0 <= g0 < g1 <= Ng), g1-g0 > chunk_rows of the
  * workspace, bad Jastrow, NULL K. */
 xtc_status xtc_build_K(const xtc_problem *pb, const xtc_jastrow *jas,
@@ -236,8 +244,12 @@ xtc_status xtc_lowdin(int32_t N, int32_t Ng, const double *chi, const double *w,
  * accumulated chunk by chunk like xtc_contract_2body (XTC_RESET, XTC_FINALIZE)
  * into FP64 accumulators in the workspace.  K2 satisfies
  * K2[p][q][r][s] = K2[r][s][p][q] but not the p <-> q symmetry (the integrals
- * are not hermitian).  F, A and B are computed in FP64 in every form (K follows
- * prec).  Needs xtc_prepare with prec | XTC_WITH_TC2.
+ * are not hermitian).  F (the sum over g') and the contractions A and B (sums
+ * over the chunk rows) follow prec like K: FP64, or the reduced form's products
+ * with FP32 partials per segment of rows (of g' for F) and FP64 sums of the
+ * partials; the accumulators across chunks are FP64.  The occupied-occupied
+ * FP64 pass of xtc_build_K is not needed here (XTC_K_REDUCED_OCC).
+ * Needs xtc_prepare with prec | XTC_WITH_TC2.
  * dphi: device [3][N][Ng], the gradients of the orbitals on the grid;
  * K: device [3][g1-g0][ldP]; K2: device [N]^4, may be NULL unless XTC_FINALIZE. */
 xtc_status xtc_tc_2body(const xtc_problem *pb, const xtc_jastrow *jas, const double *dphi,

@@ -459,39 +459,45 @@ __global__ void k_reduce_K(const float* __restrict__ part, int nseg, int cap, in
 }
 
 // --------------------------------------------------------------------------
-// Two-body assembly, reduced precision, one (component, row segment) per grid.y:
-//   part[seg][P][R] = sum_{g in segment} C_c[g][P] D_c[g][R]   (FP32)
-// Workgroup tile 128 (P) x 256 (R), waves 2 x 2 of 64 x 128 (4 x 8 MFMA blocks).
-// Clp/Dlp: [4 comps][NS][n8][ldL][8]; comp_stride = NS * split_stride.
+// Transposed product over grid rows in reduced precision (the two-body
+// assembly and the TC integral contractions), FP32 partials per row segment:
+//   part[y][P][R] = sum_{c in group} sum_{g in segment} C_c[g][P] D_c[g][R]
+// with y = group * nseg_r + segment, group = cpw consecutive components.
+// Clp: [comps][NS][n8][ldC][8], one split c_split elements apart;
+// Dlp: [comps][NS][n8][ldD][8], d_split apart; part[y] is ldC x ldD.
+// Workgroup tile 128 (P) x 256 (R), waves 2 x 2 of 64 x 128 (4 x 8 MFMA
+// blocks); n_pt = ldC / 128 tiles along P, ldD / 256 along R.  Only P < pmax,
+// R < rmax are read by the reduction: tiles entirely beyond do nothing.
 template <int FORM>
-__global__ __launch_bounds__(256) void k_gemm2b_lp(const void* __restrict__ Clp, const void* __restrict__ Dlp,
-                                                   size_t split_stride, int rows32, int ldL, int n_pt,
-                                                   int seg_len, int nseg_r, float* __restrict__ part, int ldP) {
+__global__ __launch_bounds__(256) void k_gemm_tn_lp(const void* __restrict__ Clp, int ldC, size_t c_split,
+                                                    const void* __restrict__ Dlp, int ldD, size_t d_split,
+                                                    int rows32, int n_pt, int pmax, int rmax, int cpw,
+                                                    int seg_len, int nseg_r, float* __restrict__ part) {
     constexpr int NS = Lp<FORM>::NS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int pt = blockIdx.x % n_pt, rt = blockIdx.x / n_pt;
-    // only P, R < ldP are read by the reduction: tiles entirely beyond it do nothing
-    if (pt * 128 >= ldP || rt * 256 >= ldP) return;
-    const int comp = blockIdx.y / nseg_r, sg = blockIdx.y % nseg_r;
+    if (pt * 128 >= pmax || rt * 256 >= rmax) return;
+    const int c0 = (blockIdx.y / nseg_r) * cpw, sg = blockIdx.y % nseg_r;
     const int gs = sg * seg_len, ge = min(rows32, gs + seg_len);
     const int l16 = lane & 15, lk = lane >> 4;
     const int P0 = pt * 128 + 64 * (wave & 1) + l16;
     const int R0 = rt * 256 + 128 * (wave >> 1) + l16;
-    const size_t comp_stride = (size_t)NS * split_stride;
     f4 acc[4][8];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+    for (int comp = c0; comp < c0 + cpw; ++comp)
     for (int kk = gs; kk < ge; kk += kLpK) {
-        const size_t brow = (size_t)(kk / 8 + lk) * ldL;
+        const size_t crow = (size_t)(kk / 8 + lk) * ldC;
+        const size_t drow = (size_t)(kk / 8 + lk) * ldD;
         if constexpr (FORM == 1) {
-            const float* Cb = (const float*)Clp + comp * comp_stride;
-            const float* Db = (const float*)Dlp + comp * comp_stride;
+            const float* Cb = (const float*)Clp + comp * NS * c_split;
+            const float* Db = (const float*)Dlp + comp * NS * d_split;
             float av[4][8];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const f4* p = (const f4*)(Cb + (brow + P0 + 16 * i) * 8);
+                const f4* p = (const f4*)(Cb + (crow + P0 + 16 * i) * 8);
                 const f4 x0 = p[0], x1 = p[1];
                 av[i][0] = x0[0]; av[i][1] = x0[1]; av[i][2] = x0[2]; av[i][3] = x0[3];
                 av[i][4] = x1[0]; av[i][5] = x1[1]; av[i][6] = x1[2]; av[i][7] = x1[3];
@@ -501,7 +507,7 @@ __global__ __launch_bounds__(256) void k_gemm2b_lp(const void* __restrict__ Clp,
                 float bv[4][8];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const f4* p = (const f4*)(Db + (brow + R0 + 16 * (jh + j)) * 8);
+                    const f4* p = (const f4*)(Db + (drow + R0 + 16 * (jh + j)) * 8);
                     const f4 y0 = p[0], y1 = p[1];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) { bv[j][e] = y0[e]; bv[j][4 + e] = y1[e]; }
@@ -515,13 +521,13 @@ __global__ __launch_bounds__(256) void k_gemm2b_lp(const void* __restrict__ Clp,
                             acc[i][jh + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][e], bv[j][e], acc[i][jh + j], 0, 0, 0);
             }
         } else {
-            const __bf16* Cb = (const __bf16*)Clp + comp * comp_stride;
-            const __bf16* Db = (const __bf16*)Dlp + comp * comp_stride;
+            const __bf16* Cb = (const __bf16*)Clp + comp * NS * c_split;
+            const __bf16* Db = (const __bf16*)Dlp + comp * NS * d_split;
             bf8 av[4][NS];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int s = 0; s < NS; ++s) av[i][s] = *(const bf8*)(Cb + s * split_stride + (brow + P0 + 16 * i) * 8);
+                for (int s = 0; s < NS; ++s) av[i][s] = *(const bf8*)(Cb + s * c_split + (crow + P0 + 16 * i) * 8);
 #pragma unroll
             for (int jh = 0; jh < 8; jh += 4) {
                 bf8 bv[4][NS];
@@ -529,7 +535,7 @@ __global__ __launch_bounds__(256) void k_gemm2b_lp(const void* __restrict__ Clp,
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
                     for (int s = 0; s < NS; ++s)
-                        bv[j][s] = *(const bf8*)(Db + s * split_stride + (brow + R0 + 16 * (jh + j)) * 8);
+                        bv[j][s] = *(const bf8*)(Db + s * d_split + (drow + R0 + 16 * (jh + j)) * 8);
 #pragma unroll
                 for (int t = 0; t < Terms<FORM>::n; ++t)
 #pragma unroll
@@ -540,28 +546,29 @@ __global__ __launch_bounds__(256) void k_gemm2b_lp(const void* __restrict__ Clp,
             }
         }
     }
-    float* out = part + (size_t)blockIdx.y * ldL * ldL;
+    float* out = part + (size_t)blockIdx.y * ldC * ldD;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int P = P0 - l16 + 16 * i + 4 * lk + v;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) out[(size_t)P * ldL + R0 + 16 * j] = acc[i][j][v];
+            for (int j = 0; j < 8; ++j) out[(size_t)P * ldD + R0 + 16 * j] = acc[i][j][v];
         }
 }
 
-// M[P][R] (+)= sum_s part[s][P][R] in FP64 (fixed order), P, R < ldP.
-__global__ void k_reduce_M(const float* __restrict__ part, int nseg, int ldL, int ldP, double* __restrict__ M,
-                           int accumulate) {
-    const size_t n = (size_t)ldP * ldP;
-    const size_t sstride = (size_t)ldL * ldL;
+// M[P][R] (+)= sum_s part[s][P][R] in FP64 (fixed order), P < pmax, R < rmax;
+// part[s] has leading dimension ldpart and starts sstride floats after part[s-1].
+__global__ void k_reduce_M(const float* __restrict__ part, int nseg, size_t sstride, int ldpart, int pmax, int rmax,
+                           double* __restrict__ M, int ldM, int accumulate) {
+    const size_t n = (size_t)pmax * rmax;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t P = i / ldP, R = i % ldP;
-        const size_t o = P * ldL + R;
-        double s = accumulate ? M[i] : 0.0;
+        const size_t P = i / rmax, R = i % rmax;
+        const size_t o = P * ldpart + R;
+        double* m = M + P * ldM + R;
+        double s = accumulate ? *m : 0.0;
         for (int q = 0; q < nseg; ++q) s += (double)part[q * sstride + o];
-        M[i] = s;
+        *m = s;
     }
 }
 

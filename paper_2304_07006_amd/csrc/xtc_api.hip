@@ -15,7 +15,7 @@
 //   D      [4][cap][ldP] doubles      A, Bx, By, Bz of the current chunk
 //   Kpart  [nsegK][3][cap][ldL] f32   K-build segment partials     (prec != FP64)
 //   CDlp   [8][NS][cap/8][ldL][8]     C and D of the chunk, k8-packed (prec != FP64)
-//   Mpart  [4*ceil(cap/kSegM)][ldL][ldL] f32  two-body partials    (prec != FP64)
+//   Mpart  [ceil(cap/kSegM)][4][ldL][ldL] f32  two-body partials   (prec != FP64)
 // and with XTC_WITH_BACKWARD in prec (the adjoint reuses M for Gbar):
 //   Kc [3][cap][ldP], Y [7][cap][ldP], T [cap][3][N][nocc], Wbar [cap][3],
 //   gpart [ceil(cap/32) * ngp/128][16], gacc [16], occw [N] f64, kidx [N]
@@ -88,7 +88,8 @@ struct Layout {
     size_t fixed;        // bytes before S (plus the Mpart remainder reserve)
     size_t per_row;      // bytes per chunk row
     int cap;             // chunk rows that fit (multiple of kRowQuant)
-    int nsegM;
+    size_t mslab;        // bytes of the two-body partials of one kSegM-row segment
+    size_t cdw;          // packed operand elements per row and split (CDlp)
     size_t S, D, Kpart, CDlp, Mpart, Kocc, Kc, Y, T, Wbar, gpart, KbL, Ftc, Rg, end;
 };
 
@@ -155,13 +156,18 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.Atc = off;     off = align_up(off + (L.tc2 ? (size_t)L.ldP * L.ldP * sizeof(double) : 0), kAlign);
     L.Btc = off;     off = align_up(off + (L.tc2 ? (size_t)L.ldN * L.ldP * sizeof(double) : 0), kAlign);
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);   // one 32-row tile of partials
-    const size_t mslab = (size_t)4 * L.ldL * L.ldL * sizeof(float);       // one partial per component
-    L.fixed = off + (lp ? mslab : 0) + (L.bwd ? gslab : 0) + 16 * kAlign;
+    // partials of one row segment: the four components of the two-body GEMM, or
+    // the TC integrals' B (three components summed in one partial)
+    L.mslab = lp ? std::max((size_t)4 * L.ldL * L.ldL, L.tc2 ? (size_t)L.ldN * L.ldL : 0) * sizeof(float) : 0;
+    // packed operands: C and D of the two-body GEMM (8 components of ldL), or
+    // w phi grad phi (3 of ldN) and K (3 of ldL) of the TC integrals
+    L.cdw = std::max((size_t)8 * L.ldL, L.tc2 ? (size_t)3 * L.ldN + (size_t)3 * L.ldL : 0);
+    const size_t mslab = L.mslab;
+    L.fixed = off + mslab + (L.bwd ? gslab : 0) + 16 * kAlign;
     L.per_row = (size_t)L.nspin * (8 * sizeof(double) + (size_t)4 * L.ldP * sizeof(double));
     if (lp) L.per_row += (size_t)kOccSeg * 3 * L.ldO * sizeof(double);
     if (lp)
-        L.per_row += (size_t)L.nsegK * 3 * L.ldL * sizeof(float) + (size_t)8 * L.ns * L.ldL * L.es +
-                     (mslab + kSegM - 1) / kSegM;
+        L.per_row += (size_t)L.nsegK * 3 * L.ldL * sizeof(float) + L.cdw * L.ns * L.es + (mslab + kSegM - 1) / kSegM;
     if (L.tc2) L.per_row += (size_t)L.ldP * sizeof(double) + (size_t)3 * L.ldN * sizeof(double);
     if (L.bwd)
         L.per_row += (size_t)10 * L.ldP * sizeof(double) + (size_t)3 * L.N * L.nocc * sizeof(double) +
@@ -178,14 +184,13 @@ void place_chunk(Layout& L, size_t bytes) {
     if (cap > most) cap = most;
     L.cap = (int)cap;
     const bool lp = L.form != 0;
-    L.nsegM = lp ? 4 * (int)((cap + kSegM - 1) / kSegM) : 0;
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);
-    size_t off = L.fixed - 16 * kAlign - (lp ? (size_t)4 * L.ldL * L.ldL * sizeof(float) : 0) - (L.bwd ? gslab : 0);
+    size_t off = L.fixed - 16 * kAlign - L.mslab - (L.bwd ? gslab : 0);
     L.S = off;       off = align_up(off + (size_t)L.nspin * cap * 8 * sizeof(double), kAlign);
     L.D = off;       off = align_up(off + (size_t)L.nspin * 4 * cap * L.ldP * sizeof(double), kAlign);
     L.Kpart = off;   off = align_up(off + (lp ? (size_t)L.nsegK * 3 * cap * L.ldL * sizeof(float) : 0), kAlign);
-    L.CDlp = off;    off = align_up(off + (lp ? (size_t)8 * L.ns * cap * L.ldL * L.es : 0), kAlign);
-    L.Mpart = off;   off = align_up(off + (lp ? (size_t)L.nsegM * L.ldL * L.ldL * sizeof(float) : 0), kAlign);
+    L.CDlp = off;    off = align_up(off + (lp ? L.cdw * L.ns * cap * L.es : 0), kAlign);
+    L.Mpart = off;   off = align_up(off + (size_t)((cap + kSegM - 1) / kSegM) * L.mslab, kAlign);
     L.Kocc = off;    off = align_up(off + (lp ? (size_t)kOccSeg * 3 * cap * L.ldO * sizeof(double) : 0), kAlign);
     const bool b = L.bwd;
     L.Kc = off;      off = align_up(off + (b ? (size_t)3 * cap * L.ldP * sizeof(double) : 0), kAlign);
@@ -391,7 +396,8 @@ void launch_build_occ(const Layout& L, int g0, int rows, int n_rt, int nseg, int
     }
 }
 
-xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double* K, void* ws, hipStream_t st) {
+xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double* K, bool occ64, void* ws,
+                      hipStream_t st) {
     if (J.kind == 0) {
         if (L.form == 1) launch_build_lp<0, 1>(L, g0, rows, J, ws, st);
         else if (L.form == 3) launch_build_lp<0, 3>(L, g0, rows, J, ws, st);
@@ -408,6 +414,7 @@ xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double
     hipLaunchKernelGGL(k_reduce_K, dim3(blocks), dim3(256), 0, st, at<float>(ws, L.Kpart), L.nsegK, L.cap, L.ldL,
                        rows, L.ldP, K, 3);
     if ((s = launched("reduce_K")) != XTC_OK) return s;
+    if (!occ64) return XTC_OK;
     // occupied-occupied pairs in FP64, written over the reduced-precision values:
     // kOccSeg segments of the sum over g' (enough workgroups to fill the chip),
     // FP64 partials, then a fixed-order reduction scattered into K
@@ -424,6 +431,37 @@ xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double
     return launched("reduce_occ");
 }
 
+// part[y] = C^T D over one row segment of kSegM rows and a group of cpw of the
+// ncomp components, y = group * nseg_r + segment (k_gemm_tn_lp); returns the
+// number of partials written through *nparts.
+xtc_status gemm_tn_lp(int form, const void* C, int ldC, size_t c_split, const void* D, int ldD, size_t d_split,
+                      int rows32, int pmax, int rmax, int ncomp, int cpw, float* part, int* nparts, hipStream_t st) {
+    const int n_pt = ldC / 128, n_rt = ldD / 256;
+    const int nseg_r = (rows32 + kSegM - 1) / kSegM;
+    const dim3 grid(n_pt * n_rt, (ncomp / cpw) * nseg_r);
+    if (form == 1)
+        hipLaunchKernelGGL((k_gemm_tn_lp<1>), grid, dim3(256), 0, st, C, ldC, c_split, D, ldD, d_split, rows32, n_pt,
+                           pmax, rmax, cpw, kSegM, nseg_r, part);
+    else if (form == 3)
+        hipLaunchKernelGGL((k_gemm_tn_lp<3>), grid, dim3(256), 0, st, C, ldC, c_split, D, ldD, d_split, rows32, n_pt,
+                           pmax, rmax, cpw, kSegM, nseg_r, part);
+    else
+        hipLaunchKernelGGL((k_gemm_tn_lp<6>), grid, dim3(256), 0, st, C, ldC, c_split, D, ldD, d_split, rows32, n_pt,
+                           pmax, rmax, cpw, kSegM, nseg_r, part);
+    *nparts = (int)grid.y;
+    return launched("gemm_tn_lp");
+}
+
+// M[P][R] (+)= sum of nparts partials of ldC x ldD floats, P < pmax, R < rmax.
+xtc_status reduce_parts(const float* part, int nparts, int ldC, int ldD, int pmax, int rmax, double* M, int ldM,
+                        int accumulate, hipStream_t st) {
+    const size_t n = (size_t)pmax * rmax;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_reduce_M, dim3(blocks), dim3(256), 0, st, part, nparts, (size_t)ldC * ldD, ldD, pmax, rmax, M,
+                       ldM, accumulate);
+    return launched("reduce_M");
+}
+
 xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int accumulate, void* ws, hipStream_t st) {
     xtc_status s;
     const int rows32 = (int)align_up((size_t)rows, kRowQuant);
@@ -437,11 +475,6 @@ xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int acc
         if ((s = pack_any(L.form, src, rows, L.ldP, L.ldP, n8, L.ldL, cd + c * comp_bytes, split_stride, st)) != XTC_OK)
             return s;
     }
-    const int n_pt = L.ldL / 128, n_rt = L.ldL / 256;
-    const int nseg_r = (rows32 + kSegM - 1) / kSegM;
-    const dim3 grid(n_pt * n_rt, 4 * nseg_r);
-    const void* C = cd;
-    const void* Dl = cd + 4 * comp_bytes;
     float* part = at<float>(ws, L.Mpart);
     // one spin channel at a time: its D into the operand buffer, GEMM, reduction into M^s
     for (int sp = 0; sp < L.nspin; ++sp) {
@@ -451,21 +484,13 @@ xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int acc
                               cd + (4 + c) * comp_bytes, split_stride, st)) != XTC_OK)
                 return s;
         }
-        if (L.form == 1)
-            hipLaunchKernelGGL((k_gemm2b_lp<1>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt,
-                               kSegM, nseg_r, part, L.ldP);
-        else if (L.form == 3)
-            hipLaunchKernelGGL((k_gemm2b_lp<3>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt,
-                               kSegM, nseg_r, part, L.ldP);
-        else
-            hipLaunchKernelGGL((k_gemm2b_lp<6>), grid, dim3(256), 0, st, C, Dl, split_stride, rows32, L.ldL, n_pt,
-                               kSegM, nseg_r, part, L.ldP);
-        if ((s = launched("gemm_2body_lp")) != XTC_OK) return s;
-        const size_t n = (size_t)L.ldP * L.ldP;
-        const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
-        hipLaunchKernelGGL(k_reduce_M, dim3(blocks), dim3(256), 0, st, part, 4 * nseg_r, L.ldL, L.ldP,
-                           at<double>(ws, L.M) + (size_t)sp * L.ldP * L.ldP, accumulate);
-        if ((s = launched("reduce_M")) != XTC_OK) return s;
+        int np = 0;
+        if ((s = gemm_tn_lp(L.form, cd, L.ldL, split_stride, cd + 4 * comp_bytes, L.ldL, split_stride, rows32, L.ldP,
+                            L.ldP, 4, 1, part, &np, st)) != XTC_OK)
+            return s;
+        if ((s = reduce_parts(part, np, L.ldL, L.ldL, L.ldP, L.ldP, at<double>(ws, L.M) + (size_t)sp * L.ldP * L.ldP,
+                              L.ldP, accumulate, st)) != XTC_OK)
+            return s;
     }
     return XTC_OK;
 }
@@ -478,8 +503,9 @@ xtc_status split_rows_any(int form, const double* src, size_t n, void* dst, size
     return launched("split_rows");
 }
 
-xtc_status build_K_any(const Layout& L, const JasDev& J, int g0, int rows, double* K, void* ws, hipStream_t st) {
-    if (L.form != 0) return build_K_lp(L, g0, rows, J, K, ws, st);
+xtc_status build_K_any(const Layout& L, const JasDev& J, int g0, int rows, double* K, bool occ64, void* ws,
+                       hipStream_t st) {
+    if (L.form != 0) return build_K_lp(L, g0, rows, J, K, occ64, ws, st);
     const int n_rt = (rows + kKRows - 1) / kKRows;
     const int n_ct = L.ldP / 128;
     const dim3 grid(n_rt * n_ct);
@@ -556,6 +582,8 @@ xtc_status xtc_build_K(const xtc_problem* pb, const xtc_jastrow* jas, int32_t g0
                        double* K, void* ws, size_t ws_bytes, void* stream) {
     xtc_status s;
     JasDev J;
+    const bool occ64 = !(prec & XTC_K_REDUCED_OCC);
+    prec &= ~XTC_K_REDUCED_OCC;
     if ((s = check_problem(pb)) != XTC_OK) return s;
     if ((s = check_prec(prec)) != XTC_OK) return s;
     if ((s = check_jastrow(jas, &J)) != XTC_OK) return s;
@@ -565,7 +593,7 @@ xtc_status xtc_build_K(const xtc_problem* pb, const xtc_jastrow* jas, int32_t g0
     place_chunk(L, ws_bytes);
     if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
     if ((s = check_range(L, g0, g1)) != XTC_OK) return s;
-    return build_K_any(L, J, g0, g1 - g0, K, ws, (hipStream_t)stream);
+    return build_K_any(L, J, g0, g1 - g0, K, occ64, ws, (hipStream_t)stream);
 }
 
 xtc_status xtc_contract_2body(const xtc_problem* pb, const double* K, int32_t g0, int32_t g1, int32_t prec,
@@ -700,7 +728,7 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
     for (int g0 = 0; g0 < L.Ng; g0 += L.cap) {
         const int rows = std::min(L.cap, L.Ng - g0);
         const bool last = g0 + rows >= L.Ng;
-        if ((s = build_K_any(L, J, g0, rows, Kc, ws, st)) != XTC_OK) return s;
+        if ((s = build_K_any(L, J, g0, rows, Kc, true, ws, st)) != XTC_OK) return s;
         if ((s = run_intermediates(L, pb, Kc, g0, g0 + rows, ws, st)) != XTC_OK) return s;
         const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
         const double* D = at<double>(ws, L.D);
@@ -846,18 +874,51 @@ xtc_status xtc_tc_2body(const xtc_problem* pb, const xtc_jastrow* jas, const dou
                        pb->phi, dphi, L.N, L.Ng, g0, rows, L.ldN, xs, Rg);
     if ((s = launched("rhog")) != XTC_OK) return s;
     const int acc = (flags & XTC_RESET) ? 0 : 1;
-    const int nP = L.ldP / 128, nN = L.ldN / 128;
     const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
-    hipLaunchKernelGGL(k_gemm_tn_f64, dim3(nP * nP), dim3(256), 0, st, rho_rows, (size_t)0, L.ldP, F, (size_t)0, L.ldP,
-                       1, rows, nP, at<double>(ws, L.Atc), L.ldP, acc);
-    if ((s = launched("gemm_tc_A")) != XTC_OK) return s;
-    hipLaunchKernelGGL(k_gemm_tn_f64, dim3(nN * nP), dim3(256), 0, st, Rg, xs, L.ldN, K, (size_t)rows * L.ldP, L.ldP,
-                       3, rows, nN, at<double>(ws, L.Btc), L.ldP, acc);
-    if ((s = launched("gemm_tc_B")) != XTC_OK) return s;
+    double* Atc = at<double>(ws, L.Atc);
+    double* Btc = at<double>(ws, L.Btc);
+    if (L.form == 0) {
+        const int nP = L.ldP / 128, nN = L.ldN / 128;
+        hipLaunchKernelGGL(k_gemm_tn_f64, dim3(nP * nP), dim3(256), 0, st, rho_rows, (size_t)0, L.ldP, F, (size_t)0,
+                           L.ldP, 1, rows, nP, Atc, L.ldP, acc);
+        if ((s = launched("gemm_tc_A")) != XTC_OK) return s;
+        hipLaunchKernelGGL(k_gemm_tn_f64, dim3(nN * nP), dim3(256), 0, st, Rg, xs, L.ldN, K, (size_t)rows * L.ldP,
+                           L.ldP, 3, rows, nN, Btc, L.ldP, acc);
+        if ((s = launched("gemm_tc_B")) != XTC_OK) return s;
+    } else {
+        // reduced forms: both contractions as split products over the chunk rows,
+        // FP32 partials per kSegM rows, FP64 reduction into the accumulators
+        const int rows32 = (int)align_up((size_t)rows, kRowQuant);
+        const int n8 = rows32 / 8;
+        char* cd = at<char>(ws, L.CDlp);
+        float* part = at<float>(ws, L.Mpart);
+        const size_t sL = (size_t)L.cap * L.ldL, sN = (size_t)L.cap * L.ldN;   // elements of one split
+        const size_t cL = (size_t)L.ns * sL * L.es, cN = (size_t)L.ns * sN * L.es;   // bytes of one component
+        int np = 0;
+        if ((s = pack_any(L.form, rho_rows, rows, L.ldP, L.ldP, n8, L.ldL, cd, sL, st)) != XTC_OK) return s;
+        if ((s = pack_any(L.form, F, rows, L.ldP, L.ldP, n8, L.ldL, cd + cL, sL, st)) != XTC_OK) return s;
+        if ((s = gemm_tn_lp(L.form, cd, L.ldL, sL, cd + cL, L.ldL, sL, rows32, L.ldP, L.ldP, 1, 1, part, &np, st)) !=
+            XTC_OK)
+            return s;
+        if ((s = reduce_parts(part, np, L.ldL, L.ldL, L.ldP, L.ldP, Atc, L.ldP, acc, st)) != XTC_OK) return s;
+        char* kd = cd + 3 * cN;
+        for (int x = 0; x < 3; ++x) {
+            if ((s = pack_any(L.form, Rg + x * xs, rows, L.ldN, L.ldN, n8, L.ldN, cd + x * cN, sN, st)) != XTC_OK)
+                return s;
+            if ((s = pack_any(L.form, K + (size_t)x * rows * L.ldP, rows, L.ldP, L.ldP, n8, L.ldL, kd + x * cL, sL,
+                              st)) != XTC_OK)
+                return s;
+        }
+        // the three components of rhog_pq . K_R summed inside each workgroup
+        if ((s = gemm_tn_lp(L.form, cd, L.ldN, sN, kd, L.ldL, sL, rows32, L.N * L.N, L.ldP, 3, 3, part, &np, st)) !=
+            XTC_OK)
+            return s;
+        if ((s = reduce_parts(part, np, L.ldN, L.ldL, L.N * L.N, L.ldP, Btc, L.ldP, acc, st)) != XTC_OK) return s;
+    }
     if (flags & XTC_FINALIZE) {
         const int NN = L.N * L.N;
-        hipLaunchKernelGGL(k_finalize_K2, dim3((NN + 255) / 256, L.N, L.N), dim3(256), 0, st, at<double>(ws, L.Atc),
-                           L.ldP, at<double>(ws, L.Btc), L.N, K2);
+        hipLaunchKernelGGL(k_finalize_K2, dim3((NN + 255) / 256, L.N, L.N), dim3(256), 0, st, Atc, L.ldP, Btc, L.N,
+                           K2);
         if ((s = launched("finalize_K2")) != XTC_OK) return s;
     }
     return XTC_OK;

@@ -21,6 +21,7 @@ XTC_FP64, XTC_FP32, XTC_BF16X3, XTC_BF16X6 = 0, 1, 2, 3
 XTC_RESET, XTC_FINALIZE = 1, 2
 XTC_WITH_BACKWARD = 0x10
 XTC_WITH_TC2 = 0x20
+XTC_K_REDUCED_OCC = 0x40
 PRECISIONS = {"fp64": XTC_FP64, "fp32": XTC_FP32, "bf16x3": XTC_BF16X3, "bf16x6": XTC_BF16X6}
 
 
@@ -304,7 +305,7 @@ def tc_two_body(problem, dphi, prec="fp64", chunk_rows=None, device="cuda", jast
     for i, (g0, g1) in enumerate(ch):
         flags = (XTC_RESET if i == 0 else 0) | (XTC_FINALIZE if i == len(ch) - 1 else 0)
         K = Kbuf[:3 * (g1 - g0) * ldP]
-        xtc_build_K(dp, jas, g0, g1, p, K, ws, stream)
+        xtc_build_K(dp, jas, g0, g1, p | XTC_K_REDUCED_OCC, K, ws, stream)
         _check(L.xtc_tc_2body(ctypes.byref(dp.c), ctypes.byref(jas), _ptr(dphi_t), _ptr(K), g0, g1, p, flags,
                               _ptr(K2), _ptr(ws), ws.numel(), _stream(stream)))
     return K2
