@@ -223,6 +223,62 @@ def run_tc2(problem, prec, chunk, steps, warmup):
     return (time.perf_counter() - t0) / steps, K2
 
 
+def f_backward(N, Ng):
+    """Algorithmic flops of the adjoint as built: the K recompute and the Pi
+    contraction (6 Ng^2 Npair each) and the seven X . Gbar products
+    (2 Ng Npair^2 each)."""
+    P = N * (N + 1) // 2
+    return 12 * Ng * Ng * P + 14 * Ng * P * P
+
+
+def run_backward(problem, prec, chunk, aux_seed, steps, warmup):
+    """Forward pass and adjoint (xtc_backward, K recomputed) of the loss
+    L = E0 + <h1, D> + <V2, G>, D symmetric and G 8-fold symmetric, seeded on
+    the device.  Returns seconds per forward and per backward, the gradient,
+    and the Euler check |c . dL/dc - 2 L| / |2 L| (L is homogeneous of degree 2
+    in the power-Jastrow coefficients)."""
+    import torch
+    from paper_2304_07006_amd import xtc
+    N = problem.N
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(aux_seed + 7)
+    X = torch.randn((N, N), generator=gen, device="cuda", dtype=torch.float64)
+    D = 0.5 * (X + X.T)
+    G = torch.randn((N, N, N, N), generator=gen, device="cuda", dtype=torch.float64)
+    G = 0.25 * (G + G.permute(1, 0, 2, 3) + G.permute(0, 1, 3, 2) + G.permute(1, 0, 3, 2))
+    G = (0.5 * (G + G.permute(2, 3, 0, 1))).contiguous()
+    coef = [float(c) for c in problem.jastrow.coef]
+    jas = xtc.power_jastrow(coef)
+    dp = xtc.device_problem(problem.xyz, problem.w, problem.phi, problem.occ)
+    ps = xtc.Pass(dp, xtc.PRECISIONS[prec], chunk)
+    pb = xtc.PRECISIONS[prec] | xtc.XTC_WITH_BACKWARD
+    ws = torch.empty(xtc.xtc_workspace_size(dp, pb, chunk), dtype=torch.uint8, device="cuda")
+    gc = torch.empty(len(coef), dtype=torch.float64, device="cuda")
+
+    def bwd():
+        xtc.xtc_prepare(dp, pb, chunk, ws)
+        xtc.xtc_backward(dp, jas, pb, G, D, 1.0, gc, ws)
+
+    for _ in range(warmup):
+        ps.run(jas)
+        bwd()
+    torch.cuda.synchronize()
+    tf = tb = 0.0
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        ps.run(jas)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        bwd()
+        torch.cuda.synchronize()
+        tf += t1 - t0
+        tb += time.perf_counter() - t1
+    L = ps.E0[0].item() + (ps.h1 * D).sum().item() + (ps.V2 * G).sum().item()
+    g = gc.cpu().numpy()
+    euler = abs(float(sum(c * x for c, x in zip(coef, g))) - 2 * L) / abs(2 * L)
+    return tf / steps, tb / steps, g, euler, torch.cuda.max_memory_allocated()
+
+
 def cpu_baseline(name, budget_rows):
     """The oracle (Appendix-B equations, numpy FP64) on the same workload's
     orbitals and generator, on a reduced grid of `budget_rows` points."""
@@ -258,6 +314,9 @@ def main():
                     help="reference density: closed | sa:ND,NS | natural:NACT (see apply_density)")
     ap.add_argument("--tc2", action="store_true",
                     help="time the two-body TC integrals (K build + xtc_tc_2body) instead of the xTC folding")
+    ap.add_argument("--backward", action="store_true",
+                    help="time forward + adjoint (xtc_backward) on a power-Jastrow workload "
+                         "(default workload then N96-occ12-Ng100k)")
     ap.add_argument("--probe", action="store_true",
                     help="counter pass: one 1 GiB device copy (calibration) and one K-build launch, no JSON")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -279,6 +338,8 @@ def main():
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.backward and args.workload == ap.get_default("workload"):
+        args.workload = "N96-occ12-Ng100k"
     wl = inputs.WORKLOADS[args.workload]
     problem = inputs.make_workload(args.workload)
     density = apply_density(problem, args.density)
@@ -286,6 +347,24 @@ def main():
     chunk = args.chunk or default_chunk(wl.Ng, args.prec)
     if args.probe:
         probe(problem, args.prec, chunk)
+        return
+    if args.backward:
+        if wl.jastrow_kind == "pade":
+            print("the adjoint needs a power-Jastrow workload", file=sys.stderr)
+            sys.exit(2)
+        Ff, Fb = f_alg(wl.N, wl.nocc, wl.Ng), f_backward(wl.N, wl.Ng)
+        print(f"[bench] backward {args.workload} prec={args.prec} chunk={chunk}", file=sys.stderr, flush=True)
+        tf, tb, g, euler, peak_mem = run_backward(problem, args.prec, chunk, wl.aux_seed, args.steps, args.warmup)
+        line = {"metric": "xTC forward + adjoint GFLOP/s (loss E0 + <h1,D> + <V2,G>, gradient in the Jastrow coefficients)",
+                "value": (Ff + Fb) / (tf + tb) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": (tf + tb) * 1e3, "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": DTYPE[args.prec], "data": "synthetic",
+                "config": {"workload": args.workload, "N": wl.N, "nocc": wl.nocc, "Ng": wl.Ng, "prec": args.prec,
+                           "chunk_rows": chunk, "F_fwd": Ff, "F_bwd": Fb},
+                "forward_s": tf, "backward_s": tb, "forward_tflops": Ff / tf / 1e12,
+                "backward_tflops": Fb / tb / 1e12, "euler_rel": euler, "peak_device_bytes": peak_mem,
+                "grad_head": [float(x) for x in g[:4]]}
+        print(json.dumps(line), flush=True)
         return
     if args.tc2:
         P = wl.N * (wl.N + 1) // 2

@@ -331,15 +331,28 @@ __global__ __launch_bounds__(256) void k_pi_grad(const double* __restrict__ Kbar
             red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
-// acc[j] (+)= sum_b part[b][j], fixed order; with `out`, also write acc to out.
-__global__ void k_reduce_grad(const double* __restrict__ part, int nblk, int ncoef, double* __restrict__ acc,
-                              int accumulate, double* __restrict__ out) {
-    const int j = threadIdx.x;
+// acc[j] (+)= sum_b part[b][j] for j = blockIdx.x < ncoef, in a fixed order:
+// thread t sums b = t, t + 256, ... serially, then a fixed tree over the 256
+// thread sums; with `out`, also write acc[j] to out[j].  Launch: ncoef x 256.
+__global__ __launch_bounds__(256) void k_reduce_grad(const double* __restrict__ part, int nblk, int ncoef,
+                                                     double* __restrict__ acc, int accumulate,
+                                                     double* __restrict__ out) {
+    const int j = blockIdx.x;
     if (j >= ncoef) return;
-    double s = accumulate ? acc[j] : 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * kGradMax + j];
-    acc[j] = s;
-    if (out) out[j] = s;
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += part[(size_t)b * kGradMax + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double v = (accumulate ? acc[j] : 0.0) + red[0];
+        acc[j] = v;
+        if (out) out[j] = v;
+    }
 }
 
 }  // namespace xtc

@@ -637,16 +637,36 @@ __global__ void k_split_rows(const double* __restrict__ src, size_t n, void* __r
     }
 }
 
-// Reduced-precision Pi tiles with the gradient epilogue (see k_pi_grad):
+// Gradient epilogue of one Pi value: dL/dc_j gains j t^(j-1) q^2 / r times
+// (r_g - r_g') . Pi(g,g') (power Jastrow, u' = sum_j j c_j t^(j-1) q^2 with
+// t = r q, q = 1/(1+r)); FP64, coincident points skipped.
+__device__ __forceinline__ void pi_grad_point(const d4& pi, const d4& pj, float px, float py, float pz,
+                                              double (&gsum)[16]) {
+    const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    if (!(r2 > 0.0)) return;
+    const double r = sqrt(r2);
+    const double q = 1.0 / (1.0 + r);
+    const double t = r * q;
+    double tp = (dx * (double)px + dy * (double)py + dz * (double)pz) * q * q / r;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        gsum[j] = fma((double)(j + 1), tp, gsum[j]);
+        tp *= t;
+    }
+}
+
+// FP32 Pi tiles with the gradient epilogue (see k_pi_grad):
 // Pi^x(g,g') = sum_P Kbar^x[g][P] rho[g'][P] with FP32 accumulation over all
 // pairs; workgroup 4 waves as 2 (g) x 2 (g'), wave tile 16 g x 128 g' x 3.
-// Kb: [3][NS][rows][ldP], rr: [NS][ngp][ldP] (row-major splits).
+// Kb: [3][rows][ldP], rr: [ngp][ldP] (row-major).  The split-BF16 forms use
+// k_pi_grad_bf16.
 template <int FORM>
 __global__ __launch_bounds__(256) void k_pi_grad_lp(const void* __restrict__ Kb, size_t kb_comp, size_t kb_split,
                                                     int rows, const void* __restrict__ rr, size_t rr_split,
                                                     int ldP, const d4* __restrict__ pos, int g0, int ngp, int n_jt,
                                                     int ncoef, double* __restrict__ part) {
-    constexpr int NS = Lp<FORM>::NS;
+    static_assert(FORM == 1, "FP32 form only");
     constexpr int NB = 8;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int it = blockIdx.x / n_jt, jt = blockIdx.x % n_jt;
@@ -662,51 +682,26 @@ __global__ __launch_bounds__(256) void k_pi_grad_lp(const void* __restrict__ Kb,
 #pragma unroll
     for (int b = 0; b < NB; ++b) jrow[b] = (size_t)min(j0 + 16 * b + l16, ngp - 1);
     for (int k = 0; k < ldP; k += kLpK) {
-        if constexpr (FORM == 1) {
-            const float* A = (const float*)Kb;
-            const float* B = (const float*)rr;
-            float av[3][8];
+        const float* A = (const float*)Kb;
+        const float* B = (const float*)rr;
+        float av[3][8];
 #pragma unroll
-            for (int x = 0; x < 3; ++x) {
-                const f4* p = (const f4*)(A + x * kb_comp + irow * ldP + k + kq);
-                const f4 y0 = p[0], y1 = p[1];
+        for (int x = 0; x < 3; ++x) {
+            const f4* p = (const f4*)(A + x * kb_comp + irow * ldP + k + kq);
+            const f4 y0 = p[0], y1 = p[1];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) { av[x][e] = y0[e]; av[x][4 + e] = y1[e]; }
-            }
+            for (int e = 0; e < 4; ++e) { av[x][e] = y0[e]; av[x][4 + e] = y1[e]; }
+        }
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const f4* p = (const f4*)(B + jrow[b] * ldP + k + kq);
-                const f4 y0 = p[0], y1 = p[1];
-                const float bv[8] = {y0[0], y0[1], y0[2], y0[3], y1[0], y1[1], y1[2], y1[3]};
+        for (int b = 0; b < NB; ++b) {
+            const f4* p = (const f4*)(B + jrow[b] * ldP + k + kq);
+            const f4 y0 = p[0], y1 = p[1];
+            const float bv[8] = {y0[0], y0[1], y0[2], y0[3], y1[0], y1[1], y1[2], y1[3]};
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
+            for (int e = 0; e < 8; ++e)
 #pragma unroll
-                    for (int x = 0; x < 3; ++x)
-                        acc[x][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x][e], bv[e], acc[x][b], 0, 0, 0);
-            }
-        } else {
-            const __bf16* A = (const __bf16*)Kb;
-            const __bf16* B = (const __bf16*)rr;
-            bf8 av[3][NS];
-#pragma unroll
-            for (int x = 0; x < 3; ++x)
-#pragma unroll
-                for (int s = 0; s < NS; ++s) av[x][s] = *(const bf8*)(A + x * kb_comp + s * kb_split + irow * ldP + k + kq);
-#pragma unroll
-            for (int bh = 0; bh < NB; bh += 4) {
-                bf8 bv[4][NS];
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-#pragma unroll
-                    for (int s = 0; s < NS; ++s) bv[b][s] = *(const bf8*)(B + s * rr_split + jrow[bh + b] * ldP + k + kq);
-#pragma unroll
-                for (int t = 0; t < Terms<FORM>::n; ++t)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b)
-#pragma unroll
-                        for (int x = 0; x < 3; ++x)
-                            acc[x][bh + b] = mma_bf16(av[x][Terms<FORM>::a[t]], bv[b][Terms<FORM>::b[t]], acc[x][bh + b]);
-            }
+                for (int x = 0; x < 3; ++x)
+                    acc[x][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x][e], bv[e], acc[x][b], 0, 0, 0);
         }
     }
     double gsum[16];
@@ -721,20 +716,7 @@ __global__ __launch_bounds__(256) void k_pi_grad_lp(const void* __restrict__ Kb,
         for (int b = 0; b < NB; ++b) {
             const int jg = j0 + 16 * b + l16;
             if (jg >= ngp) continue;
-            const d4 pj = pos[jg];
-            const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            if (!(r2 > 0.0)) continue;
-            const double r = sqrt(r2);
-            const double q = 1.0 / (1.0 + r);
-            const double t = r * q;
-            const double s = (dx * (double)acc[0][b][v] + dy * (double)acc[1][b][v] + dz * (double)acc[2][b][v]) * q * q / r;
-            double tp = s;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                gsum[j] = fma((double)(j + 1), tp, gsum[j]);
-                tp *= t;
-            }
+            pi_grad_point(pi, pos[jg], acc[0][b][v], acc[1][b][v], acc[2][b][v], gsum);
         }
     }
     __shared__ double red[4][16];
@@ -749,6 +731,168 @@ __global__ __launch_bounds__(256) void k_pi_grad_lp(const void* __restrict__ Kb,
     if (threadIdx.x < 16 && threadIdx.x < ncoef)
         part[(size_t)blockIdx.x * 16 + threadIdx.x] =
             red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+
+// Split-BF16 Pi tiles with the gradient epilogue, staged like the K build:
+// workgroup 512 threads = 8 waves, tile 32 grid rows (g) x 512 grid points
+// (g'), summation over the pairs in k-steps of 32.  Each k-step's split Kbar
+// tile (3 components x NS x 32 rows x 32 pairs) is loaded once by the whole
+// workgroup into LDS (double buffered, the 96-byte row pitch of the K build)
+// and shared by the eight waves; each wave loads the pair densities of its
+// own 64 g' (16 bytes per lane) one k-step ahead and owns 32 x 64 x 3 FP32
+// accumulators, so every operand value is fetched once per workgroup.
+// Kb: [3][NS][rows][ldP], rr: [NS][ngp][ldP] (row-major splits); ldP is a
+// multiple of 64.  Grid: n_rt x ceil(ngp / 512), row tile fastest, so the
+// workgroups resident on an XCD share one rr strip through its L2.
+constexpr int kPiThreads = 512;
+template <int FORM>
+__global__ __launch_bounds__(kPiThreads) void k_pi_grad_bf16(const __bf16* __restrict__ Kb, size_t kb_comp,
+                                                             size_t kb_split, int rows, const __bf16* __restrict__ rr,
+                                                             size_t rr_split, int ldP, const d4* __restrict__ pos,
+                                                             int g0, int ngp, int n_rt, int ncoef,
+                                                             double* __restrict__ part) {
+    static_assert(FORM == 3 || FORM == 6, "split-BF16 forms only");
+    constexpr int NS = Lp<FORM>::NS;
+    constexpr int NB = 4;                              // 16-column blocks per wave
+    constexpr int kARow = LpARow<FORM>::v;
+    typedef __bf16 ATile[3][NS][kLpRows][kARow];
+    __shared__ __attribute__((aligned(16))) ATile sA0;
+    __shared__ __attribute__((aligned(16))) ATile sA1;
+    constexpr int kAVec = 3 * NS * kLpRows * (kLpK / 8);          // 16-byte vectors of one tile
+    constexpr int kAPer = (kAVec + kPiThreads - 1) / kPiThreads;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rt = blockIdx.x % n_rt, jt = blockIdx.x / n_rt;
+    const int l16 = lane & 15, lk = lane >> 4;
+
+    // loader role: vector v = tid + 512 i is (component-split cs, row, 8-pair chunk q)
+    const __bf16* asrc[kAPer];
+    int adst[kAPer];
+    bool aon[kAPer];
+#pragma unroll
+    for (int i = 0; i < kAPer; ++i) {
+        const int v = threadIdx.x + kPiThreads * i;
+        aon[i] = v < kAVec;
+        const int q = v & 3, row = (v >> 2) & (kLpRows - 1), cs = aon[i] ? v >> 7 : 0;
+        asrc[i] = Kb + (cs / NS) * kb_comp + (cs % NS) * kb_split + (size_t)min(rt * kLpRows + row, rows - 1) * ldP +
+                  8 * q;
+        adst[i] = (cs * kLpRows + row) * kARow + 8 * q;
+    }
+    bf8 apre[kAPer];
+    auto loadA = [&](int k) {
+#pragma unroll
+        for (int i = 0; i < kAPer; ++i)
+            if (aon[i]) apre[i] = *(const bf8*)(asrc[i] + k);
+    };
+    auto storeA = [&](ATile& W) {
+#pragma unroll
+        for (int i = 0; i < kAPer; ++i)
+            if (aon[i]) *(bf8*)(&W[0][0][0][0] + adst[i]) = apre[i];
+    };
+    // MFMA role: the wave's 64 g' (clamped; columns >= ngp are skipped in the epilogue)
+    const int jbase = jt * (kPiThreads / 64) * 64 + wave * 64;
+    const __bf16* bsrc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) bsrc[b] = rr + (size_t)min(jbase + 16 * b + l16, ngp - 1) * ldP + 8 * lk;
+    bf8 bnext[NB][NS];
+    auto loadB = [&](int k) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) bnext[b][s] = *(const bf8*)(bsrc[b] + s * rr_split + k);
+    };
+
+    f4 acc[3][2][NB];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[c][h][b] = (f4){0.f, 0.f, 0.f, 0.f};
+
+    // per (row half, component): its split operand from LDS, then the split
+    // products over the wave's 4 column blocks (consecutive MFMAs write
+    // different accumulators)
+    auto multiply = [&](const ATile& R, const bf8 (&bv)[NB][NS]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                bf8 av[NS];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) av[s] = *(const bf8*)&R[c][s][16 * h + l16][8 * lk];
+#pragma unroll
+                for (int t = 0; t < Terms<FORM>::n; ++t)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[c][h][b] = mma_bf16(av[Terms<FORM>::a[t]], bv[b][Terms<FORM>::b[t]], acc[c][h][b]);
+            }
+    };
+    // one k-step: multiply tile R with the operand in bnext while loading the
+    // next k-step (at the last step the last one again, into a buffer that is
+    // never read: no branch in the loop body).  The six-product form has no
+    // registers for two k-steps of its operand: it loads the next one after
+    // the MFMAs are issued.
+    auto step = [&](int k, const ATile& R, ATile& W) {
+        const int kn = min(k + kLpK, ldP - kLpK);
+        loadA(kn);
+        if constexpr (FORM == 3) {
+            bf8 bv[NB][NS];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) bv[b][s] = bnext[b][s];
+            loadB(kn);
+            multiply(R, bv);
+        } else {
+            multiply(R, bnext);
+            loadB(kn);
+        }
+        storeA(W);
+    };
+    loadA(0);
+    loadB(0);
+    storeA(sA0);
+    __syncthreads();
+    for (int k = 0; k < ldP; k += 2 * kLpK) {
+        step(k, sA0, sA1);
+        __syncthreads();
+        step(k + kLpK, sA1, sA0);
+        __syncthreads();
+    }
+
+    double gsum[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) gsum[j] = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = rt * kLpRows + 16 * h + 4 * lk + v;    // MFMA output rows: 4 (l/16) + v
+            if (i >= rows) continue;
+            const d4 pi = pos[g0 + i];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int jg = jbase + 16 * b + l16;
+                if (jg >= ngp) continue;
+                pi_grad_point(pi, pos[jg], acc[0][h][b][v], acc[1][h][b][v], acc[2][h][b][v], gsum);
+            }
+        }
+    __shared__ double red[kPiThreads / 64][16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        double v = gsum[j];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+        if (lane == 0) red[wave][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16 && (int)threadIdx.x < ncoef) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kPiThreads / 64; ++w) v += red[w][threadIdx.x];
+        part[(size_t)blockIdx.x * 16 + threadIdx.x] = v;
+    }
 }
 
 }  // namespace xtc

@@ -771,24 +771,31 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
                 if ((s = split_rows_any(L.form, Y + x * ystride, (size_t)rows * L.ldP, kb + x * kb_comp * L.es,
                                         kb_split, st)) != XTC_OK)
                     return s;
-            const int n_jt_lp = (L.ngp + 255) / 256;
-            nblk_pi = n_it_pi * n_jt_lp;
             const size_t rr_split = (size_t)L.ngp * L.ldP;
-            if (L.form == 1)
+            if (L.form == 1) {
+                const int n_jt_lp = (L.ngp + 255) / 256;
+                nblk_pi = n_it_pi * n_jt_lp;
                 hipLaunchKernelGGL(k_pi_grad_lp<1>, dim3(nblk_pi), dim3(256), 0, st, (const void*)kb, kb_comp, kb_split,
                                    rows, at<void>(ws, L.rhoR), rr_split, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_jt_lp,
                                    J.ncoef, at<double>(ws, L.gpart));
-            else if (L.form == 3)
-                hipLaunchKernelGGL(k_pi_grad_lp<3>, dim3(nblk_pi), dim3(256), 0, st, (const void*)kb, kb_comp, kb_split,
-                                   rows, at<void>(ws, L.rhoR), rr_split, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_jt_lp,
-                                   J.ncoef, at<double>(ws, L.gpart));
-            else
-                hipLaunchKernelGGL(k_pi_grad_lp<6>, dim3(nblk_pi), dim3(256), 0, st, (const void*)kb, kb_comp, kb_split,
-                                   rows, at<void>(ws, L.rhoR), rr_split, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_jt_lp,
-                                   J.ncoef, at<double>(ws, L.gpart));
+            } else {
+                const int n_rt = (rows + kLpRows - 1) / kLpRows;
+                const int n_jt = (L.ngp + kPiThreads - 1) / kPiThreads;
+                nblk_pi = n_rt * n_jt;
+                const __bf16* kbb = (const __bf16*)kb;
+                const __bf16* rrb = at<__bf16>(ws, L.rhoR);
+                if (L.form == 3)
+                    hipLaunchKernelGGL(k_pi_grad_bf16<3>, dim3(nblk_pi), dim3(kPiThreads), 0, st, kbb, kb_comp,
+                                       kb_split, rows, rrb, rr_split, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_rt,
+                                       J.ncoef, at<double>(ws, L.gpart));
+                else
+                    hipLaunchKernelGGL(k_pi_grad_bf16<6>, dim3(nblk_pi), dim3(kPiThreads), 0, st, kbb, kb_comp,
+                                       kb_split, rows, rrb, rr_split, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_rt,
+                                       J.ncoef, at<double>(ws, L.gpart));
+            }
             if ((s = launched("pi_grad_lp")) != XTC_OK) return s;
         }
-        hipLaunchKernelGGL(k_reduce_grad, dim3(1), dim3(64), 0, st, at<double>(ws, L.gpart), nblk_pi, J.ncoef,
+        hipLaunchKernelGGL(k_reduce_grad, dim3(J.ncoef), dim3(256), 0, st, at<double>(ws, L.gpart), nblk_pi, J.ncoef,
                            at<double>(ws, L.gacc), first ? 0 : 1, last ? gcoef : nullptr);
         if ((s = launched("reduce_grad")) != XTC_OK) return s;
         first = false;

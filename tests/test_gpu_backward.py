@@ -68,13 +68,18 @@ def test_gradient_euler_and_fd(torch_cuda):
         assert abs(fd - g[k]) < 1e-8 * max(1.0, abs(g[k])), (k, fd, g[k])
 
 
-def test_gradient_reduced_precision_close(torch_cuda):
-    """The split-BF16 K recompute changes the gradient only at the level of its K error."""
-    p, coef, D, G = _case(12, 3, 900, 3, 34)
-    _note("case: backward bf16x3 vs fp64")
-    g64 = _gpu_grad(torch_cuda, p, coef, D, G)
-    g3 = _gpu_grad(torch_cuda, p, coef, D, G, prec="bf16x3")
-    assert np.abs(g3 - g64).max() < 1e-5 * max(1.0, np.abs(g64).max())
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6", "fp32"])
+@pytest.mark.parametrize("N,nocc,Ng,nc,seed,chunk", [(12, 3, 900, 3, 34, None), (24, 5, 1500, 6, 36, 640)])
+def test_gradient_reduced_precision_close(torch_cuda, prec, N, nocc, Ng, nc, seed, chunk):
+    """The reduced forms (K recompute and Pi contraction) change the gradient
+    only at the level of their FP32 accumulation; the second case spans
+    several pair k-steps, three g' tiles and a ragged last chunk."""
+    p, coef, D, G = _case(N, nocc, Ng, nc, seed)
+    _note(f"case: backward {prec} vs fp64 N={N} Ng={Ng} chunk={chunk}")
+    g64 = _gpu_grad(torch_cuda, p, coef, D, G, chunk_rows=chunk)
+    gr = _gpu_grad(torch_cuda, p, coef, D, G, prec=prec, chunk_rows=chunk)
+    _note(f"  max |dg| {np.abs(gr - g64).max():.3e}  scale {np.abs(g64).max():.3e}")
+    assert np.abs(gr - g64).max() < 1e-5 * max(1.0, np.abs(g64).max())
 
 
 def test_autograd_function(torch_cuda):
