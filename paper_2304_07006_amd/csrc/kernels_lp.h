@@ -660,7 +660,7 @@ __device__ __forceinline__ void pi_grad_point(const d4& pi, const d4& pj, float 
 // Pi^x(g,g') = sum_P Kbar^x[g][P] rho[g'][P] with FP32 accumulation over all
 // pairs; workgroup 4 waves as 2 (g) x 2 (g'), wave tile 16 g x 128 g' x 3.
 // Kb: [3][rows][ldP], rr: [ngp][ldP] (row-major).  The split-BF16 forms use
-// k_pi_grad_bf16.
+// k_nt_bf16.
 template <int FORM>
 __global__ __launch_bounds__(256) void k_pi_grad_lp(const void* __restrict__ Kb, size_t kb_comp, size_t kb_split,
                                                     int rows, const void* __restrict__ rr, size_t rr_split,
@@ -734,38 +734,47 @@ __global__ __launch_bounds__(256) void k_pi_grad_lp(const void* __restrict__ Kb,
 }
 
 
-// Split-BF16 Pi tiles with the gradient epilogue, staged like the K build:
-// workgroup 512 threads = 8 waves, tile 32 grid rows (g) x 512 grid points
-// (g'), summation over the pairs in k-steps of 32.  Each k-step's split Kbar
-// tile (3 components x NS x 32 rows x 32 pairs) is loaded once by the whole
-// workgroup into LDS (double buffered, the 96-byte row pitch of the K build)
-// and shared by the eight waves; each wave loads the pair densities of its
-// own 64 g' (16 bytes per lane) one k-step ahead and owns 32 x 64 x 3 FP32
-// accumulators, so every operand value is fetched once per workgroup.
-// Kb: [3][NS][rows][ldP], rr: [NS][ngp][ldP] (row-major splits); ldP is a
-// multiple of 64.  Grid: n_rt x ceil(ngp / 512), row tile fastest, so the
-// workgroups resident on an XCD share one rr strip through its L2.
+// Split-BF16 NT product out_c[i][j] = sum_k A_c[i][k] B[j][k] over NC
+// components sharing B, staged like the K build: workgroup 512 threads = 8
+// waves, tile 32 rows (i) x 512 columns (j), k-steps of 32.  Each k-step's
+// split A tile (NC components x NS x 32 rows x 32 k) is loaded once by the
+// whole workgroup into LDS (double buffered, the 96-byte row pitch of the K
+// build) and shared by the eight waves; each wave loads B for its own 64
+// columns (16 bytes per lane) one k-step ahead and owns 32 x 64 x NC FP32
+// accumulators, so every operand value is fetched once per workgroup.  FP32
+// accumulation over the whole k range.
+// A: [NC][NS][rows][ldk] (component stride a_comp, split stride a_split),
+// B: [NS][nB][ldk] (split stride b_split), both row-major with k contiguous;
+// ldk is a multiple of 64.  Grid: n_rt x ceil(nB / 512), row tile fastest, so
+// the workgroups resident on an XCD share one B strip through its L2.
+// Epilogues:
+//  GRAD (NC = 3, the Pi contraction Pi^x(g,g') = sum_P Kbar^x[g][P] rho[g'][P]
+//   with i = g - g0, j = g'): the gradient terms of every (g, g'), summed per
+//   workgroup into part[blockIdx.x][16];
+//  otherwise: out[c][i][j] = FP64 value, i < rows, j < nB (out + c * out_comp,
+//   leading dimension ldo).
 constexpr int kPiThreads = 512;
-template <int FORM>
-__global__ __launch_bounds__(kPiThreads) void k_pi_grad_bf16(const __bf16* __restrict__ Kb, size_t kb_comp,
-                                                             size_t kb_split, int rows, const __bf16* __restrict__ rr,
-                                                             size_t rr_split, int ldP, const d4* __restrict__ pos,
-                                                             int g0, int ngp, int n_rt, int ncoef,
-                                                             double* __restrict__ part) {
+template <int FORM, int NC, bool GRAD>
+__global__ __launch_bounds__(kPiThreads) void k_nt_bf16(const __bf16* __restrict__ A, size_t a_comp, size_t a_split,
+                                                        int rows, const __bf16* __restrict__ B, size_t b_split,
+                                                        int nB, int ldk, int n_rt, const d4* __restrict__ pos,
+                                                        int g0, int ncoef, double* __restrict__ out,
+                                                        size_t out_comp, int ldo) {
     static_assert(FORM == 3 || FORM == 6, "split-BF16 forms only");
+    static_assert(!GRAD || NC == 3, "the gradient epilogue takes the three components of Pi");
     constexpr int NS = Lp<FORM>::NS;
     constexpr int NB = 4;                              // 16-column blocks per wave
     constexpr int kARow = LpARow<FORM>::v;
-    typedef __bf16 ATile[3][NS][kLpRows][kARow];
+    typedef __bf16 ATile[NC][NS][kLpRows][kARow];
     __shared__ __attribute__((aligned(16))) ATile sA0;
     __shared__ __attribute__((aligned(16))) ATile sA1;
-    constexpr int kAVec = 3 * NS * kLpRows * (kLpK / 8);          // 16-byte vectors of one tile
+    constexpr int kAVec = NC * NS * kLpRows * (kLpK / 8);         // 16-byte vectors of one tile
     constexpr int kAPer = (kAVec + kPiThreads - 1) / kPiThreads;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rt = blockIdx.x % n_rt, jt = blockIdx.x / n_rt;
     const int l16 = lane & 15, lk = lane >> 4;
 
-    // loader role: vector v = tid + 512 i is (component-split cs, row, 8-pair chunk q)
+    // loader role: vector v = tid + 512 i is (component-split cs, row, 8-k chunk q)
     const __bf16* asrc[kAPer];
     int adst[kAPer];
     bool aon[kAPer];
@@ -774,7 +783,7 @@ __global__ __launch_bounds__(kPiThreads) void k_pi_grad_bf16(const __bf16* __res
         const int v = threadIdx.x + kPiThreads * i;
         aon[i] = v < kAVec;
         const int q = v & 3, row = (v >> 2) & (kLpRows - 1), cs = aon[i] ? v >> 7 : 0;
-        asrc[i] = Kb + (cs / NS) * kb_comp + (cs % NS) * kb_split + (size_t)min(rt * kLpRows + row, rows - 1) * ldP +
+        asrc[i] = A + (cs / NS) * a_comp + (cs % NS) * a_split + (size_t)min(rt * kLpRows + row, rows - 1) * ldk +
                   8 * q;
         adst[i] = (cs * kLpRows + row) * kARow + 8 * q;
     }
@@ -789,22 +798,22 @@ __global__ __launch_bounds__(kPiThreads) void k_pi_grad_bf16(const __bf16* __res
         for (int i = 0; i < kAPer; ++i)
             if (aon[i]) *(bf8*)(&W[0][0][0][0] + adst[i]) = apre[i];
     };
-    // MFMA role: the wave's 64 g' (clamped; columns >= ngp are skipped in the epilogue)
+    // MFMA role: the wave's 64 columns (clamped; columns >= nB are never written)
     const int jbase = jt * (kPiThreads / 64) * 64 + wave * 64;
     const __bf16* bsrc[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) bsrc[b] = rr + (size_t)min(jbase + 16 * b + l16, ngp - 1) * ldP + 8 * lk;
+    for (int b = 0; b < NB; ++b) bsrc[b] = B + (size_t)min(jbase + 16 * b + l16, nB - 1) * ldk + 8 * lk;
     bf8 bnext[NB][NS];
     auto loadB = [&](int k) {
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int s = 0; s < NS; ++s) bnext[b][s] = *(const bf8*)(bsrc[b] + s * rr_split + k);
+            for (int s = 0; s < NS; ++s) bnext[b][s] = *(const bf8*)(bsrc[b] + s * b_split + k);
     };
 
-    f4 acc[3][2][NB];
+    f4 acc[NC][2][NB];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -817,7 +826,7 @@ __global__ __launch_bounds__(kPiThreads) void k_pi_grad_bf16(const __bf16* __res
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < NC; ++c) {
                 bf8 av[NS];
 #pragma unroll
                 for (int s = 0; s < NS; ++s) av[s] = *(const bf8*)&R[c][s][16 * h + l16][8 * lk];
@@ -834,7 +843,7 @@ __global__ __launch_bounds__(kPiThreads) void k_pi_grad_bf16(const __bf16* __res
     // registers for two k-steps of its operand: it loads the next one after
     // the MFMAs are issued.
     auto step = [&](int k, const ATile& R, ATile& W) {
-        const int kn = min(k + kLpK, ldP - kLpK);
+        const int kn = min(k + kLpK, ldk - kLpK);
         loadA(kn);
         if constexpr (FORM == 3) {
             bf8 bv[NB][NS];
@@ -854,44 +863,62 @@ __global__ __launch_bounds__(kPiThreads) void k_pi_grad_bf16(const __bf16* __res
     loadB(0);
     storeA(sA0);
     __syncthreads();
-    for (int k = 0; k < ldP; k += 2 * kLpK) {
+    for (int k = 0; k < ldk; k += 2 * kLpK) {
         step(k, sA0, sA1);
         __syncthreads();
         step(k + kLpK, sA1, sA0);
         __syncthreads();
     }
 
-    double gsum[16];
+    if constexpr (!GRAD) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) gsum[j] = 0.0;
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+            for (int v = 0; v < 4; ++v) {
+                const int i = rt * kLpRows + 16 * h + 4 * lk + v;    // MFMA output rows: 4 (l/16) + v
+                if (i >= rows) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = rt * kLpRows + 16 * h + 4 * lk + v;    // MFMA output rows: 4 (l/16) + v
-            if (i >= rows) continue;
-            const d4 pi = pos[g0 + i];
+                for (int b = 0; b < NB; ++b) {
+                    const int j = jbase + 16 * b + l16;
+                    if (j >= nB) continue;
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int jg = jbase + 16 * b + l16;
-                if (jg >= ngp) continue;
-                pi_grad_point(pi, pos[jg], acc[0][h][b][v], acc[1][h][b][v], acc[2][h][b][v], gsum);
+                    for (int c = 0; c < NC; ++c) out[c * out_comp + (size_t)i * ldo + j] = (double)acc[c][h][b][v];
+                }
             }
+        return;
+    } else {
+        double gsum[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) gsum[j] = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = rt * kLpRows + 16 * h + 4 * lk + v;
+                if (i >= rows) continue;
+                const d4 pi = pos[g0 + i];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const int jg = jbase + 16 * b + l16;
+                    if (jg >= nB) continue;
+                    pi_grad_point(pi, pos[jg], acc[0][h][b][v], acc[1][h][b][v], acc[2][h][b][v], gsum);
+                }
+            }
+        __shared__ double red[kPiThreads / 64][16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            double v = gsum[j];
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+            if (lane == 0) red[wave][j] = v;
         }
-    __shared__ double red[kPiThreads / 64][16];
+        __syncthreads();
+        if (threadIdx.x < 16 && (int)threadIdx.x < ncoef) {
+            double v = 0.0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        double v = gsum[j];
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-        if (lane == 0) red[wave][j] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 16 && (int)threadIdx.x < ncoef) {
-        double v = 0.0;
-#pragma unroll
-        for (int w = 0; w < kPiThreads / 64; ++w) v += red[w][threadIdx.x];
-        part[(size_t)blockIdx.x * 16 + threadIdx.x] = v;
+            for (int w = 0; w < kPiThreads / 64; ++w) v += red[w][threadIdx.x];
+            out[(size_t)blockIdx.x * 16 + threadIdx.x] = v;
+        }
     }
 }
 

@@ -18,7 +18,10 @@
 //   Mpart  [ceil(cap/kSegM)][4][ldL][ldL] f32  two-body partials   (prec != FP64)
 // and with XTC_WITH_BACKWARD in prec (the adjoint reuses M for Gbar):
 //   Kc [3][cap][ldP], Y [7][cap][ldP], T [cap][3][N][nocc], Wbar [cap][3],
-//   gpart [ceil(cap/32) * ngp/128][16], gacc [16], occw [N] f64, kidx [N]
+//   gpart [ceil(cap/32) * ngp/128][16], gacc [16], occw [N] f64, kidx [N],
+//   reduced forms: rhoR [NS][ngp][ldP] (row-major split rho), KbL
+//   [7][NS][cap][ldP] (row-major split operands of the chunk), split-BF16
+//   forms: GsL [NS][ldP][ldP] (row-major split Gbar)
 // and with XTC_WITH_TC2 (two-body TC integrals; ldN = N^2 rounded up to 128):
 //   Atc [ldP][ldP], Btc [ldN][ldP] FP64 accumulators, Ftc [cap][ldP],
 //   Rg [3][cap][ldN] (w phi grad phi of the chunk)
@@ -84,7 +87,7 @@ struct Layout {
     int form, ns, es, ldL, ldO, nOP, occNB, nsegK, nspin, ldN;
     bool tc2;
     bool bwd;
-    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, occw, kidx, rhoR, Atc, Btc;
+    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, occw, kidx, rhoR, GsL, Atc, Btc;
     size_t fixed;        // bytes before S (plus the Mpart remainder reserve)
     size_t per_row;      // bytes per chunk row
     int cap;             // chunk rows that fit (multiple of kRowQuant)
@@ -153,6 +156,8 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.occw = off;    off = align_up(off + (L.bwd ? (size_t)L.N * sizeof(double) : 0), kAlign);
     L.kidx = off;    off = align_up(off + (L.bwd ? (size_t)L.N * sizeof(int) : 0), kAlign);
     L.rhoR = off;    off = align_up(off + (L.bwd && lp ? (size_t)L.ns * L.ngp * L.ldP * L.es : 0), kAlign);
+    const bool bsplit = L.bwd && (L.form == 3 || L.form == 6);   // split-BF16 X Gbar products
+    L.GsL = off;     off = align_up(off + (bsplit ? (size_t)L.ns * L.ldP * L.ldP * L.es : 0), kAlign);
     L.Atc = off;     off = align_up(off + (L.tc2 ? (size_t)L.ldP * L.ldP * sizeof(double) : 0), kAlign);
     L.Btc = off;     off = align_up(off + (L.tc2 ? (size_t)L.ldN * L.ldP * sizeof(double) : 0), kAlign);
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);   // one 32-row tile of partials
@@ -171,7 +176,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     if (L.tc2) L.per_row += (size_t)L.ldP * sizeof(double) + (size_t)3 * L.ldN * sizeof(double);
     if (L.bwd)
         L.per_row += (size_t)10 * L.ldP * sizeof(double) + (size_t)3 * L.N * L.nocc * sizeof(double) +
-                     3 * sizeof(double) + (gslab + 31) / 32 + (lp ? (size_t)3 * L.ns * L.ldP * L.es : 0);
+                     3 * sizeof(double) + (gslab + 31) / 32 + (lp ? (size_t)7 * L.ns * L.ldP * L.es : 0);
     L.cap = 0;
     return L;
 }
@@ -198,7 +203,7 @@ void place_chunk(Layout& L, size_t bytes) {
     L.T = off;       off = align_up(off + (b ? (size_t)cap * 3 * L.N * L.nocc * sizeof(double) : 0), kAlign);
     L.Wbar = off;    off = align_up(off + (b ? (size_t)cap * 3 * sizeof(double) : 0), kAlign);
     L.gpart = off;   off = align_up(off + (b ? (size_t)((cap + 31) / 32) * gslab : 0), kAlign);
-    L.KbL = off;     off = align_up(off + (b && lp ? (size_t)3 * L.ns * cap * L.ldP * L.es : 0), kAlign);
+    L.KbL = off;     off = align_up(off + (b && lp ? (size_t)7 * L.ns * cap * L.ldP * L.es : 0), kAlign);
     L.Ftc = off;     off = align_up(off + (L.tc2 ? (size_t)cap * L.ldP * sizeof(double) : 0), kAlign);
     L.Rg = off;      off = align_up(off + (L.tc2 ? (size_t)3 * cap * L.ldN * sizeof(double) : 0), kAlign);
     L.end = off;
@@ -503,6 +508,32 @@ xtc_status split_rows_any(int form, const double* src, size_t n, void* dst, size
     return launched("split_rows");
 }
 
+// Y_c = X_c Gbar for the seven adjoint operands in split BF16 (k_nt_bf16,
+// FP32 accumulation over all pairs): X split [7][NS][rows][ldP], Gbar split
+// [NS][ldP][ldP], Y [7][cap][ldP] FP64.  Components share the Gbar operand in
+// groups of 3 + 4 (six-product form: 3 + 3 + 1, for its register budget).
+template <int FORM, int NC>
+xtc_status xg_group(const __bf16* X, size_t a_comp, size_t a_split, int rows, const __bf16* Gs, int ldP, int c0,
+                    double* Y, size_t ystride, hipStream_t st) {
+    const int n_rt = (rows + kLpRows - 1) / kLpRows, n_jt = (ldP + kPiThreads - 1) / kPiThreads;
+    hipLaunchKernelGGL((k_nt_bf16<FORM, NC, false>), dim3(n_rt * n_jt), dim3(kPiThreads), 0, st, X + c0 * a_comp,
+                       a_comp, a_split, rows, Gs, (size_t)ldP * ldP, ldP, ldP, n_rt, (const d4*)nullptr, 0, 0,
+                       Y + c0 * ystride, ystride, ldP);
+    return launched("gemm_xg_bf16");
+}
+
+xtc_status xg_bf16(int form, const __bf16* X, size_t a_comp, size_t a_split, int rows, const __bf16* Gs, int ldP,
+                   double* Y, size_t ystride, hipStream_t st) {
+    xtc_status s;
+    if (form == 3) {
+        if ((s = xg_group<3, 3>(X, a_comp, a_split, rows, Gs, ldP, 0, Y, ystride, st)) != XTC_OK) return s;
+        return xg_group<3, 4>(X, a_comp, a_split, rows, Gs, ldP, 3, Y, ystride, st);
+    }
+    if ((s = xg_group<6, 3>(X, a_comp, a_split, rows, Gs, ldP, 0, Y, ystride, st)) != XTC_OK) return s;
+    if ((s = xg_group<6, 3>(X, a_comp, a_split, rows, Gs, ldP, 3, Y, ystride, st)) != XTC_OK) return s;
+    return xg_group<6, 1>(X, a_comp, a_split, rows, Gs, ldP, 6, Y, ystride, st);
+}
+
 xtc_status build_K_any(const Layout& L, const JasDev& J, int g0, int rows, double* K, bool occ64, void* ws,
                        hipStream_t st) {
     if (L.form != 0) return build_K_lp(L, g0, rows, J, K, occ64, ws, st);
@@ -720,6 +751,10 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
     hipLaunchKernelGGL(k_make_gbar, dim3((L.ldP + 255) / 256, L.ldP), dim3(256), 0, st, gV2, gh1, gE0,
                        at<double>(ws, L.occw), L.N, L.ldP, G);
     if ((s = launched("make_gbar")) != XTC_OK) return s;
+    const bool bsplit = L.form == 3 || L.form == 6;
+    if (bsplit &&
+        (s = split_rows_any(L.form, G, (size_t)L.ldP * L.ldP, at<void>(ws, L.GsL), (size_t)L.ldP * L.ldP, st)) != XTC_OK)
+        return s;
     const size_t ystride = (size_t)L.cap * L.ldP;
     double* Kc = at<double>(ws, L.Kc);
     double* Y = at<double>(ws, L.Y);
@@ -736,11 +771,24 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
         // Y slots: 0..2 Cbar_{1..3} = D_{1..3} Gbar, 3 Abar = rho Gbar, 4..6 Bbar = K Gbar
         const double* src[7] = {D + ystride, D + 2 * ystride, D + 3 * ystride, rho_rows, Kc, Kc + kstride,
                                 Kc + 2 * kstride};
-        const int n_it = (rows + 63) / 64, n_jt = L.ldP / 128;
-        for (int y = 0; y < 7; ++y) {
-            hipLaunchKernelGGL(k_gemm_xg_f64, dim3(n_it * n_jt), dim3(256), 0, st, src[y], (size_t)L.ldP, rows, G,
-                               L.ldP, n_jt, Y + y * ystride, (size_t)L.ldP);
-            if ((s = launched("gemm_xg")) != XTC_OK) return s;
+        if (bsplit) {
+            // split-BF16: the seven operands to row-major splits, then the NT
+            // products in groups of components sharing Gbar
+            const size_t a_split = (size_t)rows * L.ldP, a_comp = (size_t)L.ns * a_split;
+            char* xs = at<char>(ws, L.KbL);
+            for (int y = 0; y < 7; ++y)
+                if ((s = split_rows_any(L.form, src[y], a_split, xs + y * a_comp * L.es, a_split, st)) != XTC_OK)
+                    return s;
+            if ((s = xg_bf16(L.form, (const __bf16*)xs, a_comp, a_split, rows, at<__bf16>(ws, L.GsL), L.ldP, Y,
+                             ystride, st)) != XTC_OK)
+                return s;
+        } else {
+            const int n_it = (rows + 63) / 64, n_jt = L.ldP / 128;
+            for (int y = 0; y < 7; ++y) {
+                hipLaunchKernelGGL(k_gemm_xg_f64, dim3(n_it * n_jt), dim3(256), 0, st, src[y], (size_t)L.ldP, rows, G,
+                                   L.ldP, n_jt, Y + y * ystride, (size_t)L.ldP);
+                if ((s = launched("gemm_xg")) != XTC_OK) return s;
+            }
         }
         const size_t lds = (size_t)L.nocc * L.N * 4 * sizeof(double);
         if (lds > 64 * 1024) {
@@ -785,13 +833,13 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
                 const __bf16* kbb = (const __bf16*)kb;
                 const __bf16* rrb = at<__bf16>(ws, L.rhoR);
                 if (L.form == 3)
-                    hipLaunchKernelGGL(k_pi_grad_bf16<3>, dim3(nblk_pi), dim3(kPiThreads), 0, st, kbb, kb_comp,
-                                       kb_split, rows, rrb, rr_split, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_rt,
-                                       J.ncoef, at<double>(ws, L.gpart));
+                    hipLaunchKernelGGL((k_nt_bf16<3, 3, true>), dim3(nblk_pi), dim3(kPiThreads), 0, st, kbb, kb_comp,
+                                       kb_split, rows, rrb, rr_split, L.ngp, L.ldP, n_rt, at<d4>(ws, L.pos), g0,
+                                       J.ncoef, at<double>(ws, L.gpart), (size_t)0, 0);
                 else
-                    hipLaunchKernelGGL(k_pi_grad_bf16<6>, dim3(nblk_pi), dim3(kPiThreads), 0, st, kbb, kb_comp,
-                                       kb_split, rows, rrb, rr_split, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_rt,
-                                       J.ncoef, at<double>(ws, L.gpart));
+                    hipLaunchKernelGGL((k_nt_bf16<6, 3, true>), dim3(nblk_pi), dim3(kPiThreads), 0, st, kbb, kb_comp,
+                                       kb_split, rows, rrb, rr_split, L.ngp, L.ldP, n_rt, at<d4>(ws, L.pos), g0,
+                                       J.ncoef, at<double>(ws, L.gpart), (size_t)0, 0);
             }
             if ((s = launched("pi_grad_lp")) != XTC_OK) return s;
         }
