@@ -80,7 +80,7 @@ int pair_ld(int N) {
 constexpr int kSegK = 8192;     // g' per FP32 segment of the reduced-precision K build
 constexpr int kSegM = 2048;     // grid rows per FP32 segment of the reduced-precision two-body GEMM
 constexpr int kRowQuant = 32;
-constexpr int kOccSeg = 4;      // segments of the FP64 occupied-block sum over g'
+constexpr int kOccSegMax = 32;  // most segments of the FP64 occupied-block sum over g'
 
 struct Layout {
     int N, Ng, nocc, ldP, ngp, Npair, prec;
@@ -170,7 +170,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     const size_t mslab = L.mslab;
     L.fixed = off + mslab + (L.bwd ? gslab : 0) + 16 * kAlign;
     L.per_row = (size_t)L.nspin * (8 * sizeof(double) + (size_t)4 * L.ldP * sizeof(double));
-    if (lp) L.per_row += (size_t)kOccSeg * 3 * L.ldO * sizeof(double);
+    if (lp) L.per_row += (size_t)kOccSegMax * 3 * L.ldO * sizeof(double);
     if (lp)
         L.per_row += (size_t)L.nsegK * 3 * L.ldL * sizeof(float) + L.cdw * L.ns * L.es + (mslab + kSegM - 1) / kSegM;
     if (L.tc2) L.per_row += (size_t)L.ldP * sizeof(double) + (size_t)3 * L.ldN * sizeof(double);
@@ -196,7 +196,7 @@ void place_chunk(Layout& L, size_t bytes) {
     L.Kpart = off;   off = align_up(off + (lp ? (size_t)L.nsegK * 3 * cap * L.ldL * sizeof(float) : 0), kAlign);
     L.CDlp = off;    off = align_up(off + (lp ? L.cdw * L.ns * cap * L.es : 0), kAlign);
     L.Mpart = off;   off = align_up(off + (size_t)((cap + kSegM - 1) / kSegM) * L.mslab, kAlign);
-    L.Kocc = off;    off = align_up(off + (lp ? (size_t)kOccSeg * 3 * cap * L.ldO * sizeof(double) : 0), kAlign);
+    L.Kocc = off;    off = align_up(off + (lp ? (size_t)kOccSegMax * 3 * cap * L.ldO * sizeof(double) : 0), kAlign);
     const bool b = L.bwd;
     L.Kc = off;      off = align_up(off + (b ? (size_t)3 * cap * L.ldP * sizeof(double) : 0), kAlign);
     L.Y = off;       off = align_up(off + (b ? (size_t)7 * cap * L.ldP * sizeof(double) : 0), kAlign);
@@ -379,25 +379,55 @@ void launch_build_lp(const Layout& L, int g0, int rows, const JasDev& J, void* w
                        kSegK, J, at<float>(ws, L.Kpart), L.cap, L.ldP, n_ct, L.nsegK);
 }
 
+// Segments of the g' sum for a grid of `tiles` workgroups per segment: the
+// fewest, from 4, whose last round of workgroups keeps at least 90% of the
+// `slots` resident workgroups busy (equal-work workgroups finish in rounds,
+// and a short last round idles the rest of the chip), else the best found.
+int occ_segments(long tiles, long slots) {
+    int best = 4;
+    double best_eff = 0.0;
+    for (int ns = 4; ns <= kOccSegMax; ++ns) {
+        const long t = tiles * ns;
+        const double eff = (double)t / (double)(((t + slots - 1) / slots) * slots);
+        if (eff >= 0.9) return ns;
+        if (eff > best_eff) {
+            best_eff = eff;
+            best = ns;
+        }
+    }
+    return best;
+}
+
+// Launch the FP64 occupied block with the segment count from the kernel's
+// occupancy on the current device; returns that count (0 on a HIP error).
 template <int KIND, int NB>
-void launch_build_occ_nb(const Layout& L, int g0, int rows, int n_rt, int nseg, int seg_len, const JasDev& J, void* ws,
-                         hipStream_t st) {
-    const dim3 grid(n_rt * (L.ldO / (16 * NB)), nseg);
+int launch_build_occ_nb(const Layout& L, int g0, int rows, int n_rt, const JasDev& J, void* ws, hipStream_t st) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_build_K_occ<KIND, NB>, 256, 0) !=
+            hipSuccess)
+        return 0;
+    const long tiles = (long)n_rt * (L.ldO / (16 * NB));
+    const int want = occ_segments(tiles, (long)std::max(cus, 1) * std::max(per_cu, 1));
+    const int seg_len = (int)align_up((size_t)((L.ngp + want - 1) / want), 4);
+    const int nseg = (L.ngp + seg_len - 1) / seg_len;   // every segment starts inside the grid
+    const dim3 grid((unsigned)tiles, nseg);
     hipLaunchKernelGGL((k_build_K_occ<KIND, NB>), grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho_occ),
                        L.ldO, L.ngp, g0, rows, n_rt, J, at<double>(ws, L.Kocc), seg_len);
+    return nseg;
 }
 
 template <int KIND>
-void launch_build_occ(const Layout& L, int g0, int rows, int n_rt, int nseg, int seg_len, const JasDev& J, void* ws,
-                      hipStream_t st) {
+int launch_build_occ(const Layout& L, int g0, int rows, int n_rt, const JasDev& J, void* ws, hipStream_t st) {
     switch (L.occNB) {
-        case 1: return launch_build_occ_nb<KIND, 1>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
-        case 2: return launch_build_occ_nb<KIND, 2>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
-        case 3: return launch_build_occ_nb<KIND, 3>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
-        case 4: return launch_build_occ_nb<KIND, 4>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
-        case 5: return launch_build_occ_nb<KIND, 5>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
-        case 6: return launch_build_occ_nb<KIND, 6>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
-        default: return launch_build_occ_nb<KIND, 7>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
+        case 1: return launch_build_occ_nb<KIND, 1>(L, g0, rows, n_rt, J, ws, st);
+        case 2: return launch_build_occ_nb<KIND, 2>(L, g0, rows, n_rt, J, ws, st);
+        case 3: return launch_build_occ_nb<KIND, 3>(L, g0, rows, n_rt, J, ws, st);
+        case 4: return launch_build_occ_nb<KIND, 4>(L, g0, rows, n_rt, J, ws, st);
+        case 5: return launch_build_occ_nb<KIND, 5>(L, g0, rows, n_rt, J, ws, st);
+        case 6: return launch_build_occ_nb<KIND, 6>(L, g0, rows, n_rt, J, ws, st);
+        default: return launch_build_occ_nb<KIND, 7>(L, g0, rows, n_rt, J, ws, st);
     }
 }
 
@@ -421,13 +451,12 @@ xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double
     if ((s = launched("reduce_K")) != XTC_OK) return s;
     if (!occ64) return XTC_OK;
     // occupied-occupied pairs in FP64, written over the reduced-precision values:
-    // kOccSeg segments of the sum over g' (enough workgroups to fill the chip),
+    // segments of the sum over g' (enough, and evenly enough, to fill the chip),
     // FP64 partials, then a fixed-order reduction scattered into K
     const int n_rt = (rows + kKRows - 1) / kKRows;
-    const int nseg = kOccSeg;
-    const int seg_len = (int)align_up((size_t)((L.ngp + nseg - 1) / nseg), 4);
-    if (J.kind == 0) launch_build_occ<0>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
-    else launch_build_occ<1>(L, g0, rows, n_rt, nseg, seg_len, J, ws, st);
+    const int nseg = J.kind == 0 ? launch_build_occ<0>(L, g0, rows, n_rt, J, ws, st)
+                                 : launch_build_occ<1>(L, g0, rows, n_rt, J, ws, st);
+    if (nseg == 0) return fail(XTC_E_HIP, "occupancy query of the occupied-block kernel failed");
     if ((s = launched("build_K_occ_f64")) != XTC_OK) return s;
     double* part = at<double>(ws, L.Kocc);
     const size_t nel = (size_t)3 * rows * L.nOP;

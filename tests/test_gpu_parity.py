@@ -27,15 +27,16 @@ def _run(problem, prec="fp64", chunk_rows=None):
     return V2.cpu().numpy(), h1.cpu().numpy(), float(E0.cpu().numpy()[0])
 
 
-def _K(problem, g0, g1, chunk_rows=None):
+def _K(problem, g0, g1, chunk_rows=None, prec=None, kflags=0):
     """Grid intermediate of rows [g0,g1) through xtc_prepare + xtc_build_K."""
     import torch
     from paper_2304_07006_amd import xtc
+    prec = xtc.XTC_FP64 if prec is None else xtc.PRECISIONS[prec]
     dp = xtc.device_problem(problem.xyz, problem.w, problem.phi, problem.occ)
-    ps = xtc.Pass(dp, xtc.XTC_FP64, chunk_rows or (g1 - g0))
-    xtc.xtc_prepare(dp, xtc.XTC_FP64, ps.chunk, ps.ws)
+    ps = xtc.Pass(dp, prec, chunk_rows or (g1 - g0))
+    xtc.xtc_prepare(dp, prec, ps.chunk, ps.ws)
     K = ps.K_view(g0, g1)
-    xtc.xtc_build_K(dp, xtc.make_jastrow(problem.jastrow), g0, g1, xtc.XTC_FP64, K, ps.ws)
+    xtc.xtc_build_K(dp, xtc.make_jastrow(problem.jastrow), g0, g1, prec | kflags, K, ps.ws)
     torch.cuda.synchronize()
     return K.cpu().numpy()
 
@@ -79,6 +80,28 @@ def test_tiny_K_entries(torch_cuda):
         assert np.abs(Ku[:, g, a, b] - e).max() < 1e-14
     ldP = K.shape[2]
     assert np.all(K[:, :, N * (N + 1) // 2:ldP] == 0.0)
+
+
+def test_reduced_occ_option(torch_cuda):
+    """xtc_build_K in split BF16 with and without XTC_K_REDUCED_OCC: the pairs
+    outside the occupied-occupied block are bitwise the same, the block itself
+    is FP64 (= the FP64 build to summation noise) only without the option."""
+    from paper_2304_07006_amd import xtc
+    p = inputs.make_workload("N64-occ8-Ng50k", Ng=3001)
+    _note("case: N64-occ8-Ng3001 K rows [500,1800) bf16x3 with / without XTC_K_REDUCED_OCC")
+    K64 = _K(p, 500, 1800)
+    Kf = _K(p, 500, 1800, prec="bf16x3")
+    Kr = _K(p, 500, 1800, prec="bf16x3", kflags=xtc.XTC_K_REDUCED_OCC)
+    N = p.N
+    occ = sorted(int(k) for k in p.occ)
+    cols = [a * N - a * (a - 1) // 2 + (b - a) for i, a in enumerate(occ) for b in occ[i:]]
+    other = np.setdiff1d(np.arange(K64.shape[2]), cols)
+    assert np.array_equal(Kf[:, :, other], Kr[:, :, other])
+    scale = np.abs(K64).max()
+    assert np.abs(Kf[:, :, cols] - K64[:, :, cols]).max() < 1e-13 * scale
+    er = np.abs(Kr[:, :, cols] - K64[:, :, cols]).max()
+    _note(f"  reduced occupied block: max |dK| {er:.2e} (max |K| {scale:.2e})")
+    assert 0 < er < 2.0**-16 * scale
 
 
 @pytest.mark.parametrize("chunk_rows", [None, 1000])
