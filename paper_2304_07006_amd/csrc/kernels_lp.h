@@ -174,6 +174,17 @@ __device__ __forceinline__ float scalar_S_fast(float r2, const JasDev& J) {
 // NC = 1 builds F = S rho instead (the scalar kernel of the two-body TC
 // integrals, one component), with the same tiling.
 constexpr int kLpThreads = 512;
+// Column blocks of 16 per wave and pair columns per workgroup.  The
+// one-component build (F) generates as much per k-step as the three-component
+// one but multiplies a third as much, so in the 3-product form each wave takes
+// twice the columns (8 blocks), halving the generation per MFMA (Pade
+// Jastrow: the power series' two polynomials leave no registers for it).
+template <int KIND, int FORM, int NC> struct LpTile {
+    static constexpr int NB = (NC == 1 && FORM == 3 && KIND == 0) ? 8 : 4;
+    static constexpr int cols = (kLpThreads / 64) * 16 * NB;
+};
+static_assert(LpTile<0, 3, 3>::cols == kLpCols && LpTile<1, 3, 3>::cols == kLpCols,
+              "the K build tiles ldL = a multiple of kLpCols");
 template <int KIND, int FORM, int NC = 3>
 __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict__ pos,
                                                            const void* __restrict__ rho_lp, size_t split_stride,
@@ -182,7 +193,8 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
                                                            int cap, int ncol, int n_ct, int nseg) {
     typedef typename Lp<FORM>::T T;
     constexpr int NS = Lp<FORM>::NS;
-    constexpr int NB = 4;                          // 16-column blocks per wave
+    constexpr int NB = LpTile<KIND, FORM, NC>::NB;       // 16-column blocks per wave
+    constexpr int kWgCols = LpTile<KIND, FORM, NC>::cols;
     // two generation buffers as distinct arrays, so the compiler can prove the
     // writes of the next k-step do not alias the reads of the current one
     constexpr int kARow = LpARow<FORM>::v;
@@ -203,7 +215,7 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
     // advance through g' together.  Column tiles with idle waves finish early
     // and would stagger every later workgroup (and break that sharing), so
     // they are dispatched last, after all full tiles of all segments.
-    const int n_full = ((n_ct - 1) * kLpCols + 7 * 64 < ncol) ? n_ct : n_ct - 1;
+    const int n_full = ((n_ct - 1) * kWgCols + 7 * 16 * NB < ncol) ? n_ct : n_ct - 1;
     int rt, ct, seg;
     {
         const int id = blockIdx.x, nf = n_rt * n_full * nseg;
@@ -227,10 +239,10 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
     const d4 pr = pos[g0 + min(rt * kLpRows + grow, rows - 1)];
     // MFMA role
     const int l16 = lane & 15, lk = lane >> 4;
-    const int col0 = ct * kLpCols + wave * 64 + l16;
-    // waves whose 64 columns all lie at or beyond ncol (never read) only help
+    const int col0 = ct * kWgCols + wave * 16 * NB + l16;
+    // waves whose columns all lie at or beyond ncol (never read) only help
     // to generate the shared tiles: no operand loads, MFMAs or stores
-    const bool active = ct * kLpCols + wave * 64 < ncol;
+    const bool active = ct * kWgCols + wave * 16 * NB < ncol;
 
     f4 acc[NC][2][NB];
 #pragma unroll

@@ -373,7 +373,9 @@ xtc_status pack_any(int form, const double* src, int nrows, int ld_src, int ncol
 template <int KIND, int FORM, int NC = 3>
 void launch_build_lp(const Layout& L, int g0, int rows, const JasDev& J, void* ws, hipStream_t st) {
     const int n_rt = (rows + kLpRows - 1) / kLpRows;
-    const int n_ct = L.ldL / kLpCols;
+    // ldL is a multiple of 512; a 1024-column tile past it has only inactive waves there
+    constexpr int cols = LpTile<KIND, FORM, NC>::cols;
+    const int n_ct = (L.ldL + cols - 1) / cols;
     hipLaunchKernelGGL((k_build_K_lp<KIND, FORM, NC>), dim3(n_rt * n_ct * L.nsegK), dim3(kLpThreads), 0, st,
                        at<d4>(ws, L.pos), at<void>(ws, L.rho_lp), (size_t)L.ngp * L.ldL, L.ldL, L.ngp, g0, rows, n_rt,
                        kSegK, J, at<float>(ws, L.Kpart), L.cap, L.ldP, n_ct, L.nsegK);
