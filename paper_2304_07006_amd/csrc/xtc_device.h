@@ -29,24 +29,43 @@ struct JasDev {
     float fd2coef[16];
 };
 
+// 1/sqrt(x) and 1/x in FP64 from the hardware approximations (v_rsq_f64,
+// v_rcp_f64) refined by two Newton steps each (each step squares the
+// relative error), for x > 0 and finite: a few ulp, against the longer
+// correctly rounded sequences the compiler emits for sqrt and division.
+__device__ __forceinline__ double rsq_f64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx, y * y, 1.5);
+    y = y * fma(-hx, y * y, 1.5);
+    return y;
+}
+__device__ __forceinline__ double rcp_f64(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = y * fma(-x, y, 2.0);
+    y = y * fma(-x, y, 2.0);
+    return y;
+}
+
 // u'(r)/r for the electron-electron Jastrow, from r^2; exactly 0 at r^2 == 0
 // (coincident points: the gradient of an isotropic function is taken as 0).
 //   Pade : u = r/(2(1+br))      -> u'/r = 1 / (2 r (1+br)^2)
 //   power: u = sum c_k t^k      -> u'/r = (sum k c_k t^(k-1)) / (r (1+r)^2)
 template <int KIND>
 __device__ __forceinline__ double du_over_r(double r2, const JasDev& J) {
-    const double r = __builtin_sqrt(r2);
+    const double s = rsq_f64(r2);                 // 1/r (not finite at r2 == 0: selected away)
+    const double r = r2 * s;
     double f;
     if constexpr (KIND == 0) {
-        const double t = fma(J.b, r, 1.0);
-        f = 0.5 / (r * t * t);
+        const double it = rcp_f64(fma(J.b, r, 1.0));
+        f = 0.5 * s * it * it;
     } else {
-        const double q = 1.0 / (1.0 + r);
+        const double q = rcp_f64(1.0 + r);
         const double t = r * q;
         double p = J.dcoef[15];
 #pragma unroll
         for (int k = 14; k >= 0; --k) p = fma(p, t, J.dcoef[k]);
-        f = p * q * q / r;
+        f = p * q * q * s;
     }
     return r2 > 0.0 ? f : 0.0;
 }
