@@ -21,7 +21,7 @@
 //   gpart [ceil(cap/32) * ngp/128][16], gacc [16], occw [N] f64, kidx [N],
 //   reduced forms: rhoR [NS][ngp][ldP] (row-major split rho), KbL
 //   [7][NS][cap][ldP] (row-major split operands of the chunk), split-BF16
-//   forms: GsL [NS][ldP][ldP] (row-major split Gbar)
+//   3-product form: GsL [2][ldP][ldP] (row-major split Gbar)
 // and with XTC_WITH_TC2 (two-body TC integrals; ldN = N^2 rounded up to 128):
 //   Atc [ldP][ldP], Btc [ldN][ldP] FP64 accumulators, Ftc [cap][ldP],
 //   Rg [3][cap][ldN] (w phi grad phi of the chunk)
@@ -156,7 +156,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.occw = off;    off = align_up(off + (L.bwd ? (size_t)L.N * sizeof(double) : 0), kAlign);
     L.kidx = off;    off = align_up(off + (L.bwd ? (size_t)L.N * sizeof(int) : 0), kAlign);
     L.rhoR = off;    off = align_up(off + (L.bwd && lp ? (size_t)L.ns * L.ngp * L.ldP * L.es : 0), kAlign);
-    const bool bsplit = L.bwd && (L.form == 3 || L.form == 6);   // split-BF16 X Gbar products
+    const bool bsplit = L.bwd && L.form == 3;   // split-BF16 X Gbar products (3-product form)
     L.GsL = off;     off = align_up(off + (bsplit ? (size_t)L.ns * L.ldP * L.ldP * L.es : 0), kAlign);
     L.Atc = off;     off = align_up(off + (L.tc2 ? (size_t)L.ldP * L.ldP * sizeof(double) : 0), kAlign);
     L.Btc = off;     off = align_up(off + (L.tc2 ? (size_t)L.ldN * L.ldP * sizeof(double) : 0), kAlign);
@@ -539,10 +539,10 @@ xtc_status split_rows_any(int form, const double* src, size_t n, void* dst, size
     return launched("split_rows");
 }
 
-// Y_c = X_c Gbar for the seven adjoint operands in split BF16 (k_nt_bf16,
-// FP32 accumulation over all pairs): X split [7][NS][rows][ldP], Gbar split
-// [NS][ldP][ldP], Y [7][cap][ldP] FP64.  Components share the Gbar operand in
-// groups of 3 + 4 (six-product form: 3 + 3 + 1, for its register budget).
+// Y_c = X_c Gbar for the seven adjoint operands in the split-BF16 3-product
+// form (k_nt_bf16, FP32 accumulation over all pairs): X split
+// [7][2][rows][ldP], Gbar split [2][ldP][ldP], Y [7][cap][ldP] FP64.
+// Components share the Gbar operand in groups of 3 + 4.
 template <int FORM, int NC>
 xtc_status xg_group(const __bf16* X, size_t a_comp, size_t a_split, int rows, const __bf16* Gs, int ldP, int c0,
                     double* Y, size_t ystride, hipStream_t st) {
@@ -553,16 +553,11 @@ xtc_status xg_group(const __bf16* X, size_t a_comp, size_t a_split, int rows, co
     return launched("gemm_xg_bf16");
 }
 
-xtc_status xg_bf16(int form, const __bf16* X, size_t a_comp, size_t a_split, int rows, const __bf16* Gs, int ldP,
-                   double* Y, size_t ystride, hipStream_t st) {
+xtc_status xg_bf16x3(const __bf16* X, size_t a_comp, size_t a_split, int rows, const __bf16* Gs, int ldP, double* Y,
+                     size_t ystride, hipStream_t st) {
     xtc_status s;
-    if (form == 3) {
-        if ((s = xg_group<3, 3>(X, a_comp, a_split, rows, Gs, ldP, 0, Y, ystride, st)) != XTC_OK) return s;
-        return xg_group<3, 4>(X, a_comp, a_split, rows, Gs, ldP, 3, Y, ystride, st);
-    }
-    if ((s = xg_group<6, 3>(X, a_comp, a_split, rows, Gs, ldP, 0, Y, ystride, st)) != XTC_OK) return s;
-    if ((s = xg_group<6, 3>(X, a_comp, a_split, rows, Gs, ldP, 3, Y, ystride, st)) != XTC_OK) return s;
-    return xg_group<6, 1>(X, a_comp, a_split, rows, Gs, ldP, 6, Y, ystride, st);
+    if ((s = xg_group<3, 3>(X, a_comp, a_split, rows, Gs, ldP, 0, Y, ystride, st)) != XTC_OK) return s;
+    return xg_group<3, 4>(X, a_comp, a_split, rows, Gs, ldP, 3, Y, ystride, st);
 }
 
 xtc_status build_K_any(const Layout& L, const JasDev& J, int g0, int rows, double* K, bool occ64, void* ws,
@@ -782,7 +777,11 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
     hipLaunchKernelGGL(k_make_gbar, dim3((L.ldP + 255) / 256, L.ldP), dim3(256), 0, st, gV2, gh1, gE0,
                        at<double>(ws, L.occw), L.N, L.ldP, G);
     if ((s = launched("make_gbar")) != XTC_OK) return s;
-    const bool bsplit = L.form == 3 || L.form == 6;
+    // the X Gbar products in split BF16 only in the 3-product form: the MFMA's
+    // FP32 accumulation rounds with a small negative bias, which the six-product
+    // form (twice the accumulations per k-step, and a smaller random error to
+    // hide it) carries coherently into the gradient; it keeps them in FP64
+    const bool bsplit = L.form == 3;
     if (bsplit &&
         (s = split_rows_any(L.form, G, (size_t)L.ldP * L.ldP, at<void>(ws, L.GsL), (size_t)L.ldP * L.ldP, st)) != XTC_OK)
         return s;
@@ -810,8 +809,8 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
             for (int y = 0; y < 7; ++y)
                 if ((s = split_rows_any(L.form, src[y], a_split, xs + y * a_comp * L.es, a_split, st)) != XTC_OK)
                     return s;
-            if ((s = xg_bf16(L.form, (const __bf16*)xs, a_comp, a_split, rows, at<__bf16>(ws, L.GsL), L.ldP, Y,
-                             ystride, st)) != XTC_OK)
+            if ((s = xg_bf16x3((const __bf16*)xs, a_comp, a_split, rows, at<__bf16>(ws, L.GsL), L.ldP, Y, ystride,
+                               st)) != XTC_OK)
                 return s;
         } else {
             const int n_it = (rows + 63) / 64, n_jt = L.ldP / 128;
