@@ -115,6 +115,10 @@ typedef struct {
  *   xyz [Ng][3] bohr, w [Ng], phi [N][Ng] (orthonormal under w: not checked),
  *   occ [nocc] HOST int32, distinct, in [0,N);
  *   occ_n [nocc] HOST double, finite, or NULL.
+ * Limits: 1 <= N <= 256, 1 <= nocc <= min(N, 128), Ng >= 1 (XTC_E_ARG
+ * otherwise); nocc * N * 32 bytes (the occupied columns of rho and K staged
+ * on chip per grid point) at most 159 KB, i.e. nocc * N <= 5088
+ * (XTC_E_UNSUPPORTED otherwise).
  *
  * Open shell (restricted open-shell working equations, Appendix A): with
  * occ_n_beta != NULL the alpha and beta densities differ,

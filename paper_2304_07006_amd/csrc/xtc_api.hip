@@ -69,6 +69,10 @@ constexpr int kESplitMax = 256;
 constexpr size_t kAlign = 256;
 constexpr int kMaxN = 256;
 constexpr size_t kLdsMax = 160 * 1024;
+// The kernels that stage the occupied columns in dynamic LDS (nocc N of
+// (rho, Kx, Ky, Kz)) also keep a few static reduction slots (at most 96 B);
+// a workgroup's static plus dynamic LDS must fit kLdsMax.
+constexpr size_t kLdsStaticReserve = 1024;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -230,7 +234,7 @@ xtc_status check_problem(const xtc_problem* pb) {
         if (pb->occ_n_beta && !std::isfinite(pb->occ_n_beta[i]))
             return fail(XTC_E_ARG, "occ_n_beta[%d] not finite", i);
     }
-    if ((size_t)pb->nocc * pb->N * 4 * sizeof(double) > kLdsMax)
+    if ((size_t)pb->nocc * pb->N * 4 * sizeof(double) > kLdsMax - kLdsStaticReserve)
         return fail(XTC_E_UNSUPPORTED, "nocc*N=%d exceeds the on-chip staging of the intermediates",
                     pb->nocc * pb->N);
     return XTC_OK;
@@ -340,7 +344,10 @@ xtc_status run_intermediates(const Layout& L, const xtc_problem* pb, const doubl
     if (lds > 64 * 1024) {
         const hipError_t e = hipFuncSetAttribute((const void*)k_intermediates,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return fail(XTC_E_HIP, "intermediates LDS attribute: %s", hipGetErrorString(e));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();   // do not leave the error for the caller's next HIP call
+            return fail(XTC_E_HIP, "intermediates LDS attribute: %s", hipGetErrorString(e));
+        }
     }
     for (int sp = 0; sp < L.nspin; ++sp) {
         hipLaunchKernelGGL(k_intermediates, dim3(blocks), dim3(256), lds, st, rho_rows, K, rows, L.ldP, L.N,
@@ -824,7 +831,10 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
         if (lds > 64 * 1024) {
             const hipError_t e = hipFuncSetAttribute((const void*)k_adj_T, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      (int)lds);
-            if (e != hipSuccess) return fail(XTC_E_HIP, "adj_T LDS attribute: %s", hipGetErrorString(e));
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(XTC_E_HIP, "adj_T LDS attribute: %s", hipGetErrorString(e));
+            }
         }
         hipLaunchKernelGGL(k_adj_T, dim3(std::min(rows, 4096)), dim3(256), lds, st, rho_rows, Kc, Y, ystride, rows,
                            L.ldP, L.N, occ, at<double>(ws, L.T), at<double>(ws, L.Wbar));

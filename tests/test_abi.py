@@ -62,6 +62,10 @@ def _call_build(lib, c, j, g0=0, g1=10, prec=0, K=0x2000, ws=None, nbytes=None):
 
 @pytest.mark.parametrize("mut,expect", [
     (dict(N=0), xtc.XTC_E_ARG),
+    (dict(N=257, occ=(0,)), xtc.XTC_E_ARG),                 # above the largest supported N (256)
+    (dict(Ng=0), xtc.XTC_E_ARG),                             # empty grid
+    (dict(occ=()), xtc.XTC_E_ARG),                           # no occupied orbital
+    (dict(N=256, occ=tuple(range(20))), xtc.XTC_E_UNSUPPORTED),   # nocc N 32 B over the on-chip staging
     (dict(occ=(0, 0)), xtc.XTC_E_ARG),
     (dict(occ=(0, 9)), xtc.XTC_E_ARG),
     (dict(occ=(-1,)), xtc.XTC_E_ARG),
