@@ -68,6 +68,23 @@ def test_gradient_euler_and_fd(torch_cuda):
         assert abs(fd - g[k]) < 1e-8 * max(1.0, abs(g[k])), (k, fd, g[k])
 
 
+def test_gradient_at_the_largest_occupied_set(torch_cuda):
+    """nocc = 24, the most the adjoint's local kernels hold in registers:
+    Euler identity and GPU central differences (N=32, ragged chunks)."""
+    occ = inputs.random_occ(32, 24, seed=9)
+    p, coef, D, G = _case(32, 24, 900, 4, 37, occ=occ)
+    _note("case: backward N=32 n=24 (largest supported) chunk=320")
+    g = _gpu_grad(torch_cuda, p, coef, D, G, chunk_rows=320)
+    L = _gpu_loss(torch_cuda, p, coef, D, G)
+    assert abs(np.dot(coef, g) - 2 * L) < 1e-9 * max(1.0, abs(L))
+    h = 1e-5
+    for k in (0, 3):
+        e = np.zeros_like(coef)
+        e[k] = h
+        fd = (_gpu_loss(torch_cuda, p, coef + e, D, G) - _gpu_loss(torch_cuda, p, coef - e, D, G)) / (2 * h)
+        assert abs(fd - g[k]) < 1e-8 * max(1.0, abs(g[k])), (k, fd, g[k])
+
+
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16x6", "fp32"])
 @pytest.mark.parametrize("N,nocc,Ng,nc,seed,chunk", [(12, 3, 900, 3, 34, None), (24, 5, 1500, 6, 36, 640)])
 def test_gradient_reduced_precision_close(torch_cuda, prec, N, nocc, Ng, nc, seed, chunk):
