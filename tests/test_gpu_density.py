@@ -186,14 +186,16 @@ def test_open_shell_with_equal_spins_is_the_closed_shell(torch_cuda):
     assert abs(E0 - E0c) < 1e-14
 
 
-def test_frozen_core_folding(torch_cuda):
+@pytest.mark.parametrize("core,act", [([0, 1], list(range(2, 24))),      # the usual split
+                                      ([], list(range(24))),              # no core: the identity
+                                      ([3, 0], [5, 2, 23, 7])])           # unsorted lists, orbitals left out
+def test_frozen_core_folding(torch_cuda, core, act):
     """xtc_frozen_core on the GPU outputs against the oracle's frozen-core
     equations applied to the oracle's outputs (xTC-FC)."""
     from oracle import factorised as fb
     from paper_2304_07006_amd import xtc
     p = inputs.make_problem(24, 4, 1500, 6, "chain", "pade", seed=49)
-    core, act = [0, 1], list(range(2, 24))
-    _note("case: N24 frozen core (2 core, 22 active) fp64")
+    _note(f"case: N24 frozen core {core} / {len(act)} active fp64")
     V2o, h1o, E0o = fb.closed_shell(p.xyz, p.w, p.phi, p.occ, p.jastrow)
     Vf, hf, Ef = fb.frozen_core(V2o, h1o, E0o, core, act)
     V2, h1, E0 = xtc.forward(p, prec="fp64", chunk_rows=600)
@@ -203,6 +205,8 @@ def test_frozen_core_folding(torch_cuda):
     assert np.abs(Vg - Vf).max() < TOL_ABS
     assert np.abs(hg - hf).max() < TOL_ABS
     assert abs(Eg - Ef) < TOL_ABS
+    if not core:
+        assert Eg == float(E0.cpu()[0]) and np.array_equal(hg, h1.cpu().numpy())
 
 
 @pytest.mark.parametrize("kind,N,Ng,nc,chunk,prec", [("pade", 8, 2000, 2, 700, "fp64"),
