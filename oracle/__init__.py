@@ -14,7 +14,13 @@ three-body interactions in transcorrelated methods"):
                       ordering in determinant space.
 * ``factorised``   -- tier B: the closed-shell working equations (Appendix B,
                       eq. tcmf:2el with the intermediates eq. tcmf:inter), for
-                      any orbital subset.
+                      any orbital subset and any diagonal per-spin density
+                      (occupation numbers); the restricted open-shell
+                      equations (Appendix A); the frozen-core folding of the
+                      results (xTC-FC).
+* ``tc2``          -- the two-body TC integrals on the grid (Theory, the
+                      definition of K), as the definition written out and in
+                      factorised form.
 * ``gradient``     -- the differentiation loss and its exact gradient with
                       respect to the Jastrow coefficients.
 * ``lowdin``       -- symmetric orthonormalisation under the grid weights.
@@ -23,4 +29,4 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the HIP path
 and never takes an input computed by it.
 """
-from . import jastrow, explicit, factorised, gradient, lowdin  # noqa: F401
+from . import jastrow, explicit, factorised, gradient, lowdin, tc2  # noqa: F401
