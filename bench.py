@@ -312,7 +312,8 @@ def main():
     ap.add_argument("--compare", default="fp64", help="form run once beside the headline one ('none' to skip)")
     ap.add_argument("--chunk", type=int, default=None,
                     help="grid rows per chunk (default: Ng/10 for FP64, Ng/20 for the reduced forms: equal launches)")
-    ap.add_argument("--cpu-rows", type=int, default=300, help="grid points of the CPU oracle sample (0: skip)")
+    ap.add_argument("--cpu-rows", type=int, default=400,
+                    help="grid points of the CPU oracle sample, about 10-15 s on the host (0: skip)")
     ap.add_argument("--density", default="closed",
                     help="reference density: closed | sa:ND,NS | natural:NACT (see apply_density)")
     ap.add_argument("--tc2", action="store_true",

@@ -569,6 +569,118 @@ __global__ __launch_bounds__(256) void k_gemm_tn_lp(const void* __restrict__ Clp
         }
 }
 
+// The same product in split BF16 with both operands staged in LDS.
+// Workgroup 512 threads = 8 waves as 4 (P) x 2 (R), tile 256 (P) x 256 (R),
+// wave tile 64 x 128 (4 x 8 MFMA blocks, as in k_gemm_tn_lp).  Per k-step (32
+// grid rows) the k8-packed tiles of C and D (256 columns each, all splits)
+// are copied once into LDS through registers (the next k-step's copy is
+// loaded while the current one is multiplied) and read by the 2 (C) and 4 (D)
+// waves that share them, instead of every wave fetching its own.  An LDS row
+// (one 8-row group of one split, 256 columns x 16 bytes) is padded by 128
+// bytes, so each 16-lane phase of a b128 read covers all 64 banks.
+// ldC and ldD are multiples of 256; (component, grid row) k-steps of a
+// workgroup's group and segment run as one sequence.
+constexpr int kTnThreads = 512;
+template <int FORM>
+__global__ __launch_bounds__(kTnThreads) void k_gemm_tn_lds(const void* __restrict__ Clp, int ldC, size_t c_split,
+                                                            const void* __restrict__ Dlp, int ldD, size_t d_split,
+                                                            int rows32, int n_pt, int pmax, int rmax, int cpw,
+                                                            int seg_len, int nseg_r, float* __restrict__ part) {
+    static_assert(FORM == 3 || FORM == 6, "split-BF16 forms only");
+    constexpr int NS = Lp<FORM>::NS;
+    constexpr int kRowB = 256 * 16 + 128;           // bytes of one (split, 8-row group) LDS row
+    constexpr int kTileB = NS * 4 * kRowB;          // one operand's tile of one k-step
+    constexpr int kVec = NS * 4 * 256 / kTnThreads; // 16-byte vectors per thread and operand
+    __shared__ __attribute__((aligned(16))) char sm[2][2][kTileB];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int pt = blockIdx.x % n_pt, rt = blockIdx.x / n_pt;
+    if (pt * 256 >= pmax || rt * 256 >= rmax) return;
+    const int c0 = (blockIdx.y / nseg_r) * cpw, sg = blockIdx.y % nseg_r;
+    const int gs = sg * seg_len, ge = min(rows32, gs + seg_len);
+    const int nk = (ge - gs) / kLpK;                // k-steps per component
+    const int nq = nk * cpw;
+    const int l16 = lane & 15, lk = lane >> 4;
+    const int wp = wave & 3, wr = wave >> 2;
+    const __bf16* Cb = (const __bf16*)Clp;
+    const __bf16* Db = (const __bf16*)Dlp;
+
+    // loader role: vector v = tid + 512 i is (split s, 8-row group g8, column col)
+    int lcol[kVec], lg8[kVec], ls[kVec];
+#pragma unroll
+    for (int i = 0; i < kVec; ++i) {
+        const int v = threadIdx.x + kTnThreads * i;
+        lcol[i] = v & 255;
+        lg8[i] = (v >> 8) & 3;
+        ls[i] = v >> 10;
+    }
+    bf8 sc[kVec], sd[kVec];
+    auto load = [&](int q) {
+        const int comp = c0 + q / nk, g8 = (gs + kLpK * (q % nk)) / 8;
+        const __bf16* cb = Cb + (size_t)comp * NS * c_split;
+        const __bf16* db = Db + (size_t)comp * NS * d_split;
+#pragma unroll
+        for (int i = 0; i < kVec; ++i) {
+            sc[i] = *(const bf8*)(cb + ls[i] * c_split + ((size_t)(g8 + lg8[i]) * ldC + pt * 256 + lcol[i]) * 8);
+            sd[i] = *(const bf8*)(db + ls[i] * d_split + ((size_t)(g8 + lg8[i]) * ldD + rt * 256 + lcol[i]) * 8);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < kVec; ++i) {
+            const int o = (ls[i] * 4 + lg8[i]) * kRowB + lcol[i] * 16;
+            *(bf8*)(&sm[buf][0][o]) = sc[i];
+            *(bf8*)(&sm[buf][1][o]) = sd[i];
+        }
+    };
+
+    f4 acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+    auto multiply = [&](int buf) {
+        bf8 av[4][NS];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                av[i][s] = *(const bf8*)&sm[buf][0][(s * 4 + lk) * kRowB + (64 * wp + 16 * i + l16) * 16];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            bf8 bv[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                bv[s] = *(const bf8*)&sm[buf][1][(s * 4 + lk) * kRowB + (128 * wr + 16 * j + l16) * 16];
+#pragma unroll
+            for (int t = 0; t < Terms<FORM>::n; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    acc[i][j] = mma_bf16(av[i][Terms<FORM>::a[t]], bv[Terms<FORM>::b[t]], acc[i][j]);
+        }
+    };
+    if (nq > 0) {
+        load(0);
+        store(0);
+        __syncthreads();
+        for (int q = 0; q < nq; ++q) {
+            const int cur = q & 1;
+            if (q + 1 < nq) load(q + 1);     // uniform branch
+            multiply(cur);
+            if (q + 1 < nq) store(cur ^ 1);
+            __syncthreads();
+        }
+    }
+    float* out = part + (size_t)blockIdx.y * ldC * ldD;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int P = pt * 256 + 64 * wp + 16 * i + 4 * lk + v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) out[(size_t)P * ldD + rt * 256 + 128 * wr + 16 * j + l16] = acc[i][j][v];
+        }
+}
+
 // M[P][R] (+)= sum_s part[s][P][R] in FP64 (fixed order), P < pmax, R < rmax;
 // part[s] has leading dimension ldpart and starts sstride floats after part[s-1].
 __global__ void k_reduce_M(const float* __restrict__ part, int nseg, size_t sstride, int ldpart, int pmax, int rmax,

@@ -479,8 +479,17 @@ xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double
 // number of partials written through *nparts.
 xtc_status gemm_tn_lp(int form, const void* C, int ldC, size_t c_split, const void* D, int ldD, size_t d_split,
                       int rows32, int pmax, int rmax, int ncomp, int cpw, float* part, int* nparts, hipStream_t st) {
-    const int n_pt = ldC / 128, n_rt = ldD / 256;
     const int nseg_r = (rows32 + kSegM - 1) / kSegM;
+    if (form == 3 && ldC % 256 == 0 && ldD % 256 == 0) {
+        // both operands staged in LDS (256 x 256 tiles)
+        const int n_pt = ldC / 256, n_rt = ldD / 256;
+        const dim3 grid(n_pt * n_rt, (ncomp / cpw) * nseg_r);
+        hipLaunchKernelGGL((k_gemm_tn_lds<3>), grid, dim3(kTnThreads), 0, st, C, ldC, c_split, D, ldD, d_split, rows32,
+                           n_pt, pmax, rmax, cpw, kSegM, nseg_r, part);
+        *nparts = (int)grid.y;
+        return launched("gemm_tn_lds");
+    }
+    const int n_pt = ldC / 128, n_rt = ldD / 256;
     const dim3 grid(n_pt * n_rt, (ncomp / cpw) * nseg_r);
     if (form == 1)
         hipLaunchKernelGGL((k_gemm_tn_lp<1>), grid, dim3(256), 0, st, C, ldC, c_split, D, ldD, d_split, rows32, n_pt,
