@@ -11,17 +11,19 @@
 
 namespace xtc {
 
-// S = u'' + 2 u'/r + u'^2 from r^2 in FP64; exactly 0 at r^2 == 0.
+// S = u'' + 2 u'/r + u'^2 from r^2 in FP64 (1/r and the reciprocals from the
+// Newton-refined hardware approximations); exactly 0 at r^2 == 0.
 template <int KIND>
 __device__ __forceinline__ double scalar_S(double r2, const JasDev& J) {
-    const double r = __builtin_sqrt(r2);
+    const double s = rsq_f64(r2);                 // 1/r (not finite at r2 == 0: selected away)
+    const double r = r2 * s;
     double up, upp;
     if constexpr (KIND == 0) {
-        const double it = 1.0 / fma(J.b, r, 1.0);
+        const double it = rcp_f64(fma(J.b, r, 1.0));
         up = 0.5 * it * it;
         upp = -J.b * it * it * it;
     } else {
-        const double q = 1.0 / (1.0 + r);
+        const double q = rcp_f64(1.0 + r);
         const double t = r * q;
         double p1 = J.dcoef[15], p2 = J.d2coef[15];
 #pragma unroll
@@ -33,8 +35,8 @@ __device__ __forceinline__ double scalar_S(double r2, const JasDev& J) {
         up = p1 * q2;
         upp = q2 * (p2 * q2 - 2.0 * p1 * q);
     }
-    const double s = upp + 2.0 * up / r + up * up;
-    return r2 > 0.0 ? s : 0.0;
+    const double v = upp + 2.0 * up * s + up * up;
+    return r2 > 0.0 ? v : 0.0;
 }
 
 // F[g - g0][P] = sum_{g'} S(g, g') rho[g'][P] for the rows of the chunk
