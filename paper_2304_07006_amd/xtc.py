@@ -145,11 +145,38 @@ class DeviceProblem:
         return self.c.Ng
 
 
+def _dev(t, numel, name, dtype="float64", required=True):
+    """Check a tensor handed to the C ABI, which takes plain pointers and
+    cannot check sizes itself: on a HIP device, contiguous, of the expected
+    dtype and holding at least `numel` elements."""
+    if t is None:
+        if required:
+            raise ValueError(f"{name} is required")
+        return
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != getattr(torch, dtype):
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, {numel} needed")
+
+
 def device_problem(xyz, w, phi, occ, device="cuda", occ_n=None, occ_n_beta=None) -> DeviceProblem:
     """occ: orbitals of the reference density; occ_n: their per-spin
     occupations (None: 1 each, the closed-shell determinant); occ_n_beta: the
-    beta occupations of an open-shell reference (then occ_n is alpha)."""
+    beta occupations of an open-shell reference (then occ_n is alpha).
+    xyz [Ng][3], w [Ng], phi [N][Ng]."""
     import torch
+    if np.ndim(phi) != 2:
+        raise ValueError("phi must be [N][Ng]")
+    Ng = np.shape(phi)[1]
+    if np.shape(xyz) != (Ng, 3) or np.shape(w) != (Ng,):
+        raise ValueError(f"xyz must be [{Ng}][3] and w [{Ng}] for phi of shape {np.shape(phi)}")
+    if np.ndim(occ) != 1:
+        raise ValueError("occ must be a 1-D list of orbital indices")
     t_xyz = torch.as_tensor(np.ascontiguousarray(xyz, dtype=np.float64)).to(device)
     t_w = torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64)).to(device)
     t_phi = torch.as_tensor(np.ascontiguousarray(phi, dtype=np.float64)).to(device)
@@ -189,30 +216,53 @@ def xtc_workspace_size(dp: DeviceProblem, prec: int, chunk_rows: int) -> int:
 
 
 def xtc_prepare(dp, prec, chunk_rows, ws, stream=None):
+    _dev(ws, 1, "ws", "uint8")
     _check(load().xtc_prepare(ctypes.byref(dp.c), prec, chunk_rows, _ptr(ws), ws.numel(), _stream(stream)))
 
 
+def _nspin(dp):
+    return 2 if getattr(dp, "open_shell", False) else 1
+
+
 def xtc_build_K(dp, jas: XtcJastrow, g0, g1, prec, K, ws, stream=None):
+    _dev(ws, 1, "ws", "uint8")
+    _dev(K, 3 * max(0, g1 - g0) * xtc_pair_ld(dp.N), "K")
     _check(load().xtc_build_K(ctypes.byref(dp.c), ctypes.byref(jas), g0, g1, prec, _ptr(K), _ptr(ws),
                               ws.numel(), _stream(stream)))
 
 
 def xtc_contract_2body(dp, K, g0, g1, prec, flags, V2, ws, stream=None):
+    _dev(ws, 1, "ws", "uint8")
+    _dev(K, 3 * max(0, g1 - g0) * xtc_pair_ld(dp.N), "K")
+    _dev(V2, (3 if _nspin(dp) == 2 else 1) * dp.N ** 4, "V2", required=bool(flags & XTC_FINALIZE))
     _check(load().xtc_contract_2body(ctypes.byref(dp.c), _ptr(K), g0, g1, prec, flags, _ptr(V2), _ptr(ws),
                                      ws.numel(), _stream(stream)))
 
 
 def xtc_contract_1body_0body(dp, K, g0, g1, prec, flags, h1, E0, ws, stream=None):
+    _dev(ws, 1, "ws", "uint8")
+    _dev(K, 3 * max(0, g1 - g0) * xtc_pair_ld(dp.N), "K")
+    _dev(h1, _nspin(dp) * dp.N ** 2, "h1", required=bool(flags & XTC_FINALIZE))
+    _dev(E0, 1, "E0", required=bool(flags & XTC_FINALIZE))
     _check(load().xtc_contract_1body_0body(ctypes.byref(dp.c), _ptr(K), g0, g1, prec, flags, _ptr(h1), _ptr(E0),
                                            _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def xtc_backward(dp, jas: XtcJastrow, prec, gV2, gh1, gE0, gcoef, ws, stream=None):
+    _dev(ws, 1, "ws", "uint8")
+    _dev(gV2, dp.N ** 4, "gV2", required=False)
+    _dev(gh1, dp.N ** 2, "gh1", required=False)
+    _dev(gcoef, max(1, jas.ncoef), "gcoef")
     _check(load().xtc_backward(ctypes.byref(dp.c), ctypes.byref(jas), prec, _ptr(gV2), _ptr(gh1), float(gE0),
                                _ptr(gcoef), _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def xtc_lowdin(N, Ng, chi, w, phi, lam, ws, stream=None):
+    _dev(ws, 1, "ws", "uint8")
+    _dev(chi, N * Ng, "chi")
+    _dev(w, Ng, "w")
+    _dev(phi, N * Ng, "phi")
+    _dev(lam, N, "lambda", required=False)
     _check(load().xtc_lowdin(N, Ng, _ptr(chi), _ptr(w), _ptr(phi), _ptr(lam), _ptr(ws), ws.numel(),
                              _stream(stream)))
 
@@ -220,6 +270,8 @@ def xtc_lowdin(N, Ng, chi, w, phi, lam, ws, stream=None):
 def lowdin(chi, w, device="cuda"):
     """phi = S^{-1/2} chi and the eigenvalues of S on the device (FP64)."""
     import torch
+    if np.ndim(chi) != 2 or np.shape(w) != (np.shape(chi)[1],):
+        raise ValueError("chi must be [N][Ng] and w [Ng]")
     chi_t = torch.as_tensor(np.ascontiguousarray(chi, dtype=np.float64)).to(device)
     w_t = torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64)).to(device)
     N, Ng = chi_t.shape
@@ -289,6 +341,9 @@ def tc_two_body(problem, dphi, prec="fp64", chunk_rows=None, device="cuda", jast
     """Two-body TC integrals K2[p][q][r][s] = K_pr^qs (xtc_tc_2body) for an
     inputs.Problem; dphi [3][N][Ng] host or device.  Builds K chunk by chunk."""
     import torch
+    N, Ng = np.shape(problem.phi)
+    if tuple(dphi.shape) != (3, N, Ng):
+        raise ValueError(f"dphi must be [3][{N}][{Ng}], got {tuple(dphi.shape)}")
     dp = device_problem(problem.xyz, problem.w, problem.phi, problem.occ, device)
     p = (PRECISIONS[prec] if isinstance(prec, str) else prec) | XTC_WITH_TC2
     chunk = min(dp.Ng, chunk_rows or dp.Ng)
@@ -297,7 +352,8 @@ def tc_two_body(problem, dphi, prec="fp64", chunk_rows=None, device="cuda", jast
     xtc_prepare(dp, p, chunk, ws, stream)
     ldP = xtc_pair_ld(dp.N)
     Kbuf = torch.empty((3 * chunk * ldP,), dtype=torch.float64, device=device)
-    dphi_t = torch.as_tensor(np.ascontiguousarray(dphi, dtype=np.float64)).to(device)
+    dphi_t = torch.as_tensor(np.ascontiguousarray(dphi, dtype=np.float64)).to(device) \
+        if isinstance(dphi, np.ndarray) else dphi.to(device=device, dtype=torch.float64).contiguous()
     N = dp.N
     K2 = torch.empty((N, N, N, N), dtype=torch.float64, device=device)
     jas = make_jastrow(jastrow or problem.jastrow)
@@ -316,6 +372,9 @@ def frozen_core(V2, h1, E0, core, active, stream=None):
     returns (V2_act, h1_act, E_fc)."""
     import torch
     N = h1.shape[0]
+    _dev(V2, N ** 4, "V2")
+    _dev(h1, N ** 2, "h1")
+    _dev(E0, 1, "E0")
     c = np.ascontiguousarray(core, dtype=np.int32)
     a = np.ascontiguousarray(active, dtype=np.int32)
     na = len(a)
