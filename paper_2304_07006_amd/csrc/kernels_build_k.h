@@ -122,23 +122,37 @@ __global__ __launch_bounds__(256) void k_build_K_occ(const d4* __restrict__ pos,
 #pragma unroll
         for (int c = 0; c < NBLK; ++c) acc[x][c] = (d4){0.0, 0.0, 0.0, 0.0};
 
+    // operands of the next two k-steps in flight (a k-step's MFMAs are too short
+    // to cover the load latency of the one after it); near the end of the
+    // segment the last k-step is re-read into the slot that is never consumed
     const double* bp = rho_occ + (size_t)(gs + kq) * ldO + col;
     const d4* pp = pos + gs + kq;
-    double b[NBLK];
+    const int kl = ge - 4;                // last k-step of the segment
+    double b0[NBLK], b1[NBLK];
+    d4 p0, p1;
 #pragma unroll
-    for (int c = 0; c < NBLK; ++c) b[c] = bp[16 * c];
-    d4 pc = *pp;
+    for (int c = 0; c < NBLK; ++c) b0[c] = bp[16 * c];
+    p0 = *pp;
+    {
+        const size_t o = (size_t)(min(gs + 4, kl) - gs);
+#pragma unroll
+        for (int c = 0; c < NBLK; ++c) b1[c] = bp[o * ldO + 16 * c];
+        p1 = pp[o];
+    }
     for (int kk = gs; kk < ge; kk += 4) {
         double cb[NBLK];
 #pragma unroll
-        for (int c = 0; c < NBLK; ++c) cb[c] = b[c];
-        const d4 cp = pc;
-        if (kk + 4 < ge) {               // prefetch the next 4 grid columns
-            bp += (size_t)4 * ldO;
-            pp += 4;
+        for (int c = 0; c < NBLK; ++c) {
+            cb[c] = b0[c];
+            b0[c] = b1[c];
+        }
+        const d4 cp = p0;
+        p0 = p1;
+        {
+            const size_t o = (size_t)(min(kk + 8, kl) - gs);
 #pragma unroll
-            for (int c = 0; c < NBLK; ++c) b[c] = bp[16 * c];
-            pc = *pp;
+            for (int c = 0; c < NBLK; ++c) b1[c] = bp[o * ldO + 16 * c];
+            p1 = pp[o];
         }
         const double dx = pg.x - cp.x, dy = pg.y - cp.y, dz = pg.z - cp.z;
         const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
