@@ -457,16 +457,21 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
 // K[c][r][P] = sum_s part[s][c][r][P] in FP64 (fixed order), for c < nc, r < rows, P < ldP.
 __global__ void k_reduce_K(const float* __restrict__ part, int nseg, int cap, int ldL, int rows, int ldP,
                            double* __restrict__ K, int nc) {
-    const size_t n = (size_t)nc * rows * ldP;
+    // four consecutive pairs per thread (ldP, ldL and the component strides are
+    // multiples of 4): 16-byte partial loads, 32-byte stores, same summation order
+    const size_t n4 = (size_t)nc * rows * (ldP / 4);
     const size_t cstride = (size_t)cap * ldL;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int P = (int)(i % ldP);
-        const size_t cr = i / ldP;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
+        const int P = (int)(i % (ldP / 4)) * 4;
+        const size_t cr = i / (ldP / 4);
         const int r = (int)(cr % rows), c = (int)(cr / rows);
         const size_t o = c * cstride + (size_t)r * ldL + P;
-        double s = 0.0;
-        for (int q = 0; q < nseg; ++q) s += (double)part[(size_t)q * nc * cstride + o];
-        K[i] = s;
+        d4 s = (d4){0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < nseg; ++q) {
+            const f4 v = *(const f4*)(part + (size_t)q * nc * cstride + o);
+            s += (d4){(double)v[0], (double)v[1], (double)v[2], (double)v[3]};
+        }
+        *(d4*)(K + cr * ldP + P) = s;
     }
 }
 
@@ -685,13 +690,18 @@ __global__ __launch_bounds__(kTnThreads) void k_gemm_tn_lds(const void* __restri
 // part[s] has leading dimension ldpart and starts sstride floats after part[s-1].
 __global__ void k_reduce_M(const float* __restrict__ part, int nseg, size_t sstride, int ldpart, int pmax, int rmax,
                            double* __restrict__ M, int ldM, int accumulate) {
-    const size_t n = (size_t)pmax * rmax;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t P = i / rmax, R = i % rmax;
+    // four consecutive R per thread (rmax, ldpart, ldM and sstride are multiples
+    // of 4): 16-byte partial loads, 32-byte accumulator accesses
+    const size_t n4 = (size_t)pmax * (rmax / 4);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t P = i / (rmax / 4), R = (i % (rmax / 4)) * 4;
         const size_t o = P * ldpart + R;
-        double* m = M + P * ldM + R;
-        double s = accumulate ? *m : 0.0;
-        for (int q = 0; q < nseg; ++q) s += (double)part[q * sstride + o];
+        d4* m = (d4*)(M + P * ldM + R);
+        d4 s = accumulate ? *m : (d4){0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < nseg; ++q) {
+            const f4 v = *(const f4*)(part + q * sstride + o);
+            s += (d4){(double)v[0], (double)v[1], (double)v[2], (double)v[3]};
+        }
         *m = s;
     }
 }

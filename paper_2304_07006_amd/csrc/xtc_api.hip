@@ -453,8 +453,8 @@ xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double
     }
     xtc_status s;
     if ((s = launched("build_K_lp")) != XTC_OK) return s;
-    const size_t n = (size_t)3 * rows * L.ldP;
-    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
+    const size_t n4 = (size_t)3 * rows * L.ldP / 4;   // k_reduce_K: four pairs per thread
+    const unsigned blocks = (unsigned)std::min<size_t>((n4 + 255) / 256, 16384);
     hipLaunchKernelGGL(k_reduce_K, dim3(blocks), dim3(256), 0, st, at<float>(ws, L.Kpart), L.nsegK, L.cap, L.ldL,
                        rows, L.ldP, K, 3);
     if ((s = launched("reduce_K")) != XTC_OK) return s;
@@ -507,8 +507,8 @@ xtc_status gemm_tn_lp(int form, const void* C, int ldC, size_t c_split, const vo
 // M[P][R] (+)= sum of nparts partials of ldC x ldD floats, P < pmax, R < rmax.
 xtc_status reduce_parts(const float* part, int nparts, int ldC, int ldD, int pmax, int rmax, double* M, int ldM,
                         int accumulate, hipStream_t st) {
-    const size_t n = (size_t)pmax * rmax;
-    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
+    const size_t n4 = (size_t)pmax * rmax / 4;   // k_reduce_M: four R per thread
+    const unsigned blocks = (unsigned)std::min<size_t>((n4 + 255) / 256, 16384);
     hipLaunchKernelGGL(k_reduce_M, dim3(blocks), dim3(256), 0, st, part, nparts, (size_t)ldC * ldD, ldD, pmax, rmax, M,
                        ldM, accumulate);
     return launched("reduce_M");
@@ -966,8 +966,8 @@ xtc_status xtc_tc_2body(const xtc_problem* pb, const xtc_jastrow* jas, const dou
             else launch_build_lp<1, 6, 1>(L, g0, rows, J, ws, st);
         }
         if ((s = launched("build_F_lp")) != XTC_OK) return s;
-        const size_t n = (size_t)rows * L.ldP;
-        hipLaunchKernelGGL(k_reduce_K, dim3((unsigned)std::min<size_t>((n + 255) / 256, 16384)), dim3(256), 0, st,
+        const size_t n4 = (size_t)rows * L.ldP / 4;
+        hipLaunchKernelGGL(k_reduce_K, dim3((unsigned)std::min<size_t>((n4 + 255) / 256, 16384)), dim3(256), 0, st,
                            at<float>(ws, L.Kpart), L.nsegK, L.cap, L.ldL, rows, L.ldP, F, 1);
     }
     if ((s = launched("build_F")) != XTC_OK) return s;
