@@ -286,13 +286,27 @@ def lowdin(chi, w, device="cuda"):
 
 
 # ------------------------------------------------------------ whole pass --
+def auto_chunk(dp: DeviceProblem, prec: int, chunk_rows: int | None, fraction: float = 0.4) -> int:
+    """Grid rows per chunk: chunk_rows if given, else the largest of Ng, Ng/2,
+    Ng/4, ... (multiples of 32) whose workspace takes at most `fraction` of
+    the device memory that is free now."""
+    import torch
+    if chunk_rows:
+        return min(dp.Ng, int(chunk_rows))
+    free, _ = torch.cuda.mem_get_info()
+    chunk = dp.Ng
+    while chunk > 32 and xtc_workspace_size(dp, prec, chunk) > fraction * free:
+        chunk = max(32, ((chunk // 2 + 31) // 32) * 32)
+    return chunk
+
+
 class Pass:
     """Device buffers of one forward pass: workspace, one K chunk, outputs."""
 
     def __init__(self, dp: DeviceProblem, prec: int = XTC_FP64, chunk_rows: int | None = None, device="cuda"):
         import torch
         self.dp, self.prec = dp, prec
-        self.chunk = min(dp.Ng, chunk_rows or dp.Ng)
+        self.chunk = auto_chunk(dp, prec, chunk_rows)
         self.ldP = xtc_pair_ld(dp.N)
         nbytes = xtc_workspace_size(dp, prec, self.chunk)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
@@ -346,7 +360,7 @@ def tc_two_body(problem, dphi, prec="fp64", chunk_rows=None, device="cuda", jast
         raise ValueError(f"dphi must be [3][{N}][{Ng}], got {tuple(dphi.shape)}")
     dp = device_problem(problem.xyz, problem.w, problem.phi, problem.occ, device)
     p = (PRECISIONS[prec] if isinstance(prec, str) else prec) | XTC_WITH_TC2
-    chunk = min(dp.Ng, chunk_rows or dp.Ng)
+    chunk = auto_chunk(dp, p, chunk_rows)
     L = load()
     ws = torch.empty(xtc_workspace_size(dp, p, chunk), dtype=torch.uint8, device=device)
     xtc_prepare(dp, p, chunk, ws, stream)
@@ -399,7 +413,7 @@ def backward(dp: DeviceProblem, coef, gV2, gh1, gE0, prec="fp64", chunk_rows=Non
     """dL/dc for L = gE0 E0 + <gh1, h1> + <gV2, V2> (device tensors or None), power Jastrow."""
     import torch
     p = (PRECISIONS[prec] if isinstance(prec, str) else prec) | XTC_WITH_BACKWARD
-    chunk = min(dp.Ng, chunk_rows or dp.Ng)
+    chunk = auto_chunk(dp, p, chunk_rows)
     ws = torch.empty(xtc_workspace_size(dp, p, chunk), dtype=torch.uint8, device=device)
     xtc_prepare(dp, p, chunk, ws)
     g = torch.empty(len(coef), dtype=torch.float64, device=device)

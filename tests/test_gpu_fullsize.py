@@ -146,6 +146,25 @@ def test_full_size_forward_against_fp64(torch_cuda, problem):
     assert np.array_equal(ha, ha.T) and np.array_equal(hr, hr.T)
 
 
+def test_full_size_default_chunking(torch_cuda, problem):
+    """Without chunk_rows the binding picks the largest halving of Ng whose
+    workspace fits 40% of the free device memory.  The two-body term's FP32
+    segments follow the chunk rows, so V2 changes within the reduced form's
+    error (bar 1e-6); h1 and E0 are FP64 reductions."""
+    from paper_2304_07006_amd import xtc
+    p = problem
+    dp = xtc.device_problem(p.xyz, p.w, p.phi, p.occ)
+    chunk = xtc.auto_chunk(dp, xtc.XTC_BF16X3, None)
+    _note(f"case: {WORKLOAD} bf16x3 default chunk = {chunk} rows")
+    del dp
+    Va, ha, Ea = (t.cpu().numpy() for t in xtc.forward(p, prec="bf16x3"))
+    torch_cuda.cuda.empty_cache()
+    Vb, hb, Eb = (t.cpu().numpy() for t in xtc.forward(p, prec="bf16x3", chunk_rows=_chunk("bf16x3", p.Ng)))
+    _note(f"  |dV2| {np.abs(Va - Vb).max():.2e} |dh1| {np.abs(ha - hb).max():.2e} |dE0| {abs(Ea[0] - Eb[0]):.2e}")
+    assert 32 <= chunk <= p.Ng
+    assert np.abs(Va - Vb).max() < 1e-6 and np.abs(ha - hb).max() < 1e-10 and abs(Ea[0] - Eb[0]) < 1e-12
+
+
 def test_full_size_adjoint_euler(torch_cuda):
     """The loss E0 + <h1,D> + <V2,G> is homogeneous of degree 2 in the
     power-Jastrow coefficients, so c . dL/dc = 2L at any size; N=96,
