@@ -1,7 +1,8 @@
 """Edge cases of the HIP path against the oracle: the largest supported N
 (256) with the largest occupied set the on-chip staging of the intermediates
 takes (19: nocc N 32 B within 159 KB), checked on an orbital subset; a
-single orbital; every orbital occupied."""
+single orbital; every orbital occupied; a grid smaller than one tile; a
+single grid point."""
 import numpy as np
 import pytest
 
@@ -91,3 +92,28 @@ def test_every_orbital_occupied(torch_cuda, prec):
     V2, h1, E0 = xtc.forward(p, prec=prec, chunk_rows=192)
     ref = fb.closed_shell(p.xyz, p.w, p.phi, p.occ, p.jastrow)
     _check(V2.cpu().numpy(), h1.cpu().numpy(), float(E0.cpu()[0]), ref, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_grid_smaller_than_one_tile(torch_cuda, prec):
+    """Ng=40 (one padded 128-point block, ragged 32-row chunks: 32 + 8)."""
+    from oracle import factorised as fb
+    from paper_2304_07006_amd import xtc
+    p = inputs.make_problem(8, 2, 40, 2, "pair", "pade", seed=64)
+    _note(f"case: N=8 n=2 Ng=40 chunk=32 {prec}")
+    V2, h1, E0 = xtc.forward(p, prec=prec, chunk_rows=32)
+    ref = fb.closed_shell(p.xyz, p.w, p.phi, p.occ, p.jastrow)
+    _check(V2.cpu().numpy(), h1.cpu().numpy(), float(E0.cpu()[0]), ref,
+           "fp64" if prec == "fp64" else prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_single_grid_point(torch_cuda, prec):
+    """Ng=1: the only pair of points is the point with itself, where the
+    Jastrow gradient is 0, so K = 0 and every output vanishes exactly."""
+    from paper_2304_07006_amd import xtc
+    p = inputs.make_problem(8, 2, 40, 2, "pair", "pade", seed=65)
+    q = inputs.Problem(p.xyz[:1], p.w[:1], p.chi[:, :1], p.phi[:, :1], p.occ, p.centres, p.jastrow)
+    _note(f"case: N=8 n=2 Ng=1 {prec}")
+    V2, h1, E0 = xtc.forward(q, prec=prec)
+    assert not V2.any() and not h1.any() and float(E0.cpu()[0]) == 0.0
