@@ -299,7 +299,9 @@ def cpu_baseline(name, budget_rows):
             "sample": f"N={wl.N} n={wl.nocc} on a {budget_rows}-point grid from the same generator "
                       f"(full orbital set, Appendix-B equations in numpy FP64); {dt:.1f} s wall; "
                       f"rate = F_alg(sample)/time",
-            "seconds": dt}
+            "seconds": dt,
+            # F_alg of the whole workload at the sample's rate (extrapolated, not run)
+            "full_workload_seconds_extrapolated": f_alg(wl.N, wl.nocc, wl.Ng) / (F / dt)}
 
 
 def main():
