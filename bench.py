@@ -282,6 +282,34 @@ def run_backward(problem, prec, chunk, aux_seed, steps, warmup):
     return tf, tb, g, euler, torch.cuda.max_memory_allocated()
 
 
+def gemm_calibration(reps=10):
+    """Executed rate of the vendor BF16 GEMM (torch.matmul -> hipBLASLt) on
+    random normal operands: what a plain dense BF16 contraction sustains on
+    this device, as a scale for the K build's executed MFMA rate."""
+    import torch
+    torch.manual_seed(0)
+    rows = []
+    for M, N, K in ((8192, 8192, 8192), (7520, 8704, 32768), (16384, 16384, 16384)):
+        a = torch.randn(M, K, device="cuda", dtype=torch.bfloat16)
+        b = torch.randn(K, N, device="cuda", dtype=torch.bfloat16)
+        for _ in range(2):
+            c = a @ b
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            c = a @ b
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        rows.append({"M": M, "N": N, "K": K, "ms": ms, "tflops": 2.0 * M * N * K / ms / 1e9})
+        print(f"[calibration] bf16 GEMM {M}x{N}x{K}: {ms:.3f} ms, {rows[-1]['tflops']:.1f} TFLOP/s",
+              file=sys.stderr, flush=True)
+        del a, b, c
+        torch.cuda.empty_cache()
+    return rows
+
+
 def cpu_baseline(name, budget_rows):
     """The oracle (Appendix-B equations, numpy FP64) on the same workload's
     orbitals and generator, on a reduced grid of `budget_rows` points."""
@@ -325,6 +353,8 @@ def main():
                          "(default workload then N96-occ12-Ng100k)")
     ap.add_argument("--probe", action="store_true",
                     help="counter pass: one 1 GiB device copy (calibration) and one K-build launch, no JSON")
+    ap.add_argument("--gemm-calibration", action="store_true",
+                    help="time the vendor BF16 GEMM (torch.matmul) on random data instead, one JSON line")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two --probe counter runs into profiles/traffic_xtc_build_K.json (no GPU)")
     args = ap.parse_args()
@@ -344,6 +374,10 @@ def main():
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.gemm_calibration:
+        print(json.dumps({"calibration": "vendor BF16 GEMM (torch.matmul, random normal operands)",
+                          "runs": gemm_calibration()}), flush=True)
+        return
     if args.backward and args.workload == ap.get_default("workload"):
         args.workload = "N96-occ12-Ng100k"
     wl = inputs.WORKLOADS[args.workload]
