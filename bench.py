@@ -174,7 +174,8 @@ def run_gpu(problem, prec, steps, warmup, chunk):
                 e1.record(stream)
                 kev.append((e0, e1, g1 - g0))
             xtc.xtc_contract_2body(dp, K, g0, g1, ps.prec, flags, ps.V2, ps.ws)
-            xtc.xtc_contract_1body_0body(dp, K, g0, g1, ps.prec, flags, ps.h1, ps.E0, ps.ws)
+            xtc.xtc_contract_1body_0body(dp, K, g0, g1, ps.prec, flags | xtc.XTC_REUSE_INTERMEDIATES, ps.h1,
+                                         ps.E0, ps.ws)
 
     for _ in range(warmup):
         step(False)

@@ -84,7 +84,14 @@ enum { XTC_K_REDUCED_OCC = 0x40 };
 /* flags of the contraction calls */
 enum {
     XTC_RESET = 1,       /* zero the accumulator before adding this chunk           */
-    XTC_FINALIZE = 2     /* after adding this chunk, write the outputs              */
+    XTC_FINALIZE = 2,    /* after adding this chunk, write the outputs              */
+    /* xtc_contract_1body_0body only: the caller asserts that the workspace
+     * still holds this chunk's intermediates, computed by an
+     * xtc_contract_2body call on the same problem, workspace, K (contents
+     * unchanged), g0, g1 and prec with no other call on that workspace in
+     * between; they are then not recomputed.  Not checked: a false assertion
+     * gives wrong h1 and E0. */
+    XTC_REUSE_INTERMEDIATES = 4
 };
 
 /* Electron-electron Jastrow u(r12) (paper: Theory, Jastrow factorisation; the
@@ -196,6 +203,8 @@ xtc_status xtc_contract_2body(const xtc_problem *pb, const double *K,
  * With XTC_FINALIZE, write h1 (device [N][N] FP64, symmetric bitwise) and
  * E0 = -(2/3) sum_k n_k h1[k][k] (device, one FP64).  The reduction is always
  * FP64; `prec` names the arithmetic the workspace was prepared for.
+ * The intermediates A, B are recomputed from K unless flags has
+ * XTC_REUSE_INTERMEDIATES (directly after xtc_contract_2body on this chunk).
  * h1 and E0 may be NULL unless XTC_FINALIZE is set. */
 xtc_status xtc_contract_1body_0body(const xtc_problem *pb, const double *K,
                                     int32_t g0, int32_t g1, int32_t prec, int32_t flags,

@@ -725,14 +725,17 @@ xtc_status xtc_contract_1body_0body(const xtc_problem* pb, const double* K, int3
     if ((s = check_prec(prec)) != XTC_OK) return s;
     if (!K) return fail(XTC_E_ARG, "K is NULL");
     if ((s = check_align(K, "K")) != XTC_OK) return s;
-    if (flags & ~(XTC_RESET | XTC_FINALIZE)) return fail(XTC_E_ARG, "flags=%d unknown bits", flags);
+    if (flags & ~(XTC_RESET | XTC_FINALIZE | XTC_REUSE_INTERMEDIATES))
+        return fail(XTC_E_ARG, "flags=%d unknown bits", flags);
     if ((flags & XTC_FINALIZE) && (!h1 || !E0)) return fail(XTC_E_ARG, "h1/E0 NULL with XTC_FINALIZE");
     Layout L = make_layout(pb, prec);
     place_chunk(L, ws_bytes);
     if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
     if ((s = check_range(L, g0, g1)) != XTC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    if ((s = run_intermediates(L, pb, K, g0, g1, ws, st)) != XTC_OK) return s;
+    // the intermediates of this chunk (D = [A; B] and the per-row scalars S)
+    // are in the workspace already when the two-body call has just made them
+    if (!(flags & XTC_REUSE_INTERMEDIATES) && (s = run_intermediates(L, pb, K, g0, g1, ws, st)) != XTC_OK) return s;
     const int rows = g1 - g0;
     const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
     const size_t dstride = (size_t)L.cap * L.ldP;

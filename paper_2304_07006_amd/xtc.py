@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libxtc.so")
 
 XTC_OK, XTC_E_ARG, XTC_E_WORKSPACE, XTC_E_HIP, XTC_E_UNSUPPORTED = 0, -1, -2, -3, -4
 XTC_FP64, XTC_FP32, XTC_BF16X3, XTC_BF16X6 = 0, 1, 2, 3
-XTC_RESET, XTC_FINALIZE = 1, 2
+XTC_RESET, XTC_FINALIZE, XTC_REUSE_INTERMEDIATES = 1, 2, 4
 XTC_WITH_BACKWARD = 0x10
 XTC_WITH_TC2 = 0x20
 XTC_K_REDUCED_OCC = 0x40
@@ -338,7 +338,9 @@ class Pass:
             if two_body:
                 xtc_contract_2body(self.dp, K, g0, g1, self.prec, flags, self.V2, self.ws, stream)
             if one_body:
-                xtc_contract_1body_0body(self.dp, K, g0, g1, self.prec, flags, self.h1, self.E0, self.ws, stream)
+                reuse = XTC_REUSE_INTERMEDIATES if two_body else 0   # A, B of this chunk are in ws
+                xtc_contract_1body_0body(self.dp, K, g0, g1, self.prec, flags | reuse, self.h1, self.E0, self.ws,
+                                         stream)
         return self.V2, self.h1, self.E0
 
 

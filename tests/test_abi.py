@@ -147,6 +147,17 @@ def test_contract_flags(lib):
     st = lib.xtc_contract_1body_0body(ctypes.byref(c), ctypes.c_void_p(0x2000), 0, 10, 0, xtc.XTC_FINALIZE,
                                       None, None, ctypes.c_void_p(0x100000), n, None)
     assert st == xtc.XTC_E_ARG
+    # the reuse assertion is a one-body flag only
+    st = lib.xtc_contract_2body(ctypes.byref(c), ctypes.c_void_p(0x2000), 0, 10, 0, xtc.XTC_REUSE_INTERMEDIATES,
+                                None, ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG and "unknown bits" in xtc.last_error()
+    st = lib.xtc_contract_1body_0body(ctypes.byref(c), ctypes.c_void_p(0x2000), 0, 10, 0,
+                                      xtc.XTC_FINALIZE | xtc.XTC_REUSE_INTERMEDIATES,
+                                      None, None, ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG and "NULL" in xtc.last_error()        # past the flag check
+    st = lib.xtc_contract_1body_0body(ctypes.byref(c), ctypes.c_void_p(0x2000), 0, 10, 0, 8,
+                                      None, None, ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG and "unknown bits" in xtc.last_error()
 
 
 def test_backward_validation(lib):

@@ -215,3 +215,41 @@ def test_lowdin_against_oracle(torch_cuda, name, Ng):
     S = (phi_g * p.w) @ phi_g.T
     assert np.abs(S - np.eye(p.N)).max() < 50 * np.finfo(float).eps * cond
     assert np.allclose(np.sort(lam_g.cpu().numpy()), np.sort(lam_o), rtol=1e-9, atol=1e-14 * lam_o.max())
+
+
+# ------------------------------------------------- intermediates reuse flag --
+@pytest.mark.parametrize("case", ["closed-fp64", "closed-bf16x3", "open-bf16x3"])
+def test_reuse_intermediates_is_bitwise_recompute(torch_cuda, case):
+    """xtc_contract_1body_0body with XTC_REUSE_INTERMEDIATES right after
+    xtc_contract_2body (what the forward pass does) gives bitwise the h1 and
+    E0 of the same call recomputing the intermediates from K, over several
+    ragged chunks; open shell: both spin channels' intermediates are kept."""
+    import torch
+    from paper_2304_07006_amd import xtc
+    shell, prec = case.split("-")
+    if shell == "open":
+        k, na, nb = inputs.open_shell_occupations(3, 2)
+        p = inputs.make_problem(24, 5, 1900, 6, "chain", "pade", seed=71, occ=k)
+        p.occ_n, p.occ_n_beta = na, nb
+    else:
+        p = inputs.make_problem(24, 4, 1900, 6, "chain", "pade", seed=71)
+    _note(f"case: N24 Ng1900 {case} reuse vs recompute, chunks of 700")
+    dp = xtc.device_problem(p.xyz, p.w, p.phi, p.occ, occ_n=getattr(p, "occ_n", None),
+                            occ_n_beta=getattr(p, "occ_n_beta", None))
+    jas = xtc.make_jastrow(p.jastrow)
+    out = {}
+    for reuse in (0, xtc.XTC_REUSE_INTERMEDIATES):
+        ps = xtc.Pass(dp, xtc.PRECISIONS[prec], 700)
+        xtc.xtc_prepare(dp, ps.prec, ps.chunk, ps.ws)
+        ch = ps.chunks()
+        for i, (g0, g1) in enumerate(ch):
+            flags = (xtc.XTC_RESET if i == 0 else 0) | (xtc.XTC_FINALIZE if i == len(ch) - 1 else 0)
+            K = ps.K_view(g0, g1)
+            xtc.xtc_build_K(dp, jas, g0, g1, ps.prec, K, ps.ws)
+            xtc.xtc_contract_2body(dp, K, g0, g1, ps.prec, flags, ps.V2, ps.ws)
+            xtc.xtc_contract_1body_0body(dp, K, g0, g1, ps.prec, flags | reuse, ps.h1, ps.E0, ps.ws)
+        torch.cuda.synchronize()
+        out[reuse] = (ps.V2.cpu().numpy(), ps.h1.cpu().numpy(), ps.E0.cpu().numpy())
+    (Va, ha, Ea), (Vb, hb, Eb) = out[0], out[xtc.XTC_REUSE_INTERMEDIATES]
+    assert np.array_equal(Va, Vb) and np.array_equal(ha, hb) and np.array_equal(Ea, Eb)
+    assert np.abs(ha).max() > 0
