@@ -15,7 +15,7 @@
 //   D      [4][cap][ldP] doubles      A, Bx, By, Bz of the current chunk
 //   Kpart  [nsegK][3][cap][ldL] f32   K-build segment partials     (prec != FP64)
 //   CDlp   [8][NS][cap/8][ldL][8]     C and D of the chunk, k8-packed (prec != FP64)
-//   Mpart  [ceil(cap/kSegM)][4][ldL][ldL] f32  two-body partials   (prec != FP64)
+//   Mpart  [ceil(cap/segM)][4][ldL][ldL] f32   two-body partials   (prec != FP64)
 // and with XTC_WITH_BACKWARD in prec (the adjoint reuses M for Gbar):
 //   Kc [3][cap][ldP], Y [7][cap][ldP], T [cap][3][N][nocc], Wbar [cap][3],
 //   gpart [ceil(cap/32) * ngp/128][16], gacc [16], occw [N] f64, kidx [N],
@@ -81,21 +81,27 @@ int pair_ld(int N) {
     return (int)((npair + kPairTile - 1) / kPairTile * kPairTile);
 }
 
-constexpr int kSegK = 8192;     // g' per FP32 segment of the reduced-precision K build
-constexpr int kSegM = 2048;     // grid rows per FP32 segment of the reduced-precision two-body GEMM
+// FP32 accumulation segments of the reduced-precision forms (the partials are
+// summed in FP64): g' per segment of the K build, grid rows per segment of the
+// two-body GEMM.  The split-BF16 forms' error is their dropped products, so
+// long segments cost nothing there; the FP32 form's error grows with the
+// segment (one rounding per 4 products in v_mfma_f32_16x16x4_f32) and at
+// N=128, Ng=150 000 needs 8x and 4x shorter ones to meet the 1e-6 Eh bars.
+constexpr int kSegK = 8192, kSegKF32 = 1024;
+constexpr int kSegM = 2048, kSegMF32 = 512;
 constexpr int kRowQuant = 32;
 constexpr int kOccSegMax = 32;  // most segments of the FP64 occupied-block sum over g'
 
 struct Layout {
     int N, Ng, nocc, ldP, ngp, Npair, prec;
-    int form, ns, es, ldL, ldO, nOP, occNB, nsegK, nspin, ldN;
+    int form, ns, es, ldL, ldO, nOP, occNB, nsegK, nspin, ldN, segK, segM;
     bool tc2;
     bool bwd;
     size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, occw, kidx, rhoR, GsL, Atc, Btc;
     size_t fixed;        // bytes before S (plus the Mpart remainder reserve)
     size_t per_row;      // bytes per chunk row
     int cap;             // chunk rows that fit (multiple of kRowQuant)
-    size_t mslab;        // bytes of the two-body partials of one kSegM-row segment
+    size_t mslab;        // bytes of the two-body partials of one segM-row segment
     size_t cdw;          // packed operand elements per row and split (CDlp)
     size_t S, D, Kpart, CDlp, Mpart, Kocc, Kc, Y, T, Wbar, gpart, KbL, Ftc, Rg, end;
 };
@@ -141,7 +147,9 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.nOP = pb->nocc * (pb->nocc + 1) / 2;
     L.occNB = occ_blocks(L.nOP);
     L.ldO = (int)align_up((size_t)L.nOP, (size_t)16 * L.occNB);
-    L.nsegK = (L.ngp + kSegK - 1) / kSegK;
+    L.segK = L.form == 1 ? kSegKF32 : kSegK;
+    L.segM = L.form == 1 ? kSegMF32 : kSegM;
+    L.nsegK = (L.ngp + L.segK - 1) / L.segK;
     L.bwd = (prec & XTC_WITH_BACKWARD) != 0;
     L.tc2 = (prec & XTC_WITH_TC2) != 0;
     L.ldN = (int)align_up((size_t)pb->N * pb->N, 128);
@@ -176,7 +184,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.per_row = (size_t)L.nspin * (8 * sizeof(double) + (size_t)4 * L.ldP * sizeof(double));
     if (lp) L.per_row += (size_t)kOccSegMax * 3 * L.ldO * sizeof(double);
     if (lp)
-        L.per_row += (size_t)L.nsegK * 3 * L.ldL * sizeof(float) + L.cdw * L.ns * L.es + (mslab + kSegM - 1) / kSegM;
+        L.per_row += (size_t)L.nsegK * 3 * L.ldL * sizeof(float) + L.cdw * L.ns * L.es + (mslab + L.segM - 1) / L.segM;
     if (L.tc2) L.per_row += (size_t)L.ldP * sizeof(double) + (size_t)3 * L.ldN * sizeof(double);
     if (L.bwd)
         L.per_row += (size_t)10 * L.ldP * sizeof(double) + (size_t)3 * L.N * L.nocc * sizeof(double) +
@@ -199,7 +207,7 @@ void place_chunk(Layout& L, size_t bytes) {
     L.D = off;       off = align_up(off + (size_t)L.nspin * 4 * cap * L.ldP * sizeof(double), kAlign);
     L.Kpart = off;   off = align_up(off + (lp ? (size_t)L.nsegK * 3 * cap * L.ldL * sizeof(float) : 0), kAlign);
     L.CDlp = off;    off = align_up(off + (lp ? L.cdw * L.ns * cap * L.es : 0), kAlign);
-    L.Mpart = off;   off = align_up(off + (size_t)((cap + kSegM - 1) / kSegM) * L.mslab, kAlign);
+    L.Mpart = off;   off = align_up(off + (size_t)((cap + L.segM - 1) / L.segM) * L.mslab, kAlign);
     L.Kocc = off;    off = align_up(off + (lp ? (size_t)kOccSegMax * 3 * cap * L.ldO * sizeof(double) : 0), kAlign);
     const bool b = L.bwd;
     L.Kc = off;      off = align_up(off + (b ? (size_t)3 * cap * L.ldP * sizeof(double) : 0), kAlign);
@@ -385,7 +393,7 @@ void launch_build_lp(const Layout& L, int g0, int rows, const JasDev& J, void* w
     const int n_ct = (L.ldL + cols - 1) / cols;
     hipLaunchKernelGGL((k_build_K_lp<KIND, FORM, NC>), dim3(n_rt * n_ct * L.nsegK), dim3(kLpThreads), 0, st,
                        at<d4>(ws, L.pos), at<void>(ws, L.rho_lp), (size_t)L.ngp * L.ldL, L.ldL, L.ngp, g0, rows, n_rt,
-                       kSegK, J, at<float>(ws, L.Kpart), L.cap, L.ldP, n_ct, L.nsegK);
+                       L.segK, J, at<float>(ws, L.Kpart), L.cap, L.ldP, n_ct, L.nsegK);
 }
 
 // Segments of the g' sum for a grid of `tiles` workgroups per segment: the
@@ -474,18 +482,19 @@ xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double
     return launched("reduce_occ");
 }
 
-// part[y] = C^T D over one row segment of kSegM rows and a group of cpw of the
+// part[y] = C^T D over one row segment of seg_len rows and a group of cpw of the
 // ncomp components, y = group * nseg_r + segment (k_gemm_tn_lp); returns the
 // number of partials written through *nparts.
 xtc_status gemm_tn_lp(int form, const void* C, int ldC, size_t c_split, const void* D, int ldD, size_t d_split,
-                      int rows32, int pmax, int rmax, int ncomp, int cpw, float* part, int* nparts, hipStream_t st) {
-    const int nseg_r = (rows32 + kSegM - 1) / kSegM;
+                      int rows32, int pmax, int rmax, int ncomp, int cpw, int seg_len, float* part, int* nparts,
+                      hipStream_t st) {
+    const int nseg_r = (rows32 + seg_len - 1) / seg_len;
     if (form == 3 && ldC % 256 == 0 && ldD % 256 == 0) {
         // both operands staged in LDS (256 x 256 tiles)
         const int n_pt = ldC / 256, n_rt = ldD / 256;
         const dim3 grid(n_pt * n_rt, (ncomp / cpw) * nseg_r);
         hipLaunchKernelGGL((k_gemm_tn_lds<3>), grid, dim3(kTnThreads), 0, st, C, ldC, c_split, D, ldD, d_split, rows32,
-                           n_pt, pmax, rmax, cpw, kSegM, nseg_r, part);
+                           n_pt, pmax, rmax, cpw, seg_len, nseg_r, part);
         *nparts = (int)grid.y;
         return launched("gemm_tn_lds");
     }
@@ -493,13 +502,13 @@ xtc_status gemm_tn_lp(int form, const void* C, int ldC, size_t c_split, const vo
     const dim3 grid(n_pt * n_rt, (ncomp / cpw) * nseg_r);
     if (form == 1)
         hipLaunchKernelGGL((k_gemm_tn_lp<1>), grid, dim3(256), 0, st, C, ldC, c_split, D, ldD, d_split, rows32, n_pt,
-                           pmax, rmax, cpw, kSegM, nseg_r, part);
+                           pmax, rmax, cpw, seg_len, nseg_r, part);
     else if (form == 3)
         hipLaunchKernelGGL((k_gemm_tn_lp<3>), grid, dim3(256), 0, st, C, ldC, c_split, D, ldD, d_split, rows32, n_pt,
-                           pmax, rmax, cpw, kSegM, nseg_r, part);
+                           pmax, rmax, cpw, seg_len, nseg_r, part);
     else
         hipLaunchKernelGGL((k_gemm_tn_lp<6>), grid, dim3(256), 0, st, C, ldC, c_split, D, ldD, d_split, rows32, n_pt,
-                           pmax, rmax, cpw, kSegM, nseg_r, part);
+                           pmax, rmax, cpw, seg_len, nseg_r, part);
     *nparts = (int)grid.y;
     return launched("gemm_tn_lp");
 }
@@ -538,7 +547,7 @@ xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int acc
         }
         int np = 0;
         if ((s = gemm_tn_lp(L.form, cd, L.ldL, split_stride, cd + 4 * comp_bytes, L.ldL, split_stride, rows32, L.ldP,
-                            L.ldP, 4, 1, part, &np, st)) != XTC_OK)
+                            L.ldP, 4, 1, L.segM, part, &np, st)) != XTC_OK)
             return s;
         if ((s = reduce_parts(part, np, L.ldL, L.ldL, L.ldP, L.ldP, at<double>(ws, L.M) + (size_t)sp * L.ldP * L.ldP,
                               L.ldP, accumulate, st)) != XTC_OK)
@@ -994,7 +1003,7 @@ xtc_status xtc_tc_2body(const xtc_problem* pb, const xtc_jastrow* jas, const dou
         if ((s = launched("gemm_tc_B")) != XTC_OK) return s;
     } else {
         // reduced forms: both contractions as split products over the chunk rows,
-        // FP32 partials per kSegM rows, FP64 reduction into the accumulators
+        // FP32 partials per segM rows, FP64 reduction into the accumulators
         const int rows32 = (int)align_up((size_t)rows, kRowQuant);
         const int n8 = rows32 / 8;
         char* cd = at<char>(ws, L.CDlp);
@@ -1004,8 +1013,8 @@ xtc_status xtc_tc_2body(const xtc_problem* pb, const xtc_jastrow* jas, const dou
         int np = 0;
         if ((s = pack_any(L.form, rho_rows, rows, L.ldP, L.ldP, n8, L.ldL, cd, sL, st)) != XTC_OK) return s;
         if ((s = pack_any(L.form, F, rows, L.ldP, L.ldP, n8, L.ldL, cd + cL, sL, st)) != XTC_OK) return s;
-        if ((s = gemm_tn_lp(L.form, cd, L.ldL, sL, cd + cL, L.ldL, sL, rows32, L.ldP, L.ldP, 1, 1, part, &np, st)) !=
-            XTC_OK)
+        if ((s = gemm_tn_lp(L.form, cd, L.ldL, sL, cd + cL, L.ldL, sL, rows32, L.ldP, L.ldP, 1, 1, L.segM,
+                            part, &np, st)) != XTC_OK)
             return s;
         if ((s = reduce_parts(part, np, L.ldL, L.ldL, L.ldP, L.ldP, Atc, L.ldP, acc, st)) != XTC_OK) return s;
         char* kd = cd + 3 * cN;
@@ -1017,8 +1026,8 @@ xtc_status xtc_tc_2body(const xtc_problem* pb, const xtc_jastrow* jas, const dou
                 return s;
         }
         // the three components of rhog_pq . K_R summed inside each workgroup
-        if ((s = gemm_tn_lp(L.form, cd, L.ldN, sN, kd, L.ldL, sL, rows32, L.N * L.N, L.ldP, 3, 3, part, &np, st)) !=
-            XTC_OK)
+        if ((s = gemm_tn_lp(L.form, cd, L.ldN, sN, kd, L.ldL, sL, rows32, L.N * L.N, L.ldP, 3, 3, L.segM,
+                            part, &np, st)) != XTC_OK)
             return s;
         if ((s = reduce_parts(part, np, L.ldN, L.ldL, L.N * L.N, L.ldP, Btc, L.ldP, acc, st)) != XTC_OK) return s;
     }

@@ -2,7 +2,7 @@
 configuration bench.py times (N=128, 16 occupied, Ng=150 000, 20 chunks of
 7500 rows in split BF16 x3, 10 in FP64): sampled K entries against their exact
 grid sums, the antisymmetry of the pair contraction of K, the split-BF16
-outputs against the FP64 path to the bars, bitwise symmetry and determinism;
+and FP32 outputs against the FP64 path to the bars, bitwise symmetry and determinism;
 and the adjoint at N=96, Ng=100 000 through the Euler identity of the
 quadratic loss."""
 import numpy as np
@@ -123,22 +123,25 @@ def test_full_size_pair_antisymmetry(torch_cuda, problem):
 
 
 def test_full_size_forward_against_fp64(torch_cuda, problem):
-    """Split BF16 x3 at the bench configuration against the FP64 path: the
-    1e-6 Eh two-body bar (one-body 1e-6, zero-body 1e-8); bitwise symmetry of
-    V2 and h1, bitwise determinism of two split-BF16 runs."""
+    """Split BF16 x3 at the bench configuration, and the FP32 form in the same
+    chunks, against the FP64 path: the 1e-6 Eh two-body bar (one-body 1e-6,
+    zero-body 1e-8); bitwise symmetry of V2 and h1, bitwise determinism of two
+    split-BF16 runs."""
     from paper_2304_07006_amd import xtc
     p = problem
-    _note(f"case: {WORKLOAD} forward bf16x3 (x2) vs fp64")
+    _note(f"case: {WORKLOAD} forward bf16x3 (x2) and fp32 vs fp64")
     out = {}
-    for prec, tag in (("bf16x3", "a"), ("bf16x3", "b"), ("fp64", "r")):
+    for prec, tag in (("bf16x3", "a"), ("bf16x3", "b"), ("fp32", "f"), ("fp64", "r")):
         V2, h1, E0 = xtc.forward(p, prec=prec, chunk_rows=_chunk(prec, p.Ng))
         out[tag] = (V2.cpu().numpy(), h1.cpu().numpy(), float(E0.cpu()[0]))
         del V2, h1, E0
         torch_cuda.cuda.empty_cache()
     (Va, ha, Ea), (Vb, hb, Eb), (Vr, hr, Er) = out["a"], out["b"], out["r"]
-    eV, eh, eE = np.abs(Va - Vr).max(), np.abs(ha - hr).max(), abs(Ea - Er)
-    _note(f"  |dV2| {eV:.2e} |dh1| {eh:.2e} |dE0| {eE:.2e} (E0 = {Er:.10f})")
-    assert eV < 1e-6 and eh < 1e-6 and eE < 1e-8
+    for tag in ("a", "f"):
+        V, h, E = out[tag]
+        eV, eh, eE = np.abs(V - Vr).max(), np.abs(h - hr).max(), abs(E - Er)
+        _note(f"  {'bf16x3' if tag == 'a' else 'fp32'}: |dV2| {eV:.2e} |dh1| {eh:.2e} |dE0| {eE:.2e} (E0 = {Er:.10f})")
+        assert eV < 1e-6 and eh < 1e-6 and eE < 1e-8, tag
     assert np.array_equal(Va, Vb) and np.array_equal(ha, hb) and Ea == Eb
     for V in (Va, Vr):
         for perm in [(1, 0, 2, 3), (0, 1, 3, 2), (2, 3, 0, 1)]:
