@@ -771,6 +771,34 @@ __global__ void k_split_rows(const double* __restrict__ src, size_t n, void* __r
     }
 }
 
+// Split an FP64 row-major array src[nrows][ld] (ld a multiple of 8) into the
+// k-packed operand format of k_nt_bf16, dst[s][ld/8][nrows][8]: element
+// (j, k) goes to dst[s][k/8][j][k%8], so that the 8 consecutive k a lane
+// multiplies are one 16-byte vector and 16 consecutive rows of one 8-k group
+// are 256 contiguous bytes (row-major splits put them 2 ld bytes apart).
+template <int FORM>
+__global__ __launch_bounds__(256) void k_pack_kmajor(const double* __restrict__ src, int nrows, int ld,
+                                                     __bf16* __restrict__ dst, size_t split_stride) {
+    static_assert(FORM == 3 || FORM == 6, "split-BF16 forms only");
+    constexpr int NS = Lp<FORM>::NS;
+    const size_t n = (size_t)nrows * (ld / 8);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t j = i % nrows, k8 = i / nrows;      // consecutive threads: consecutive rows (16-byte stores)
+        const d4* p = (const d4*)(src + j * ld + 8 * k8);
+        const d4 x0 = p[0], x1 = p[1];
+        bf8 out[NS];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            __bf16 t[NS];
+            split_bf16<NS>((float)(e < 4 ? x0[e] : x1[e - 4]), t);
+#pragma unroll
+            for (int q = 0; q < NS; ++q) out[q][e] = t[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) *(bf8*)(dst + q * split_stride + (k8 * nrows + j) * 8) = out[q];
+    }
+}
+
 // Gradient epilogue of one Pi value: dL/dc_j gains j t^(j-1) q^2 / r times
 // (r_g - r_g') . Pi(g,g') (power Jastrow, u' = sum_j j c_j t^(j-1) q^2 with
 // t = r q, q = 1/(1+r)); FP64, coincident points skipped.
@@ -877,10 +905,12 @@ __global__ __launch_bounds__(256) void k_pi_grad_lp(const void* __restrict__ Kb,
 // columns (16 bytes per lane) one k-step ahead and owns 32 x 64 x NC FP32
 // accumulators, so every operand value is fetched once per workgroup.  FP32
 // accumulation over the whole k range.
-// A: [NC][NS][rows][ldk] (component stride a_comp, split stride a_split),
-// B: [NS][nB][ldk] (split stride b_split), both row-major with k contiguous;
-// ldk is a multiple of 64.  Grid: n_rt x ceil(nB / 512), row tile fastest, so
-// the workgroups resident on an XCD share one B strip through its L2.
+// A: [NC][NS][ldk/8][rows][8] (component stride a_comp, split stride a_split),
+// B: [NS][ldk/8][nB][8] (split stride b_split), both k-packed (k_pack_kmajor):
+// each 16-byte operand vector and each 16-row block of one 8-k group is
+// contiguous.  ldk is a multiple of 64.  Grid: n_rt x ceil(nB / 512), row
+// tile fastest, so the workgroups resident on an XCD share one B strip
+// through its L2.
 // Epilogues:
 //  GRAD (NC = 3, the Pi contraction Pi^x(g,g') = sum_P Kbar^x[g][P] rho[g'][P]
 //   with i = g - g0, j = g'): the gradient terms of every (g, g'), summed per
@@ -908,7 +938,8 @@ __global__ __launch_bounds__(kPiThreads) void k_nt_bf16(const __bf16* __restrict
     const int rt = blockIdx.x % n_rt, jt = blockIdx.x / n_rt;
     const int l16 = lane & 15, lk = lane >> 4;
 
-    // loader role: vector v = tid + 512 i is (component-split cs, row, 8-k chunk q)
+    // loader role: vector v = tid + 512 i is (component-split cs, 8-k chunk q,
+    // row), rows fastest: the 32 rows of one chunk are 512 contiguous bytes
     const __bf16* asrc[kAPer];
     int adst[kAPer];
     bool aon[kAPer];
@@ -916,16 +947,17 @@ __global__ __launch_bounds__(kPiThreads) void k_nt_bf16(const __bf16* __restrict
     for (int i = 0; i < kAPer; ++i) {
         const int v = threadIdx.x + kPiThreads * i;
         aon[i] = v < kAVec;
-        const int q = v & 3, row = (v >> 2) & (kLpRows - 1), cs = aon[i] ? v >> 7 : 0;
-        asrc[i] = A + (cs / NS) * a_comp + (cs % NS) * a_split + (size_t)min(rt * kLpRows + row, rows - 1) * ldk +
-                  8 * q;
+        const int row = v & (kLpRows - 1), q = (v >> 5) & 3, cs = aon[i] ? v >> 7 : 0;
+        asrc[i] = A + (cs / NS) * a_comp + (cs % NS) * a_split +
+                  ((size_t)q * rows + min(rt * kLpRows + row, rows - 1)) * 8;
         adst[i] = (cs * kLpRows + row) * kARow + 8 * q;
     }
     bf8 apre[kAPer];
+    // the 8-k group k/8 starts k * rows elements in (k a multiple of 32)
     auto loadA = [&](int k) {
 #pragma unroll
         for (int i = 0; i < kAPer; ++i)
-            if (aon[i]) apre[i] = *(const bf8*)(asrc[i] + k);
+            if (aon[i]) apre[i] = *(const bf8*)(asrc[i] + (size_t)k * rows);
     };
     auto storeA = [&](ATile& W) {
 #pragma unroll
@@ -936,13 +968,13 @@ __global__ __launch_bounds__(kPiThreads) void k_nt_bf16(const __bf16* __restrict
     const int jbase = jt * (kPiThreads / 64) * 64 + wave * 64;
     const __bf16* bsrc[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) bsrc[b] = B + (size_t)min(jbase + 16 * b + l16, nB - 1) * ldk + 8 * lk;
+    for (int b = 0; b < NB; ++b) bsrc[b] = B + ((size_t)lk * nB + min(jbase + 16 * b + l16, nB - 1)) * 8;
     bf8 bnext[NB][NS];
     auto loadB = [&](int k) {
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int s = 0; s < NS; ++s) bnext[b][s] = *(const bf8*)(bsrc[b] + s * b_split + k);
+            for (int s = 0; s < NS; ++s) bnext[b][s] = *(const bf8*)(bsrc[b] + s * b_split + (size_t)k * nB);
     };
 
     f4 acc[NC][2][NB];

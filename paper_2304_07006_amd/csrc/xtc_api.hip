@@ -19,9 +19,10 @@
 // and with XTC_WITH_BACKWARD in prec (the adjoint reuses M for Gbar):
 //   Kc [3][cap][ldP], Y [7][cap][ldP], T [cap][3][N][nocc], Wbar [cap][3],
 //   gpart [ceil(cap/32) * ngp/128][16], gacc [16], occw [N] f64, kidx [N],
-//   reduced forms: rhoR [NS][ngp][ldP] (row-major split rho), KbL
-//   [7][NS][cap][ldP] (row-major split operands of the chunk), split-BF16
-//   3-product form: GsL [2][ldP][ldP] (row-major split Gbar)
+//   reduced forms: rhoR (split rho: FP32 row-major [1][ngp][ldP], split BF16
+//   k-packed [NS][ldP/8][ngp][8]), KbL [7][NS][cap * ldP] (split operands of
+//   the chunk, same two layouts), split-BF16 3-product form: GsL (k-packed
+//   split Gbar, [2][ldP/8][ldP][8])
 // and with XTC_WITH_TC2 (two-body TC integrals; ldN = N^2 rounded up to 128):
 //   Atc [ldP][ldP], Btc [ldN][ldP] FP64 accumulators, Ftc [cap][ldP],
 //   Rg [3][cap][ldN] (w phi grad phi of the chunk)
@@ -564,9 +565,24 @@ xtc_status split_rows_any(int form, const double* src, size_t n, void* dst, size
     return launched("split_rows");
 }
 
+// Split an FP64 row-major [nrows][ld] array into the k-packed operand format
+// of k_nt_bf16 (split-BF16 forms).
+xtc_status pack_kmajor_any(int form, const double* src, int nrows, int ld, void* dst, size_t split_stride,
+                           hipStream_t st) {
+    const size_t n = (size_t)nrows * (ld / 8);
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
+    if (form == 3)
+        hipLaunchKernelGGL(k_pack_kmajor<3>, dim3(blocks), dim3(256), 0, st, src, nrows, ld, (__bf16*)dst,
+                           split_stride);
+    else
+        hipLaunchKernelGGL(k_pack_kmajor<6>, dim3(blocks), dim3(256), 0, st, src, nrows, ld, (__bf16*)dst,
+                           split_stride);
+    return launched("pack_kmajor");
+}
+
 // Y_c = X_c Gbar for the seven adjoint operands in the split-BF16 3-product
-// form (k_nt_bf16, FP32 accumulation over all pairs): X split
-// [7][2][rows][ldP], Gbar split [2][ldP][ldP], Y [7][cap][ldP] FP64.
+// form (k_nt_bf16, FP32 accumulation over all pairs): X k-packed splits
+// [7][2][ldP/8][rows][8], Gbar k-packed splits [2][ldP/8][ldP][8], Y [7][cap][ldP] FP64.
 // Components share the Gbar operand in groups of 3 + 4.
 template <int FORM, int NC>
 xtc_status xg_group(const __bf16* X, size_t a_comp, size_t a_split, int rows, const __bf16* Gs, int ldP, int c0,
@@ -648,9 +664,14 @@ xtc_status xtc_prepare(const xtc_problem* pb, int32_t prec, int32_t chunk_rows, 
         hipLaunchKernelGGL(k_gather_occ, dim3(4096), dim3(256), 0, st, at<double>(ws, L.rho), L.ldP, L.ngp,
                            at<int>(ws, L.colmap), L.ldO, at<double>(ws, L.rho_occ));
         if ((s = launched("gather_occ")) != XTC_OK) return s;
-        if (L.bwd &&
+        // the adjoint's Pi operand: k-packed splits of rho (FP32: row-major)
+        if (L.bwd && L.form == 1 &&
             (s = split_rows_any(L.form, at<double>(ws, L.rho), (size_t)L.ngp * L.ldP, at<void>(ws, L.rhoR),
                                 (size_t)L.ngp * L.ldP, st)) != XTC_OK)
+            return s;
+        if (L.bwd && L.form != 1 &&
+            (s = pack_kmajor_any(L.form, at<double>(ws, L.rho), L.ngp, L.ldP, at<void>(ws, L.rhoR),
+                                 (size_t)L.ngp * L.ldP, st)) != XTC_OK)
             return s;
     }
     // zero the accumulators and the chunk buffers (padding columns of D stay 0)
@@ -811,7 +832,7 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
     // hide it) carries coherently into the gradient; it keeps them in FP64
     const bool bsplit = L.form == 3;
     if (bsplit &&
-        (s = split_rows_any(L.form, G, (size_t)L.ldP * L.ldP, at<void>(ws, L.GsL), (size_t)L.ldP * L.ldP, st)) != XTC_OK)
+        (s = pack_kmajor_any(L.form, G, L.ldP, L.ldP, at<void>(ws, L.GsL), (size_t)L.ldP * L.ldP, st)) != XTC_OK)
         return s;
     const size_t ystride = (size_t)L.cap * L.ldP;
     double* Kc = at<double>(ws, L.Kc);
@@ -830,12 +851,13 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
         const double* src[7] = {D + ystride, D + 2 * ystride, D + 3 * ystride, rho_rows, Kc, Kc + kstride,
                                 Kc + 2 * kstride};
         if (bsplit) {
-            // split-BF16: the seven operands to row-major splits, then the NT
+            // split-BF16: the seven operands to k-packed splits, then the NT
             // products in groups of components sharing Gbar
             const size_t a_split = (size_t)rows * L.ldP, a_comp = (size_t)L.ns * a_split;
             char* xs = at<char>(ws, L.KbL);
             for (int y = 0; y < 7; ++y)
-                if ((s = split_rows_any(L.form, src[y], a_split, xs + y * a_comp * L.es, a_split, st)) != XTC_OK)
+                if ((s = pack_kmajor_any(L.form, src[y], rows, L.ldP, xs + y * a_comp * L.es, a_split, st)) !=
+                    XTC_OK)
                     return s;
             if ((s = xg_bf16x3((const __bf16*)xs, a_comp, a_split, rows, at<__bf16>(ws, L.GsL), L.ldP, Y, ystride,
                                st)) != XTC_OK)
@@ -873,13 +895,17 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
                                L.ldP, L.ldP, at<d4>(ws, L.pos), g0, L.ngp, n_jt_pi, J.ncoef, at<double>(ws, L.gpart));
             if ((s = launched("pi_grad")) != XTC_OK) return s;
         } else {
-            // Kbar of the chunk to the row-major split format, then the reduced Pi tiles
+            // Kbar of the chunk to split operands (FP32: row-major; split BF16:
+            // k-packed), then the reduced Pi tiles
             const size_t kb_split = (size_t)rows * L.ldP, kb_comp = (size_t)L.ns * kb_split;
             char* kb = at<char>(ws, L.KbL);
-            for (int x = 0; x < 3; ++x)
-                if ((s = split_rows_any(L.form, Y + x * ystride, (size_t)rows * L.ldP, kb + x * kb_comp * L.es,
-                                        kb_split, st)) != XTC_OK)
-                    return s;
+            for (int x = 0; x < 3; ++x) {
+                s = L.form == 1 ? split_rows_any(L.form, Y + x * ystride, (size_t)rows * L.ldP,
+                                                 kb + x * kb_comp * L.es, kb_split, st)
+                                : pack_kmajor_any(L.form, Y + x * ystride, rows, L.ldP, kb + x * kb_comp * L.es,
+                                                  kb_split, st);
+                if (s != XTC_OK) return s;
+            }
             const size_t rr_split = (size_t)L.ngp * L.ldP;
             if (L.form == 1) {
                 const int n_jt_lp = (L.ngp + 255) / 256;
