@@ -124,8 +124,8 @@ typedef struct {
  *   occ_n [nocc] HOST double, finite, or NULL.
  * Limits: 1 <= N <= 256, 1 <= nocc <= min(N, 128), Ng >= 1 (XTC_E_ARG
  * otherwise); nocc * N * 32 bytes (the occupied columns of rho and K staged
- * on chip per grid point) at most 159 KB, i.e. nocc * N <= 5088
- * (XTC_E_UNSUPPORTED otherwise).
+ * on chip per grid point) at most 159 KB, i.e. nocc * N <= 5088, and
+ * Ng <= 2^28 (XTC_E_UNSUPPORTED otherwise).
  *
  * Open shell (restricted open-shell working equations, Appendix A): with
  * occ_n_beta != NULL the alpha and beta densities differ,
@@ -240,7 +240,8 @@ xtc_status xtc_backward(const xtc_problem *pb, const xtc_jastrow *jas, int32_t p
  * small eigenvalues to high relative accuracy; S must be positive definite).
  * chi, phi: device [N][Ng]; w: device [Ng]; lambda: device [N] (eigenvalues
  * of S, unordered) or NULL.  Workspace of xtc_lowdin_workspace_size(N, Ng)
- * bytes, 256-byte aligned; no state is kept in it after the call. */
+ * bytes, 256-byte aligned; no state is kept in it after the call.
+ * 1 <= N <= 256 and Ng >= 1 (XTC_E_ARG), Ng <= 2^28 (XTC_E_UNSUPPORTED). */
 size_t xtc_lowdin_workspace_size(int32_t N, int32_t Ng);
 xtc_status xtc_lowdin(int32_t N, int32_t Ng, const double *chi, const double *w, double *phi,
                       double *lambda, void *ws, size_t ws_bytes, void *stream);

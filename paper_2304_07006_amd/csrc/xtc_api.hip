@@ -69,6 +69,9 @@ constexpr int kT1Split = 64;
 constexpr int kESplitMax = 256;
 constexpr size_t kAlign = 256;
 constexpr int kMaxN = 256;
+// Grid points: kernels index the padded grid with 32-bit integers; 2^28 points
+// of even one orbital pair already take 275 GB for rho alone.
+constexpr int kMaxNg = 1 << 28;
 constexpr size_t kLdsMax = 160 * 1024;
 // The kernels that stage the occupied columns in dynamic LDS (nocc N of
 // (rho, Kx, Ky, Kz)) also keep a few static reduction slots (at most 96 B);
@@ -230,6 +233,7 @@ xtc_status check_problem(const xtc_problem* pb) {
     if (pb->reserved != 0) return fail(XTC_E_ARG, "problem.reserved must be 0");
     if (pb->N < 1 || pb->N > kMaxN) return fail(XTC_E_ARG, "N=%d outside [1,%d]", pb->N, kMaxN);
     if (pb->Ng < 1) return fail(XTC_E_ARG, "Ng=%d < 1", pb->Ng);
+    if (pb->Ng > kMaxNg) return fail(XTC_E_UNSUPPORTED, "Ng=%d above %d", pb->Ng, kMaxNg);
     if (pb->nocc < 1 || pb->nocc > pb->N || pb->nocc > kMaxOcc)
         return fail(XTC_E_ARG, "nocc=%d outside [1,min(N,%d)]", pb->nocc, kMaxOcc);
     if (!pb->xyz || !pb->w || !pb->phi || !pb->occ) return fail(XTC_E_ARG, "NULL array in problem");
@@ -1099,8 +1103,8 @@ xtc_status xtc_frozen_core(int32_t N, const double* V2, const double* h1, const 
 }
 
 size_t xtc_lowdin_workspace_size(int32_t N, int32_t Ng) {
-    if (N < 1 || N > kMaxN || Ng < 1) {
-        fail(XTC_E_ARG, "N=%d or Ng=%d out of range", N, Ng);
+    if (N < 1 || N > kMaxN || Ng < 1 || Ng > kMaxNg) {
+        fail(Ng > kMaxNg ? XTC_E_UNSUPPORTED : XTC_E_ARG, "N=%d or Ng=%d out of range", N, Ng);
         return 0;
     }
     return lowdin_layout(N, Ng).total;
@@ -1109,6 +1113,7 @@ size_t xtc_lowdin_workspace_size(int32_t N, int32_t Ng) {
 xtc_status xtc_lowdin(int32_t N, int32_t Ng, const double* chi, const double* w, double* phi, double* lambda,
                       void* ws, size_t ws_bytes, void* stream) {
     if (N < 1 || N > kMaxN || Ng < 1) return fail(XTC_E_ARG, "N=%d or Ng=%d out of range", N, Ng);
+    if (Ng > kMaxNg) return fail(XTC_E_UNSUPPORTED, "Ng=%d above %d", Ng, kMaxNg);
     if (!chi || !w || !phi) return fail(XTC_E_ARG, "NULL array");
     if (!ws) return fail(XTC_E_WORKSPACE, "workspace is NULL");
     if ((uintptr_t)ws % kAlign) return fail(XTC_E_WORKSPACE, "workspace not 256-byte aligned");

@@ -64,6 +64,7 @@ def _call_build(lib, c, j, g0=0, g1=10, prec=0, K=0x2000, ws=None, nbytes=None):
     (dict(N=0), xtc.XTC_E_ARG),
     (dict(N=257, occ=(0,)), xtc.XTC_E_ARG),                 # above the largest supported N (256)
     (dict(Ng=0), xtc.XTC_E_ARG),                             # empty grid
+    (dict(Ng=(1 << 28) + 1), xtc.XTC_E_UNSUPPORTED),          # above the 32-bit grid indexing limit
     (dict(occ=()), xtc.XTC_E_ARG),                           # no occupied orbital
     (dict(N=256, occ=tuple(range(20))), xtc.XTC_E_UNSUPPORTED),   # nocc N 32 B over the on-chip staging
     (dict(occ=(0, 0)), xtc.XTC_E_ARG),
@@ -78,6 +79,15 @@ def test_bad_problem(lib, mut, expect):
     st = _call_build(lib, c, _jas(), nbytes=1 << 30)
     assert st == expect
     assert xtc.last_error()
+
+
+def test_lowdin_limits(lib):
+    assert lib.xtc_lowdin_workspace_size(8, 0) == 0 and "out of range" in xtc.last_error()
+    assert lib.xtc_lowdin_workspace_size(8, (1 << 28) + 1) == 0
+    assert lib.xtc_lowdin_workspace_size(8, 1 << 28) > 0
+    st = lib.xtc_lowdin(8, (1 << 28) + 1, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000),
+                        None, ctypes.c_void_p(0x100000), 1 << 20, None)
+    assert st == xtc.XTC_E_UNSUPPORTED
 
 
 @pytest.mark.parametrize("bad", [float("nan"), float("inf")])
