@@ -73,6 +73,28 @@ __device__ __forceinline__ f4 mma_bf16(const bf8& a, const bf8& b, f4 acc) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
 }
 
+// Tile of workgroup `id` in a flat grid of nstrip column strips x n_rt row
+// tiles whose workgroups all read their strip's operand.  The dispatcher
+// deals workgroup i to XCD i % 8, and each XCD has its own L2: the first
+// 8 floor(nstrip/8) strips are therefore dealt whole, XCD x taking strips
+// x, x+8, ... with each strip's row tiles in order, so that a strip is
+// fetched into one L2 and shared there by the ~32 workgroups resident on
+// that XCD; the remaining strips follow in plain order (row tile fastest).
+// With plain order every XCD read every strip, and the strips that straddled
+// a dispatch round twice (2.3x the L2 misses of the K build at N=128).
+__device__ __forceinline__ void xcd_strip_tile(int id, int n_rt, int nstrip, int& rt, int& strip) {
+    const int q8 = nstrip / 8;
+    if (id < 8 * q8 * n_rt) {
+        const int li = id / 8;
+        rt = li % n_rt;
+        strip = id % 8 + 8 * (li / n_rt);
+    } else {
+        const int i2 = id - 8 * q8 * n_rt;
+        rt = i2 % n_rt;
+        strip = 8 * q8 + i2 / n_rt;
+    }
+}
+
 // --------------------------------------------------------------------------
 // Pack an FP64 row-major array src[nrows][ld_src] (columns < ncols valid) into
 // the k8-packed operand format dst[s][n8][ld_dst][8]; rows >= nrows and
@@ -210,8 +232,9 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
     __shared__ __attribute__((aligned(16))) PTile sP1[kLpThreads / 64];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // Flat grid, row tile fastest, so that the ~32 workgroups resident on an
-    // XCD share one column strip of the operand through its L2 while they
+    // Flat grid over strips (column tile, segment of g') x row tiles, in the
+    // XCD-aware order of xcd_strip_tile, so that the ~32 workgroups resident
+    // on an XCD share one strip of the operand through its L2 while they
     // advance through g' together.  Column tiles with idle waves finish early
     // and would stagger every later workgroup (and break that sharing), so
     // they are dispatched last, after all full tiles of all segments.
@@ -220,9 +243,10 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
     {
         const int id = blockIdx.x, nf = n_rt * n_full * nseg;
         if (id < nf) {
-            rt = id % n_rt;
-            ct = (id / n_rt) % n_full;
-            seg = id / (n_rt * n_full);
+            int strip;
+            xcd_strip_tile(id, n_rt, n_full * nseg, rt, strip);
+            ct = strip % n_full;
+            seg = strip / n_full;
         } else {
             rt = (id - nf) % n_rt;
             seg = (id - nf) / n_rt;
@@ -908,9 +932,9 @@ __global__ __launch_bounds__(256) void k_pi_grad_lp(const void* __restrict__ Kb,
 // A: [NC][NS][ldk/8][rows][8] (component stride a_comp, split stride a_split),
 // B: [NS][ldk/8][nB][8] (split stride b_split), both k-packed (k_pack_kmajor):
 // each 16-byte operand vector and each 16-row block of one 8-k group is
-// contiguous.  ldk is a multiple of 64.  Grid: n_rt x ceil(nB / 512), row
-// tile fastest, so the workgroups resident on an XCD share one B strip
-// through its L2.
+// contiguous.  ldk is a multiple of 64.  Grid: n_rt x ceil(nB / 512) in the
+// XCD-aware order of xcd_strip_tile, so the workgroups resident on an XCD
+// share one B strip through its L2.
 // Epilogues:
 //  GRAD (NC = 3, the Pi contraction Pi^x(g,g') = sum_P Kbar^x[g][P] rho[g'][P]
 //   with i = g - g0, j = g'): the gradient terms of every (g, g'), summed per
@@ -935,7 +959,8 @@ __global__ __launch_bounds__(kPiThreads) void k_nt_bf16(const __bf16* __restrict
     constexpr int kAVec = NC * NS * kLpRows * (kLpK / 8);         // 16-byte vectors of one tile
     constexpr int kAPer = (kAVec + kPiThreads - 1) / kPiThreads;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int rt = blockIdx.x % n_rt, jt = blockIdx.x / n_rt;
+    int rt, jt;
+    xcd_strip_tile(blockIdx.x, n_rt, gridDim.x / n_rt, rt, jt);   // strips: 512-column tiles of B
     const int l16 = lane & 15, lk = lane >> 4;
 
     // loader role: vector v = tid + 512 i is (component-split cs, 8-k chunk q,
