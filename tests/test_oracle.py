@@ -444,3 +444,35 @@ def test_loss_homogeneous_quadratic_and_gradient():
         fd = (og.loss(p.xyz, p.w, p.phi, p.occ, c + e, D, G)
               - og.loss(p.xyz, p.w, p.phi, p.occ, c - e, D, G)) / (2 * h)
         assert abs(fd - g[k]) < 1e-8 * max(1.0, abs(g[k]))
+
+
+def test_open_shell_loss_gradient_pins():
+    """The open-shell loss is a homogeneous quadratic in c (Euler identity,
+    L(2c) = 4 L(c)); with equal spin densities and seeds split evenly over
+    the spin blocks it is the closed-shell loss (so are the gradients); and
+    exchanging the spins, with D^a <-> D^b, G^aa <-> G^bb and the ab block's
+    pair indices exchanged, leaves it unchanged."""
+    p = inputs.make_problem(8, 3, 250, 2, "pair", "power16", seed=21, aux_seed=22)
+    c = np.array(p.jastrow.coef[:4])
+    k, na, nb = inputs.open_shell_occupations(2, 1)
+    ga = np.zeros((8, 8)); ga[k, k] = na
+    gb = np.zeros((8, 8)); gb[k, k] = nb
+    D, G = inputs.loss_weights(8, 23)
+    D2, G2 = inputs.loss_weights(8, 24)
+    D3, G3 = inputs.loss_weights(8, 25)
+    Do, Go = (D, D2), (G, G2, G3)
+    L1 = og.loss_open(p.xyz, p.w, p.phi, ga, gb, c, Do, Go)
+    assert abs(og.loss_open(p.xyz, p.w, p.phi, ga, gb, 2 * c, Do, Go) - 4 * L1) < 1e-12 * max(1, abs(L1))
+    g = og.exact_gradient_open(p.xyz, p.w, p.phi, ga, gb, c, Do, Go)
+    assert abs(np.dot(c, g) - 2 * L1) < 1e-12 * max(1, abs(L1))
+    # spin exchange
+    Ls = og.loss_open(p.xyz, p.w, p.phi, gb, ga, c, (D2, D), (G3, G2.transpose(2, 3, 0, 1), G))
+    assert abs(Ls - L1) < 1e-13 * max(1, abs(L1))
+    # equal spins: the closed-shell loss with the seeds summed over the spin blocks
+    g1 = np.zeros((8, 8)); g1[[0, 1], [0, 1]] = 1.0
+    Lc = og.loss(p.xyz, p.w, p.phi, np.array([0, 1]), c, D, G)
+    Le = og.loss_open(p.xyz, p.w, p.phi, g1, g1, c, (D / 2, D / 2), (G / 3, G / 3, G / 3))
+    assert abs(Le - Lc) < 1e-13 * max(1, abs(Lc))
+    gc = og.exact_gradient(p.xyz, p.w, p.phi, np.array([0, 1]), c, D, G)
+    ge = og.exact_gradient_open(p.xyz, p.w, p.phi, g1, g1, c, (D / 2, D / 2), (G / 3, G / 3, G / 3))
+    assert np.abs(ge - gc).max() < 1e-12 * max(1, np.abs(gc).max())
