@@ -139,8 +139,8 @@ typedef struct {
  *   h1 [2][N][N]: [Delta h]^a, [Delta h]^b,
  *   E0 = -1/3 sum_s [Delta h]^s . gamma^s.
  * Intermediates W and W~ use the total density, Z~ and Z that of each spin;
- * the two-body GEMM runs once per spin.  xtc_backward supports the closed
- * shell only (XTC_E_UNSUPPORTED here). */
+ * the two-body GEMM runs once per spin.  xtc_backward takes spin-blocked
+ * seeds for such a problem (see there). */
 typedef struct {
     int32_t N;
     int32_t Ng;
@@ -224,6 +224,11 @@ xtc_status xtc_contract_1body_0body(const xtc_problem *pb, const double *K,
  * over all (g, g') in FP64 with a fixed-order reduction (deterministic).
  * Requires a workspace prepared (xtc_prepare) with prec | XTC_WITH_BACKWARD.
  * gV2: device [N]^4 or NULL (= 0); gh1: device [N][N] or NULL; gE0: host value.
+ * Open shell (occ_n_beta set): the loss of the spin-resolved outputs,
+ *   L = gE0 * E0 + sum_s gh1[s] . h1[s] + sum_b gV2[b] . V2[b],
+ * gV2 device [3][N]^4 (blocks aa, ab, bb as xtc_contract_2body writes them),
+ * gh1 device [2][N][N] (alpha, beta); the folding follows Appendix A and the
+ * two accumulators M^a, M^b get separate, non-symmetric adjoints.
  * The K recompute follows prec (reduced forms keep the occupied block FP64);
  * the adjoint GEMMs and the coefficient contraction are FP64.
  * Errors: XTC_E_UNSUPPORTED for a Pade Jastrow or nocc > 24. */

@@ -15,6 +15,17 @@
 //   dL/dc_j = sum_{g,g'} (gj'(r)/r) sum_x (r_g - r_g')_x Pi^x(g,g'),
 //   Pi^x(g,g') = sum_P Kbar^x_P(g) rho_P(g'),  gj(r) = t^j,  gj'(r) = j t^(j-1)/(1+r)^2.
 // Pi is never stored: each tile is reduced into 16 FP64 sums in the epilogue.
+//
+// Restricted open shell (Appendix A): blocks V2^ab[pq,rs] = -(M^b[P,R] + M^a[R,P])
+// for ab in (aa, ab, bb), h1^s = -1/2 (sum_t V2^st . gamma^t - V2^ss[p,k,k,q] n^s_k)
+// (V2^ba[pq,rs] = V2^ab[rs,pq]) and E0 = -1/3 sum_s h1^s . gamma^s give the
+// effective seeds Gt^aa, Gt^ab, Gt^bb (seed_eff_open) and
+//   Gbar^a[P][R] = -sum (Gt^aa[abcd] + Gt^aa[cdab] + Gt^ab[cdab]),
+//   Gbar^b[P][R] = -sum (Gt^bb[abcd] + Gt^bb[cdab] + Gt^ab[abcd]),
+// which are not symmetric.  M^t = sum_g C^T D^t then gives
+//   Cbar_c = sum_t D^t_c Gbar^t^T,  Dbar^t_c = C_c Gbar^t,
+// and the local adjoint sums the two spin channels: W, W~ come from the
+// total density, Z~^t, Z^t from gamma^t (k_adj_T once per spin).
 #pragma once
 #include "kernels_contract.h"
 #include "xtc_device.h"
@@ -44,14 +55,44 @@ __device__ __forceinline__ double seed_eff(const double* __restrict__ gV2, const
     return v;
 }
 
-// occw[p] = n_p (0 outside the density), kidx[p] = position of p in occ or -1.
+// Effective seed of block `blk` (0: aa, 1: ab, 2: bb) of the open-shell loss
+// (see the header comment): gV2 [3][N^4], gh1 [2][N^2] (either may be NULL),
+// occw [3][N] = (n^a, n^b, n^a + n^b), 0 outside the density.
+__device__ __forceinline__ double seed_eff_open(const double* __restrict__ gV2, const double* __restrict__ gh1,
+                                                double gE0, const double* __restrict__ occw, int N, int blk, int a,
+                                                int b, int c, int d) {
+    const size_t NN = (size_t)N * N;
+    // D'^s[p][q] = gh1^s[p][q] - (1/3) gE0 n^s_p [p == q]
+    auto dprime = [&](int sp, int p, int q) {
+        double v = gh1 ? gh1[sp * NN + (size_t)p * N + q] : 0.0;
+        if (p == q) v -= (1.0 / 3.0) * gE0 * occw[sp * N + p];
+        return v;
+    };
+    double v = gV2 ? gV2[blk * NN * NN + ((size_t)a * N + b) * NN + (size_t)c * N + d] : 0.0;
+    if (blk != 1) {   // aa or bb: Coulomb-like and exchange terms of h1^s, s = the block's spin
+        const int sp = blk / 2;
+        if (c == d && occw[sp * N + c] != 0.0) v -= 0.5 * occw[sp * N + c] * dprime(sp, a, b);
+        if (b == c && occw[sp * N + b] != 0.0) v += 0.5 * occw[sp * N + b] * dprime(sp, a, d);
+    } else {          // ab: h1^a with t = b, and h1^b with t = a through V2^ba[pq,kk] = V2^ab[kk,pq]
+        if (c == d && occw[N + c] != 0.0) v -= 0.5 * occw[N + c] * dprime(0, a, b);
+        if (a == b && occw[a] != 0.0) v -= 0.5 * occw[a] * dprime(1, c, d);
+    }
+    return v;
+}
+
+// occw [3][N] = (n_p of the list's spin, total minus that, total) with 0
+// outside the density (closed shell: n_p, n_p, 2 n_p; open shell with the
+// alpha list: n^a, n^b, n^a + n^b); kidx[p] = position of p in occ or -1.
 __global__ void k_occ_flags(OccList occ, int N, double* __restrict__ occw, int* __restrict__ kidx) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     int idx = -1;
     for (int i = 0; i < occ.n; ++i)
         if (occ.k[i] == p) idx = i;
-    occw[p] = idx >= 0 ? occ.w[idx] : 0.0;
+    const double w = idx >= 0 ? occ.w[idx] : 0.0, wt = idx >= 0 ? occ.wt[idx] : 0.0;
+    occw[p] = w;
+    occw[N + p] = wt - w;
+    occw[2 * N + p] = wt;
     kidx[p] = idx;
 }
 
@@ -84,15 +125,54 @@ __global__ __launch_bounds__(256) void k_make_gbar(const double* __restrict__ gV
     G[(size_t)P * ldP + R] = -acc;
 }
 
+// Open shell: Gbar^a, Gbar^b [ldP][ldP] and their transposes GaT, GbT (see the
+// header comment); zero in the padding.
+__global__ __launch_bounds__(256) void k_make_gbar_open(const double* __restrict__ gV2, const double* __restrict__ gh1,
+                                                        double gE0, const double* __restrict__ occw, int N, int ldP,
+                                                        double* __restrict__ Ga, double* __restrict__ Gb,
+                                                        double* __restrict__ GaT, double* __restrict__ GbT) {
+    const int R = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = blockIdx.y;
+    if (R >= ldP) return;
+    const int Npair = N * (N + 1) / 2;
+    double acc_a = 0.0, acc_b = 0.0;
+    if (P < Npair && R < Npair) {
+        int p = 0, rem = P;
+        while (rem >= N - p) { rem -= N - p; ++p; }
+        const int q = p + rem;
+        int r = 0;
+        rem = R;
+        while (rem >= N - r) { rem -= N - r; ++r; }
+        const int s = r + rem;
+        const int ab[2][2] = {{p, q}, {q, p}};
+        const int cd[2][2] = {{r, s}, {s, r}};
+        const int nab = p == q ? 1 : 2, ncd = r == s ? 1 : 2;
+        for (int i = 0; i < nab; ++i)
+            for (int j = 0; j < ncd; ++j) {
+                const int a = ab[i][0], b = ab[i][1], c = cd[j][0], d = cd[j][1];
+                acc_a += seed_eff_open(gV2, gh1, gE0, occw, N, 0, a, b, c, d) +
+                         seed_eff_open(gV2, gh1, gE0, occw, N, 0, c, d, a, b) +
+                         seed_eff_open(gV2, gh1, gE0, occw, N, 1, c, d, a, b);
+                acc_b += seed_eff_open(gV2, gh1, gE0, occw, N, 2, a, b, c, d) +
+                         seed_eff_open(gV2, gh1, gE0, occw, N, 2, c, d, a, b) +
+                         seed_eff_open(gV2, gh1, gE0, occw, N, 1, a, b, c, d);
+            }
+    }
+    Ga[(size_t)P * ldP + R] = -acc_a;
+    Gb[(size_t)P * ldP + R] = -acc_b;
+    GaT[(size_t)R * ldP + P] = -acc_a;
+    GbT[(size_t)R * ldP + P] = -acc_b;
+}
+
 // ------------------------------------------------------- NT GEMM (FP64) --
-// Y[i][j] = sum_k X[i][k] Gm[j][k] for i < rows, j < ldP, k < ldP (Gm symmetric,
-// so this is X Gbar).  Workgroup 4 waves as 2 x 2, wave tile 32 (i) x 64 (j).
+// Y[i][j] (+)= sum_k X[i][k] Gm[j][k] for i < rows, j < ldP, k < ldP, i.e.
+// X Gm^T (closed shell: Gm = Gbar, symmetric).  Workgroup 4 waves as 2 x 2, wave tile 32 (i) x 64 (j).
 // Each lane loads 4 consecutive k of one row per operand block (32-byte
 // vectors); MFMA e of a 16-k step uses element e, i.e. the k index inside the
 // step is permuted as 4 (l/16) + e identically for both operands.
 __global__ __launch_bounds__(256) void k_gemm_xg_f64(const double* __restrict__ X, size_t ldx, int rows,
                                                      const double* __restrict__ Gm, int ldP, int n_jt,
-                                                     double* __restrict__ Y, size_t ldy) {
+                                                     double* __restrict__ Y, size_t ldy, int accumulate) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int it = blockIdx.x / n_jt, jt = blockIdx.x % n_jt;
     const int i0 = it * 64 + 32 * (wave & 1), j0 = jt * 128 + 64 * (wave >> 1);
@@ -129,7 +209,10 @@ __global__ __launch_bounds__(256) void k_gemm_xg_f64(const double* __restrict__ 
             const int i = i0 + 16 * a + (lane >> 4) + 4 * v;
             if (i < rows) {
 #pragma unroll
-                for (int b = 0; b < 4; ++b) Y[(size_t)i * ldy + j0 + 16 * b + l16] = acc[a][b][v];
+                for (int b = 0; b < 4; ++b) {
+                    double* y = Y + (size_t)i * ldy + j0 + 16 * b + l16;
+                    *y = accumulate ? *y + acc[a][b][v] : acc[a][b][v];
+                }
             }
         }
 }
@@ -140,10 +223,12 @@ __global__ __launch_bounds__(256) void k_gemm_xg_f64(const double* __restrict__ 
 // (off-diagonal packed entries counted half in each full-matrix slot),
 //   T^x[r][k] = -2 n_k sum_s (Abar'[r][s] X^x[s][k] + Bbar'^x[r][s] rho_o[s][k])
 // and Wbar^x = sum_R Abar_R K^x_R.  T goes to scratch [rows][3][N][nocc].
+// Open shell: one launch per spin channel (its Abar, Bbar slots and
+// occupations), the second adding into T and Wbar (accumulate).
 __global__ __launch_bounds__(256) void k_adj_T(const double* __restrict__ rho_rows, const double* __restrict__ K,
                                                const double* __restrict__ Y, size_t ystride, int rows, int ldP,
                                                int N, OccList occ, double* __restrict__ T,
-                                               double* __restrict__ Wbar) {
+                                               double* __restrict__ Wbar, int accumulate) {
     extern __shared__ d4 locc[];                    // [nocc][N] of (rho, Kx, Ky, Kz)
     __shared__ double red[3][4];
     const int n = occ.n;
@@ -177,7 +262,10 @@ __global__ __launch_bounds__(256) void k_adj_T(const double* __restrict__ rho_ro
         if (lane == 0) { red[0][wave] = w0; red[1][wave] = w1; red[2][wave] = w2; }
         __syncthreads();
         if (threadIdx.x == 0) {
-            for (int x = 0; x < 3; ++x) Wbar[(size_t)g * 3 + x] = red[x][0] + red[x][1] + red[x][2] + red[x][3];
+            for (int x = 0; x < 3; ++x) {
+                const double v = red[x][0] + red[x][1] + red[x][2] + red[x][3];
+                Wbar[(size_t)g * 3 + x] = accumulate ? Wbar[(size_t)g * 3 + x] + v : v;
+            }
         }
         // T rows: one thread per r, all occupied columns in registers
         for (int r = threadIdx.x; r < N; r += blockDim.x) {
@@ -206,9 +294,10 @@ __global__ __launch_bounds__(256) void k_adj_T(const double* __restrict__ rho_ro
             for (int kk = 0; kk < kMaxOccAdj; ++kk) {
                 if (kk < n) {
                     const double m2n = -2.0 * occ.w[kk];
-                    tg[(size_t)0 * N * n + r * n + kk] = m2n * t0[kk];
-                    tg[(size_t)1 * N * n + r * n + kk] = m2n * t1[kk];
-                    tg[(size_t)2 * N * n + r * n + kk] = m2n * t2[kk];
+                    double* t = tg + r * n + kk;
+                    t[(size_t)0 * N * n] = (accumulate ? t[(size_t)0 * N * n] : 0.0) + m2n * t0[kk];
+                    t[(size_t)1 * N * n] = (accumulate ? t[(size_t)1 * N * n] : 0.0) + m2n * t1[kk];
+                    t[(size_t)2 * N * n] = (accumulate ? t[(size_t)2 * N * n] : 0.0) + m2n * t2[kk];
                 }
             }
         }
@@ -216,14 +305,17 @@ __global__ __launch_bounds__(256) void k_adj_T(const double* __restrict__ rho_ro
     }
 }
 
-// Kbar^x_R = Cbar^x_R + Abar_R W^x + (Wt/2) Bbar^x_R + [a = b in occ] 2 n_a Wbar^x
+// Kbar^x_R = Cbar^x_R + Abar_R W^x + (Wt/2) Bbar^x_R + [a = b in occ] nt_a Wbar^x
 //            + [b in occ] T^x[a][b] + [a in occ, a != b] T^x[b][a],   R = pair(a <= b)
-// (W, Wt from the per-point scalars S of the intermediates: S[0] = Wt/2, S[1..3] = W/2).
+// with nt the total occupations (closed shell 2 n) and, for the open shell,
+// Abar and Bbar summed over the two spin channels (Y slots 3..6 and 7..10)
+// (W, Wt from the per-point scalars S of the intermediates: S[0] = Wt/2,
+// S[1..3] = W/2, the same in both channels).
 // Written into Y slots 0..2 in place (Cbar there already).
 __global__ void k_adj_assemble(double* __restrict__ Y, size_t ystride, const double* __restrict__ S,
                                const double* __restrict__ T, const double* __restrict__ Wbar,
                                const int* __restrict__ kidx, const double* __restrict__ occw, int rows, int ldP,
-                               int N, int nocc) {
+                               int N, int nocc, int nspin) {
     const int Npair = N * (N + 1) / 2;
     const size_t n = (size_t)rows * Npair;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
@@ -234,13 +326,14 @@ __global__ void k_adj_assemble(double* __restrict__ Y, size_t ystride, const dou
         const double* s = S + (size_t)g * 8;
         const double hWt = s[0], W[3] = {2.0 * s[1], 2.0 * s[2], 2.0 * s[3]};
         const size_t o = (size_t)g * ldP + R;
-        const double ab = Y[3 * ystride + o];
+        const double ab = Y[3 * ystride + o] + (nspin == 2 ? Y[7 * ystride + o] : 0.0);
         const int ka = kidx[a], kb = kidx[b];
         const double* tg = T + (size_t)g * 3 * N * nocc;
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
-            double v = Y[x * ystride + o] + ab * W[x] + hWt * Y[(4 + x) * ystride + o];
-            if (a == b && ka >= 0) v += 2.0 * occw[a] * Wbar[(size_t)g * 3 + x];
+            const double bb = Y[(4 + x) * ystride + o] + (nspin == 2 ? Y[(8 + x) * ystride + o] : 0.0);
+            double v = Y[x * ystride + o] + ab * W[x] + hWt * bb;
+            if (a == b && ka >= 0) v += occw[2 * N + a] * Wbar[(size_t)g * 3 + x];
             if (kb >= 0) v += tg[(size_t)x * N * nocc + a * nocc + kb];
             if (ka >= 0 && a != b) v += tg[(size_t)x * N * nocc + b * nocc + ka];
             Y[x * ystride + o] = v;

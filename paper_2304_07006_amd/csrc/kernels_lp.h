@@ -939,15 +939,15 @@ __global__ __launch_bounds__(256) void k_pi_grad_lp(const void* __restrict__ Kb,
 //  GRAD (NC = 3, the Pi contraction Pi^x(g,g') = sum_P Kbar^x[g][P] rho[g'][P]
 //   with i = g - g0, j = g'): the gradient terms of every (g, g'), summed per
 //   workgroup into part[blockIdx.x][16];
-//  otherwise: out[c][i][j] = FP64 value, i < rows, j < nB (out + c * out_comp,
-//   leading dimension ldo).
+//  otherwise: out[c][i][j] = FP64 value (added to out with accumulate),
+//   i < rows, j < nB (out + c * out_comp, leading dimension ldo).
 constexpr int kPiThreads = 512;
 template <int FORM, int NC, bool GRAD>
 __global__ __launch_bounds__(kPiThreads) void k_nt_bf16(const __bf16* __restrict__ A, size_t a_comp, size_t a_split,
                                                         int rows, const __bf16* __restrict__ B, size_t b_split,
                                                         int nB, int ldk, int n_rt, const d4* __restrict__ pos,
                                                         int g0, int ncoef, double* __restrict__ out,
-                                                        size_t out_comp, int ldo) {
+                                                        size_t out_comp, int ldo, int accumulate) {
     static_assert(FORM == 3 || FORM == 6, "split-BF16 forms only");
     static_assert(!GRAD || NC == 3, "the gradient epilogue takes the three components of Pi");
     constexpr int NS = Lp<FORM>::NS;
@@ -1073,7 +1073,10 @@ __global__ __launch_bounds__(kPiThreads) void k_nt_bf16(const __bf16* __restrict
                     const int j = jbase + 16 * b + l16;
                     if (j >= nB) continue;
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) out[c * out_comp + (size_t)i * ldo + j] = (double)acc[c][h][b][v];
+                    for (int c = 0; c < NC; ++c) {
+                        double* o = out + c * out_comp + (size_t)i * ldo + j;
+                        *o = (accumulate ? *o : 0.0) + (double)acc[c][h][b][v];
+                    }
                 }
             }
         return;

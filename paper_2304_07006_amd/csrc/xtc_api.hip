@@ -99,9 +99,10 @@ constexpr int kOccSegMax = 32;  // most segments of the FP64 occupied-block sum 
 struct Layout {
     int N, Ng, nocc, ldP, ngp, Npair, prec;
     int form, ns, es, ldL, ldO, nOP, occNB, nsegK, nspin, ldN, segK, segM;
+    int nY;              // adjoint Y slots: Cbar (3), then Abar, Bbar (4) per spin channel
     bool tc2;
     bool bwd;
-    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, occw, kidx, rhoR, GsL, Atc, Btc;
+    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, occw, kidx, rhoR, GsL, Atc, Btc, GT;
     size_t fixed;        // bytes before S (plus the Mpart remainder reserve)
     size_t per_row;      // bytes per chunk row
     int cap;             // chunk rows that fit (multiple of kRowQuant)
@@ -156,6 +157,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.nsegK = (L.ngp + L.segK - 1) / L.segK;
     L.bwd = (prec & XTC_WITH_BACKWARD) != 0;
     L.tc2 = (prec & XTC_WITH_TC2) != 0;
+    L.nY = 3 + 4 * L.nspin;
     L.ldN = (int)align_up((size_t)pb->N * pb->N, 128);
     const bool lp = L.form != 0;
     size_t off = 0;
@@ -169,11 +171,16 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.T1 = off;      off = align_up(off + (size_t)kT1Split * L.ldP * sizeof(double), kAlign);
     L.E = off;       off = align_up(off + (size_t)kESplitMax * L.N * L.N * sizeof(double), kAlign);
     L.gacc = off;    off = align_up(off + (L.bwd ? kGradMax * sizeof(double) : 0), kAlign);
-    L.occw = off;    off = align_up(off + (L.bwd ? (size_t)L.N * sizeof(double) : 0), kAlign);
+    L.occw = off;    off = align_up(off + (L.bwd ? (size_t)3 * L.N * sizeof(double) : 0), kAlign);
     L.kidx = off;    off = align_up(off + (L.bwd ? (size_t)L.N * sizeof(int) : 0), kAlign);
     L.rhoR = off;    off = align_up(off + (L.bwd && lp ? (size_t)L.ns * L.ngp * L.ldP * L.es : 0), kAlign);
     const bool bsplit = L.bwd && L.form == 3;   // split-BF16 X Gbar products (3-product form)
-    L.GsL = off;     off = align_up(off + (bsplit ? (size_t)L.ns * L.ldP * L.ldP * L.es : 0), kAlign);
+    // open shell: Gbar^a, Gbar^b in M, their transposes in GT; split copies
+    // (k-packed) of Gbar (closed) or of Gbar^a, Gbar^b, Gbar^aT, Gbar^bT
+    L.GT = off;      off = align_up(off + (L.bwd && L.nspin == 2 ? (size_t)2 * L.ldP * L.ldP * sizeof(double) : 0),
+                                    kAlign);
+    L.GsL = off;     off = align_up(off + (bsplit ? (size_t)(L.nspin == 2 ? 4 : 1) * L.ns * L.ldP * L.ldP * L.es : 0),
+                                    kAlign);
     L.Atc = off;     off = align_up(off + (L.tc2 ? (size_t)L.ldP * L.ldP * sizeof(double) : 0), kAlign);
     L.Btc = off;     off = align_up(off + (L.tc2 ? (size_t)L.ldN * L.ldP * sizeof(double) : 0), kAlign);
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);   // one 32-row tile of partials
@@ -191,7 +198,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
         L.per_row += (size_t)L.nsegK * 3 * L.ldL * sizeof(float) + L.cdw * L.ns * L.es + (mslab + L.segM - 1) / L.segM;
     if (L.tc2) L.per_row += (size_t)L.ldP * sizeof(double) + (size_t)3 * L.ldN * sizeof(double);
     if (L.bwd)
-        L.per_row += (size_t)10 * L.ldP * sizeof(double) + (size_t)3 * L.N * L.nocc * sizeof(double) +
+        L.per_row += (size_t)(3 + L.nY) * L.ldP * sizeof(double) + (size_t)3 * L.N * L.nocc * sizeof(double) +
                      3 * sizeof(double) + (gslab + 31) / 32 + (lp ? (size_t)7 * L.ns * L.ldP * L.es : 0);
     L.cap = 0;
     return L;
@@ -215,7 +222,7 @@ void place_chunk(Layout& L, size_t bytes) {
     L.Kocc = off;    off = align_up(off + (lp ? (size_t)kOccSegMax * 3 * cap * L.ldO * sizeof(double) : 0), kAlign);
     const bool b = L.bwd;
     L.Kc = off;      off = align_up(off + (b ? (size_t)3 * cap * L.ldP * sizeof(double) : 0), kAlign);
-    L.Y = off;       off = align_up(off + (b ? (size_t)7 * cap * L.ldP * sizeof(double) : 0), kAlign);
+    L.Y = off;       off = align_up(off + (b ? (size_t)L.nY * cap * L.ldP * sizeof(double) : 0), kAlign);
     L.T = off;       off = align_up(off + (b ? (size_t)cap * 3 * L.N * L.nocc * sizeof(double) : 0), kAlign);
     L.Wbar = off;    off = align_up(off + (b ? (size_t)cap * 3 * sizeof(double) : 0), kAlign);
     L.gpart = off;   off = align_up(off + (b ? (size_t)((cap + 31) / 32) * gslab : 0), kAlign);
@@ -588,21 +595,16 @@ xtc_status pack_kmajor_any(int form, const double* src, int nrows, int ld, void*
 // form (k_nt_bf16, FP32 accumulation over all pairs): X k-packed splits
 // [7][2][ldP/8][rows][8], Gbar k-packed splits [2][ldP/8][ldP][8], Y [7][cap][ldP] FP64.
 // Components share the Gbar operand in groups of 3 + 4.
-template <int FORM, int NC>
-xtc_status xg_group(const __bf16* X, size_t a_comp, size_t a_split, int rows, const __bf16* Gs, int ldP, int c0,
-                    double* Y, size_t ystride, hipStream_t st) {
+// Y_c (+)= X_c Gm^T for NC consecutive components (X k-packed splits from X,
+// Y FP64 from Y, component strides a_comp and ystride), Gm k-packed split.
+template <int NC>
+xtc_status xg_group(const __bf16* X, size_t a_comp, size_t a_split, int rows, const __bf16* Gs, int ldP,
+                    double* Y, size_t ystride, int accumulate, hipStream_t st) {
     const int n_rt = (rows + kLpRows - 1) / kLpRows, n_jt = (ldP + kPiThreads - 1) / kPiThreads;
-    hipLaunchKernelGGL((k_nt_bf16<FORM, NC, false>), dim3(n_rt * n_jt), dim3(kPiThreads), 0, st, X + c0 * a_comp,
-                       a_comp, a_split, rows, Gs, (size_t)ldP * ldP, ldP, ldP, n_rt, (const d4*)nullptr, 0, 0,
-                       Y + c0 * ystride, ystride, ldP);
+    hipLaunchKernelGGL((k_nt_bf16<3, NC, false>), dim3(n_rt * n_jt), dim3(kPiThreads), 0, st, X, a_comp, a_split,
+                       rows, Gs, (size_t)ldP * ldP, ldP, ldP, n_rt, (const d4*)nullptr, 0, 0, Y, ystride, ldP,
+                       accumulate);
     return launched("gemm_xg_bf16");
-}
-
-xtc_status xg_bf16x3(const __bf16* X, size_t a_comp, size_t a_split, int rows, const __bf16* Gs, int ldP, double* Y,
-                     size_t ystride, hipStream_t st) {
-    xtc_status s;
-    if ((s = xg_group<3, 3>(X, a_comp, a_split, rows, Gs, ldP, 0, Y, ystride, st)) != XTC_OK) return s;
-    return xg_group<3, 4>(X, a_comp, a_split, rows, Gs, ldP, 3, Y, ystride, st);
 }
 
 xtc_status build_K_any(const Layout& L, const JasDev& J, int g0, int rows, double* K, bool occ64, void* ws,
@@ -817,27 +819,46 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
     if (!gcoef) return fail(XTC_E_ARG, "gcoef is NULL");
     if (!std::isfinite(gE0)) return fail(XTC_E_ARG, "gE0 not finite");
     if (pb->nocc > kMaxOccAdj) return fail(XTC_E_UNSUPPORTED, "the adjoint supports nocc <= %d", kMaxOccAdj);
-    if (pb->occ_n_beta) return fail(XTC_E_UNSUPPORTED, "the adjoint covers the closed-shell equations only");
     Layout L = make_layout(pb, prec);
     place_chunk(L, ws_bytes);
     if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    const OccList occ = make_occ(pb);
+    const bool open = L.nspin == 2;
+    const OccList occ = make_occ(pb, 0);
     hipLaunchKernelGGL(k_occ_flags, dim3((L.N + 255) / 256), dim3(256), 0, st, occ, L.N, at<double>(ws, L.occw),
                        at<int>(ws, L.kidx));
     if ((s = launched("occ_flags")) != XTC_OK) return s;
+    // adjoint of the packed accumulator(s): Gm[t] is the right operand of the
+    // Cbar products (Gbar^t) and Gm[2 + t] that of the Abar, Bbar products
+    // (Gbar^t transposed); closed shell: one symmetric Gbar for both
+    const size_t gsz = (size_t)L.ldP * L.ldP;
     double* G = at<double>(ws, L.M);
-    hipLaunchKernelGGL(k_make_gbar, dim3((L.ldP + 255) / 256, L.ldP), dim3(256), 0, st, gV2, gh1, gE0,
-                       at<double>(ws, L.occw), L.N, L.ldP, G);
+    const double* Gm[4] = {G, G, G, G};
+    if (!open) {
+        hipLaunchKernelGGL(k_make_gbar, dim3((L.ldP + 255) / 256, L.ldP), dim3(256), 0, st, gV2, gh1, gE0,
+                           at<double>(ws, L.occw), L.N, L.ldP, G);
+    } else {
+        double* GT = at<double>(ws, L.GT);
+        hipLaunchKernelGGL(k_make_gbar_open, dim3((L.ldP + 255) / 256, L.ldP), dim3(256), 0, st, gV2, gh1, gE0,
+                           at<double>(ws, L.occw), L.N, L.ldP, G, G + gsz, GT, GT + gsz);
+        Gm[1] = G + gsz;
+        Gm[2] = GT;
+        Gm[3] = GT + gsz;
+    }
     if ((s = launched("make_gbar")) != XTC_OK) return s;
     // the X Gbar products in split BF16 only in the 3-product form: the MFMA's
     // FP32 accumulation rounds with a small negative bias, which the six-product
     // form (twice the accumulations per k-step, and a smaller random error to
     // hide it) carries coherently into the gradient; it keeps them in FP64
     const bool bsplit = L.form == 3;
-    if (bsplit &&
-        (s = pack_kmajor_any(L.form, G, L.ldP, L.ldP, at<void>(ws, L.GsL), (size_t)L.ldP * L.ldP, st)) != XTC_OK)
-        return s;
+    const __bf16* Gs[4];
+    for (int i = 0; i < 4; ++i) {
+        const int slot = open ? i : 0;
+        Gs[i] = at<__bf16>(ws, L.GsL) + (size_t)slot * L.ns * gsz;
+        if (bsplit && (open || i == 0) &&
+            (s = pack_kmajor_any(L.form, Gm[i], L.ldP, L.ldP, (void*)Gs[i], gsz, st)) != XTC_OK)
+            return s;
+    }
     const size_t ystride = (size_t)L.cap * L.ldP;
     double* Kc = at<double>(ws, L.Kc);
     double* Y = at<double>(ws, L.Y);
@@ -849,29 +870,42 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
         if ((s = build_K_any(L, J, g0, rows, Kc, true, ws, st)) != XTC_OK) return s;
         if ((s = run_intermediates(L, pb, Kc, g0, g0 + rows, ws, st)) != XTC_OK) return s;
         const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
-        const double* D = at<double>(ws, L.D);
         const size_t kstride = (size_t)rows * L.ldP;
-        // Y slots: 0..2 Cbar_{1..3} = D_{1..3} Gbar, 3 Abar = rho Gbar, 4..6 Bbar = K Gbar
-        const double* src[7] = {D + ystride, D + 2 * ystride, D + 3 * ystride, rho_rows, Kc, Kc + kstride,
-                                Kc + 2 * kstride};
-        if (bsplit) {
-            // split-BF16: the seven operands to k-packed splits, then the NT
-            // products in groups of components sharing Gbar
-            const size_t a_split = (size_t)rows * L.ldP, a_comp = (size_t)L.ns * a_split;
-            char* xs = at<char>(ws, L.KbL);
-            for (int y = 0; y < 7; ++y)
-                if ((s = pack_kmajor_any(L.form, src[y], rows, L.ldP, xs + y * a_comp * L.es, a_split, st)) !=
+        // Y slots: 0..2 Cbar_{1..3} = sum_t D^t_{1..3} Gbar^t^T, then per spin
+        // channel t: 3 + 4t Abar^t = rho Gbar^t, 4 + 4t .. 6 + 4t Bbar^t = K Gbar^t
+        const double* rk[4] = {rho_rows, Kc, Kc + kstride, Kc + 2 * kstride};
+        const size_t a_split = (size_t)rows * L.ldP, a_comp = (size_t)L.ns * a_split;
+        char* xs = at<char>(ws, L.KbL);
+        // split-BF16: rho and K to k-packed splits once (slots 3..6), D^t (slots 0..2) per channel
+        if (bsplit)
+            for (int y = 0; y < 4; ++y)
+                if ((s = pack_kmajor_any(L.form, rk[y], rows, L.ldP, xs + (3 + y) * a_comp * L.es, a_split, st)) !=
                     XTC_OK)
                     return s;
-            if ((s = xg_bf16x3((const __bf16*)xs, a_comp, a_split, rows, at<__bf16>(ws, L.GsL), L.ldP, Y, ystride,
-                               st)) != XTC_OK)
-                return s;
-        } else {
-            const int n_it = (rows + 63) / 64, n_jt = L.ldP / 128;
-            for (int y = 0; y < 7; ++y) {
-                hipLaunchKernelGGL(k_gemm_xg_f64, dim3(n_it * n_jt), dim3(256), 0, st, src[y], (size_t)L.ldP, rows, G,
-                                   L.ldP, n_jt, Y + y * ystride, (size_t)L.ldP);
-                if ((s = launched("gemm_xg")) != XTC_OK) return s;
+        for (int t = 0; t < L.nspin; ++t) {
+            const double* D = at<double>(ws, L.D) + (size_t)t * 4 * ystride;
+            const double* dsrc[3] = {D + ystride, D + 2 * ystride, D + 3 * ystride};
+            double* Yab = Y + (size_t)(3 + 4 * t) * ystride;
+            if (bsplit) {
+                for (int y = 0; y < 3; ++y)
+                    if ((s = pack_kmajor_any(L.form, dsrc[y], rows, L.ldP, xs + y * a_comp * L.es, a_split, st)) !=
+                        XTC_OK)
+                        return s;
+                if ((s = xg_group<3>((const __bf16*)xs, a_comp, a_split, rows, Gs[t], L.ldP, Y, ystride, t, st)) !=
+                    XTC_OK)
+                    return s;
+                if ((s = xg_group<4>((const __bf16*)(xs + 3 * a_comp * L.es), a_comp, a_split, rows, Gs[2 + t],
+                                     L.ldP, Yab, ystride, 0, st)) != XTC_OK)
+                    return s;
+            } else {
+                const int n_it = (rows + 63) / 64, n_jt = L.ldP / 128;
+                for (int y = 0; y < 7; ++y) {
+                    const double* X = y < 3 ? dsrc[y] : rk[y - 3];
+                    double* Yy = y < 3 ? Y + (size_t)y * ystride : Yab + (size_t)(y - 3) * ystride;
+                    hipLaunchKernelGGL(k_gemm_xg_f64, dim3(n_it * n_jt), dim3(256), 0, st, X, (size_t)L.ldP, rows,
+                                       Gm[y < 3 ? t : 2 + t], L.ldP, n_jt, Yy, (size_t)L.ldP, y < 3 ? t : 0);
+                    if ((s = launched("gemm_xg")) != XTC_OK) return s;
+                }
             }
         }
         const size_t lds = (size_t)L.nocc * L.N * 4 * sizeof(double);
@@ -883,13 +917,16 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
                 return fail(XTC_E_HIP, "adj_T LDS attribute: %s", hipGetErrorString(e));
             }
         }
-        hipLaunchKernelGGL(k_adj_T, dim3(std::min(rows, 4096)), dim3(256), lds, st, rho_rows, Kc, Y, ystride, rows,
-                           L.ldP, L.N, occ, at<double>(ws, L.T), at<double>(ws, L.Wbar));
-        if ((s = launched("adj_T")) != XTC_OK) return s;
+        for (int t = 0; t < L.nspin; ++t) {
+            hipLaunchKernelGGL(k_adj_T, dim3(std::min(rows, 4096)), dim3(256), lds, st, rho_rows, Kc,
+                               Y + (size_t)4 * t * ystride, ystride, rows, L.ldP, L.N, make_occ(pb, t),
+                               at<double>(ws, L.T), at<double>(ws, L.Wbar), t);
+            if ((s = launched("adj_T")) != XTC_OK) return s;
+        }
         const size_t nel = (size_t)rows * L.Npair;
         hipLaunchKernelGGL(k_adj_assemble, dim3((unsigned)std::min<size_t>((nel + 255) / 256, 16384)), dim3(256), 0, st,
                            Y, ystride, at<double>(ws, L.S), at<double>(ws, L.T), at<double>(ws, L.Wbar),
-                           at<int>(ws, L.kidx), at<double>(ws, L.occw), rows, L.ldP, L.N, L.nocc);
+                           at<int>(ws, L.kidx), at<double>(ws, L.occw), rows, L.ldP, L.N, L.nocc, L.nspin);
         if ((s = launched("adj_assemble")) != XTC_OK) return s;
         const int n_it_pi = (rows + 31) / 32;
         int nblk_pi;
@@ -926,11 +963,11 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
                 if (L.form == 3)
                     hipLaunchKernelGGL((k_nt_bf16<3, 3, true>), dim3(nblk_pi), dim3(kPiThreads), 0, st, kbb, kb_comp,
                                        kb_split, rows, rrb, rr_split, L.ngp, L.ldP, n_rt, at<d4>(ws, L.pos), g0,
-                                       J.ncoef, at<double>(ws, L.gpart), (size_t)0, 0);
+                                       J.ncoef, at<double>(ws, L.gpart), (size_t)0, 0, 0);
                 else
                     hipLaunchKernelGGL((k_nt_bf16<6, 3, true>), dim3(nblk_pi), dim3(kPiThreads), 0, st, kbb, kb_comp,
                                        kb_split, rows, rrb, rr_split, L.ngp, L.ldP, n_rt, at<d4>(ws, L.pos), g0,
-                                       J.ncoef, at<double>(ws, L.gpart), (size_t)0, 0);
+                                       J.ncoef, at<double>(ws, L.gpart), (size_t)0, 0, 0);
             }
             if ((s = launched("pi_grad_lp")) != XTC_OK) return s;
         }

@@ -250,8 +250,9 @@ def xtc_contract_1body_0body(dp, K, g0, g1, prec, flags, h1, E0, ws, stream=None
 
 def xtc_backward(dp, jas: XtcJastrow, prec, gV2, gh1, gE0, gcoef, ws, stream=None):
     _dev(ws, 1, "ws", "uint8")
-    _dev(gV2, dp.N ** 4, "gV2", required=False)
-    _dev(gh1, dp.N ** 2, "gh1", required=False)
+    blocks = 3 if _nspin(dp) == 2 else 1          # open shell: spin-blocked seeds (aa, ab, bb) and (a, b)
+    _dev(gV2, blocks * dp.N ** 4, "gV2", required=False)
+    _dev(gh1, (2 if blocks == 3 else 1) * dp.N ** 2, "gh1", required=False)
     _dev(gcoef, max(1, jas.ncoef), "gcoef")
     _check(load().xtc_backward(ctypes.byref(dp.c), ctypes.byref(jas), prec, _ptr(gV2), _ptr(gh1), float(gE0),
                                _ptr(gcoef), _ptr(ws), ws.numel(), _stream(stream)))
