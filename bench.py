@@ -224,33 +224,38 @@ def run_tc2(problem, prec, chunk, steps, warmup):
     return (time.perf_counter() - t0) / steps, K2
 
 
-def f_backward(N, Ng):
+def f_backward(N, Ng, nspin=1):
     """Algorithmic flops of the adjoint as built: the K recompute and the Pi
     contraction (6 Ng^2 Npair each) and the seven X . Gbar products
-    (2 Ng Npair^2 each)."""
+    (2 Ng Npair^2 each) per spin channel."""
     P = N * (N + 1) // 2
-    return 12 * Ng * Ng * P + 14 * Ng * P * P
+    return 12 * Ng * Ng * P + nspin * 14 * Ng * P * P
 
 
 def run_backward(problem, prec, chunk, aux_seed, steps, warmup):
     """Forward pass and adjoint (xtc_backward, K recomputed) of the loss
     L = E0 + <h1, D> + <V2, G>, D symmetric and G 8-fold symmetric, seeded on
-    the device.  Returns seconds per forward and per backward, the gradient,
-    and the Euler check |c . dL/dc - 2 L| / |2 L| (L is homogeneous of degree 2
-    in the power-Jastrow coefficients)."""
+    the device (open shell: one D per spin and one G per block aa, ab, bb).
+    Returns seconds per forward and per backward, the gradient, and the Euler
+    check |c . dL/dc - 2 L| / |2 L| (L is homogeneous of degree 2 in the
+    power-Jastrow coefficients)."""
     import torch
     from paper_2304_07006_amd import xtc
     N = problem.N
+    occ_n, occ_nb = getattr(problem, "occ_n", None), getattr(problem, "occ_n_beta", None)
+    nD, nG = (2, 3) if occ_nb is not None else (1, 1)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(aux_seed + 7)
-    X = torch.randn((N, N), generator=gen, device="cuda", dtype=torch.float64)
-    D = 0.5 * (X + X.T)
-    G = torch.randn((N, N, N, N), generator=gen, device="cuda", dtype=torch.float64)
-    G = 0.25 * (G + G.permute(1, 0, 2, 3) + G.permute(0, 1, 3, 2) + G.permute(1, 0, 3, 2))
-    G = (0.5 * (G + G.permute(2, 3, 0, 1))).contiguous()
+    X = torch.randn((nD, N, N), generator=gen, device="cuda", dtype=torch.float64)
+    D = 0.5 * (X + X.transpose(1, 2))
+    G = torch.randn((nG, N, N, N, N), generator=gen, device="cuda", dtype=torch.float64)
+    G = 0.25 * (G + G.permute(0, 2, 1, 3, 4) + G.permute(0, 1, 2, 4, 3) + G.permute(0, 2, 1, 4, 3))
+    G = (0.5 * (G + G.permute(0, 3, 4, 1, 2))).contiguous()
+    if nD == 1:
+        D, G = D[0].contiguous(), G[0].contiguous()
     coef = [float(c) for c in problem.jastrow.coef]
     jas = xtc.power_jastrow(coef)
-    dp = xtc.device_problem(problem.xyz, problem.w, problem.phi, problem.occ)
+    dp = xtc.device_problem(problem.xyz, problem.w, problem.phi, problem.occ, occ_n=occ_n, occ_n_beta=occ_nb)
 
     def timed(fn):
         for _ in range(warmup):
@@ -393,15 +398,16 @@ def main():
         if wl.jastrow_kind == "pade":
             print("the adjoint needs a power-Jastrow workload", file=sys.stderr)
             sys.exit(2)
-        Ff, Fb = f_alg(wl.N, wl.nocc, wl.Ng), f_backward(wl.N, wl.Ng)
+        nspin = 2 if getattr(problem, "occ_n_beta", None) is not None else 1
+        Ff, Fb = f_alg(wl.N, nref, wl.Ng, nspin), f_backward(wl.N, wl.Ng, nspin)
         print(f"[bench] backward {args.workload} prec={args.prec} chunk={chunk}", file=sys.stderr, flush=True)
         tf, tb, g, euler, peak_mem = run_backward(problem, args.prec, chunk, wl.aux_seed, args.steps, args.warmup)
         line = {"metric": "xTC forward + adjoint GFLOP/s (loss E0 + <h1,D> + <V2,G>, gradient in the Jastrow coefficients)",
                 "value": (Ff + Fb) / (tf + tb) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
                 "warmup": args.warmup, "ms_per_step": (tf + tb) * 1e3, "higher_is_better": True, "scaling": "weak",
                 "vs_baseline": None, "dtype": DTYPE[args.prec], "data": "synthetic",
-                "config": {"workload": args.workload, "N": wl.N, "nocc": wl.nocc, "Ng": wl.Ng, "prec": args.prec,
-                           "chunk_rows": chunk, "F_fwd": Ff, "F_bwd": Fb},
+                "config": {"workload": args.workload, "N": wl.N, "nocc": nref, "Ng": wl.Ng, "prec": args.prec,
+                           "chunk_rows": chunk, "density": density, "F_fwd": Ff, "F_bwd": Fb},
                 "forward_s": tf, "backward_s": tb, "forward_tflops": Ff / tf / 1e12,
                 "backward_tflops": Fb / tb / 1e12, "euler_rel": euler, "peak_device_bytes": peak_mem,
                 "grad_head": [float(x) for x in g[:4]]}
