@@ -3,8 +3,8 @@ configuration bench.py times (N=128, 16 occupied, Ng=150 000, 20 chunks of
 7500 rows in split BF16 x3, 10 in FP64): sampled K entries against their exact
 grid sums, the antisymmetry of the pair contraction of K, the split-BF16
 and FP32 outputs against the FP64 path to the bars, bitwise symmetry and determinism;
-and the adjoint at N=96, Ng=100 000 through the Euler identity of the
-quadratic loss."""
+and the adjoint at N=96, Ng=100 000 (closed and open shell) through the
+Euler identity of the quadratic loss."""
 import numpy as np
 import pytest
 
@@ -176,6 +176,20 @@ def test_full_size_adjoint_euler(torch_cuda):
     wl = inputs.WORKLOADS["N96-occ12-Ng100k"]
     p = inputs.make_workload(wl.name)
     _note("case: N96-occ12-Ng100k adjoint bf16x3, Euler identity")
+    tf, tb, g, euler, _ = bench.run_backward(p, "bf16x3", _chunk("bf16x3", p.Ng), wl.aux_seed, 1, 0)
+    _note(f"  |c.g - 2L| / |2L| = {euler:.2e}; forward {tf:.2f} s, adjoint {tb:.2f} s")
+    assert np.all(np.isfinite(g)) and euler < 1e-5
+
+
+def test_full_size_open_shell_adjoint_euler(torch_cuda):
+    """The open-shell adjoint at N=96, Ng=100 000 (10 doubly and 4 singly
+    occupied orbitals, spin-blocked seeds), split BF16 x3 in 20 chunks:
+    c . dL/dc = 2L (bench.py --backward --density open:10,4)."""
+    import bench
+    wl = inputs.WORKLOADS["N96-occ12-Ng100k"]
+    p = inputs.make_workload(wl.name)
+    bench.apply_density(p, "open:10,4")
+    _note("case: N96-occ12-Ng100k open shell 10+4 adjoint bf16x3, Euler identity")
     tf, tb, g, euler, _ = bench.run_backward(p, "bf16x3", _chunk("bf16x3", p.Ng), wl.aux_seed, 1, 0)
     _note(f"  |c.g - 2L| / |2L| = {euler:.2e}; forward {tf:.2f} s, adjoint {tb:.2f} s")
     assert np.all(np.isfinite(g)) and euler < 1e-5
