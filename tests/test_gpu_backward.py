@@ -174,3 +174,21 @@ def test_open_shell_gradient_equal_spins_and_spin_exchange(torch_cuda):
                         (Go[2], np.ascontiguousarray(Go[1].transpose(2, 3, 0, 1)), Go[0]), chunk_rows=256)
     _note(f"  |g - g(spins exchanged)| {np.abs(g1 - g2).max():.3e} of {np.abs(g1).max():.3e}")
     assert np.abs(g1 - g2).max() < 1e-11 * max(1.0, np.abs(g1).max())
+
+
+def test_open_shell_autograd_function(torch_cuda):
+    """XtcFunction on an open-shell problem: the spin-blocked outputs' gradients
+    flow back as the spin-blocked seeds of xtc_backward."""
+    import torch
+    from paper_2304_07006_amd import xtc
+    p, ga, gb, coef, D, G = _open_case(8, 1, 1, 500, 2, 45)
+    _note("case: autograd.Function, open shell")
+    dp = xtc.device_problem(p.xyz, p.w, p.phi, p.occ, occ_n=p.occ_n, occ_n_beta=p.occ_n_beta)
+    c = torch.tensor(coef, dtype=torch.float64, device="cuda", requires_grad=True)
+    V2, h1, E0 = xtc.XtcFunction.apply(c, dp)
+    assert tuple(V2.shape) == (3, 8, 8, 8, 8) and tuple(h1.shape) == (2, 8, 8)
+    loss = (E0.sum() + (h1 * torch.as_tensor(np.stack(D)).cuda()).sum()
+            + (V2 * torch.as_tensor(np.stack(G)).cuda()).sum())
+    loss.backward()
+    g = _gpu_grad_open(torch, p, coef, D, G)
+    assert np.abs(c.grad.cpu().numpy() - g).max() < 1e-12 * max(1.0, np.abs(g).max())
