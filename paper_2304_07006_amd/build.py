@@ -21,17 +21,27 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *SOURCES, "-o", tmp]
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer for the C-ABI
+# checks (device code is built as usual); load with the sanitizer runtime
+# preloaded.
+SANITIZE_FLAGS = ("-O1 -g -Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined "
+                  "-Xarch_host -fno-omit-frame-pointer -shared-libsan").split()
+
+
+def build(verbose: bool = False, out: str | None = None, sanitize: bool = False) -> str:
+    """Compile libxtc.so in-tree (or to `out`); `sanitize` adds the host-side
+    sanitizers (a checking build, not the product library)."""
+    lib = out or LIB
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, *FLAGS, *(SANITIZE_FLAGS if sanitize else ()), *SOURCES, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{out}")
     if verbose and out.strip():
         print(out, file=sys.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
