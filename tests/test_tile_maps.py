@@ -1,0 +1,50 @@
+"""The XCD-aware tile orders of the split K build and the NT products
+(xcd_strip_tile in kernels_lp.h), transcribed index for index: every
+workgroup id of the launched grid maps to a distinct (row tile, strip) and
+every tile is covered, for the launch shapes in use and ragged ones; each
+XCD (id % 8) walks whole strips among the first 8 floor(nstrip/8)."""
+import pytest
+
+
+def xcd_strip_tile(wg, n_rt, nstrip):
+    q8 = nstrip // 8
+    if wg < 8 * q8 * n_rt:
+        li = wg // 8
+        return li % n_rt, wg % 8 + 8 * (li // n_rt)
+    i2 = wg - 8 * q8 * n_rt
+    return i2 % n_rt, 8 * q8 + i2 // n_rt
+
+
+def k_build_tile(wg, n_rt, n_full, n_ct, nseg):
+    """The K build's (row tile, column tile, segment): full column tiles in
+    XCD-aware order, then the column tile with idle waves (if any)."""
+    nf = n_rt * n_full * nseg
+    if wg < nf:
+        rt, strip = xcd_strip_tile(wg, n_rt, n_full * nseg)
+        return rt, strip % n_full, strip // n_full
+    return (wg - nf) % n_rt, n_ct - 1, (wg - nf) // n_rt
+
+
+@pytest.mark.parametrize("n_rt,n_full,n_ct,nseg", [
+    (235, 16, 17, 19),      # N=128, 7500-row chunks, split BF16 (last column tile partly idle)
+    (391, 25, 26, 31),      # N=160, 12500-row chunks
+    (1, 1, 1, 1), (3, 1, 2, 2), (7, 3, 3, 5), (5, 8, 8, 1),
+])
+def test_k_build_tile_map_is_a_bijection(n_rt, n_full, n_ct, nseg):
+    total = n_rt * n_full * nseg + (n_rt * nseg if n_full < n_ct else 0)
+    tiles = {k_build_tile(w, n_rt, n_full, n_ct, nseg) for w in range(total)}
+    assert len(tiles) == total
+    assert all(0 <= rt < n_rt and 0 <= ct < n_ct and 0 <= s < nseg for rt, ct, s in tiles)
+
+
+@pytest.mark.parametrize("n_rt,nstrip", [(391, 489), (32, 17), (1, 1), (9, 8), (4, 23)])
+def test_strip_order_bijection_and_xcd_affinity(n_rt, nstrip):
+    seen, owner = set(), {}
+    for w in range(n_rt * nstrip):
+        rt, strip = xcd_strip_tile(w, n_rt, nstrip)
+        assert 0 <= rt < n_rt and 0 <= strip < nstrip
+        seen.add((rt, strip))
+        if strip < 8 * (nstrip // 8):
+            owner.setdefault(strip, set()).add(w % 8)
+    assert len(seen) == n_rt * nstrip
+    assert all(len(x) == 1 for x in owner.values())     # a dealt strip stays on one XCD
