@@ -591,12 +591,12 @@ xtc_status pack_kmajor_any(int form, const double* src, int nrows, int ld, void*
     return launched("pack_kmajor");
 }
 
-// Y_c = X_c Gbar for the seven adjoint operands in the split-BF16 3-product
-// form (k_nt_bf16, FP32 accumulation over all pairs): X k-packed splits
-// [7][2][ldP/8][rows][8], Gbar k-packed splits [2][ldP/8][ldP][8], Y [7][cap][ldP] FP64.
-// Components share the Gbar operand in groups of 3 + 4.
-// Y_c (+)= X_c Gm^T for NC consecutive components (X k-packed splits from X,
-// Y FP64 from Y, component strides a_comp and ystride), Gm k-packed split.
+// The adjoint's X Gbar products in the split-BF16 3-product form (k_nt_bf16,
+// FP32 accumulation over all pairs): Y_c (+)= X_c Gm^T for NC consecutive
+// components sharing one right operand (X k-packed splits [NC][2][ldP/8][rows][8]
+// with component stride a_comp, Gm k-packed splits [2][ldP/8][ldP][8], Y FP64
+// [NC][cap][ldP] with component stride ystride).  The seven operands of a spin
+// channel form two groups: D_{1..3} with Gbar, and rho, K^{x,y,z} with Gbar^T.
 template <int NC>
 xtc_status xg_group(const __bf16* X, size_t a_comp, size_t a_split, int rows, const __bf16* Gs, int ldP,
                     double* Y, size_t ystride, int accumulate, hipStream_t st) {
