@@ -56,7 +56,7 @@ def test_natural_occupations_fp64(torch_cuda):
     assert abs(E0 - E0o) < TOL_ABS
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
 def test_spin_averaged_open_shell(torch_cuda, prec):
     """Spin-averaged density of a high-spin open-shell determinant: 3 doubly
     and 2 singly occupied orbitals (n = 1, 1, 1, 1/2, 1/2), 16-term power Jastrow."""
@@ -156,7 +156,7 @@ def test_open_shell_tiny_against_explicit_L(torch_cuda):
     assert max(e) < TOL_ABS
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
 def test_open_shell_against_appendix_a(torch_cuda, prec):
     from oracle import factorised as fb
     k, na, nb = inputs.open_shell_occupations(3, 2)
