@@ -65,7 +65,7 @@ def traffic_record(prec, workload, chunk):
 KBUILD_KERNELS = ("k_build_K_lp", "k_reduce_K", "k_build_K_occ", "k_reduce_occ", "k_build_K_f64")
 
 
-def traffic_from(fetch_dir, write_dir, workload, prec, chunk):
+def traffic_from(fetch_dir, write_dir, workload, prec, chunk, path=None):
     """Write the per-launch HBM bytes of xtc_build_K into
     profiles/traffic_xtc_build_K.json from two counter runs of --probe
     (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, --output-format csv).
@@ -96,7 +96,7 @@ def traffic_from(fetch_dir, write_dir, workload, prec, chunk):
 
     fetch, ff = per_kernel(fetch_dir, "FETCH_SIZE")
     write, wf = per_kernel(write_dir, "WRITE_SIZE")
-    path = os.path.join(ROOT, "profiles", "traffic_xtc_build_K.json")
+    path = path or os.path.join(ROOT, "profiles", "traffic_xtc_build_K.json")
     rec = json.load(open(path)) if os.path.exists(path) else {}
     rec[f"{workload}/{prec}/{chunk}"] = {
         "bytes_per_launch": sum(fetch.values()) + sum(write.values()),

@@ -1,0 +1,58 @@
+"""Host-side pieces of bench.py: the algorithmic flop counts behind the
+reported rates (against the counts the scope table gives for the measured
+workloads) and the conversion of two counter runs into per-launch HBM bytes
+(synthetic counter files: a 1 GiB calibration copy and the K-build kernels)."""
+import csv
+import json
+import os
+
+import bench
+
+
+def test_algorithmic_flop_counts():
+    # F_alg = 6 Ng^2 Npair + 8 Ng Npair^2 + (18 n + 10) Ng Npair
+    assert bench.f_alg(128, 16, 150000) == 1196722886400000          # 1.197e15 at N=128, Ng=150 000
+    assert abs(bench.f_alg(8, 2, 2000) - 8.9e8) / 8.9e8 < 0.01
+    assert abs(bench.f_alg(64, 8, 50000) - 3.30e13) / 3.30e13 < 0.01
+    # K build of one chunk: 6 rows Ng Npair
+    assert bench.f_kbuild(128, 7500, 150000) == 6 * 7500 * 150000 * 8256
+    # adjoint: 12 Ng^2 Npair + 14 Ng Npair^2 (about 5.9e14 at N=96, Ng=100 000)
+    assert abs(bench.f_backward(96, 100000) - 5.9e14) / 5.9e14 < 0.01
+    # open shell: the two-body terms once per spin channel
+    P = 128 * 129 // 2
+    assert bench.f_alg(128, 16, 150000, 2) - bench.f_alg(128, 16, 150000) == 8 * 150000 * P * P + 298 * 150000 * P
+    assert bench.f_backward(96, 100000, 2) - bench.f_backward(96, 100000) == 14 * 100000 * 4656 ** 2
+
+
+def _counter_csv(d, counter, rows):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "run_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for did, name, value in rows:
+            # two device instances per dispatch, summed by the reader
+            w.writerow([did, name, counter, value / 2])
+            w.writerow([did, name, counter, value / 2])
+
+
+def test_traffic_from_counter_runs(tmp_path):
+    kib = 1024.0
+    # the copy moves 2^30 bytes: FETCH_SIZE reads half of that (factor 2), WRITE_SIZE all of it
+    fetch = [(1, "__amd_rocclr_copyBuffer", 2 ** 29 / kib),
+             (2, "void xtc::k_build_K_lp<0, 3, 3>(double const*, ...)", 10e9 / kib),
+             (3, "xtc::k_reduce_K(float const*, int)", 3e9 / kib),
+             (4, "xtc::k_unrelated(int)", 7e9 / kib)]
+    write = [(1, "__amd_rocclr_copyBuffer", 2 ** 30 / kib),
+             (2, "void xtc::k_build_K_lp<0, 3, 3>(double const*, ...)", 1e9 / kib),
+             (3, "xtc::k_reduce_K(float const*, int)", 0.5e9 / kib)]
+    _counter_csv(str(tmp_path / "f"), "FETCH_SIZE", fetch)
+    _counter_csv(str(tmp_path / "w"), "WRITE_SIZE", write)
+    out = str(tmp_path / "traffic.json")
+    bench.traffic_from(str(tmp_path / "f"), str(tmp_path / "w"), "W", "bf16x3", 7500, path=out)
+    rec = json.load(open(out))["W/bf16x3/7500"]
+    assert abs(rec["fetch_factor"] - 2.0) < 1e-12 and abs(rec["write_factor"] - 1.0) < 1e-12
+    per = rec["per_kernel_bytes"]
+    assert set(per) == {"k_build_K_lp", "k_reduce_K"}                # unrelated kernels are not counted
+    assert abs(per["k_build_K_lp"]["fetch"] - 20e9) < 1 and abs(per["k_reduce_K"]["write"] - 0.5e9) < 1
+    assert abs(rec["bytes_per_launch"] - (20e9 + 6e9 + 1e9 + 0.5e9)) < 4
+    assert rec["sources"] == bench.kernel_sources_hash()
