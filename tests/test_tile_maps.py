@@ -6,8 +6,8 @@ XCD (id % 8) walks whole strips among the first 8 floor(nstrip/8)."""
 import pytest
 
 
-def xcd_strip_tile(wg, n_rt, nstrip):
-    q8 = nstrip // 8
+def xcd_strip_tile(wg, n_rt, nstrip, deal=True):
+    q8 = nstrip // 8 if deal else 0
     if wg < 8 * q8 * n_rt:
         li = wg // 8
         return li % n_rt, wg % 8 + 8 * (li // n_rt)
@@ -15,12 +15,12 @@ def xcd_strip_tile(wg, n_rt, nstrip):
     return i2 % n_rt, 8 * q8 + i2 // n_rt
 
 
-def k_build_tile(wg, n_rt, n_full, n_ct, nseg):
+def k_build_tile(wg, n_rt, n_full, n_ct, nseg, deal=True):
     """The K build's (row tile, column tile, segment): full column tiles in
     XCD-aware order, then the column tile with idle waves (if any)."""
     nf = n_rt * n_full * nseg
     if wg < nf:
-        rt, strip = xcd_strip_tile(wg, n_rt, n_full * nseg)
+        rt, strip = xcd_strip_tile(wg, n_rt, n_full * nseg, deal)
         return rt, strip % n_full, strip // n_full
     return (wg - nf) % n_rt, n_ct - 1, (wg - nf) // n_rt
 
@@ -32,9 +32,10 @@ def k_build_tile(wg, n_rt, n_full, n_ct, nseg):
 ])
 def test_k_build_tile_map_is_a_bijection(n_rt, n_full, n_ct, nseg):
     total = n_rt * n_full * nseg + (n_rt * nseg if n_full < n_ct else 0)
-    tiles = {k_build_tile(w, n_rt, n_full, n_ct, nseg) for w in range(total)}
-    assert len(tiles) == total
-    assert all(0 <= rt < n_rt and 0 <= ct < n_ct and 0 <= s < nseg for rt, ct, s in tiles)
+    for deal in (True, False):                       # dealt to XCDs, or plain order (large strips)
+        tiles = {k_build_tile(w, n_rt, n_full, n_ct, nseg, deal) for w in range(total)}
+        assert len(tiles) == total
+        assert all(0 <= rt < n_rt and 0 <= ct < n_ct and 0 <= s < nseg for rt, ct, s in tiles)
 
 
 @pytest.mark.parametrize("n_rt,nstrip", [(391, 489), (32, 17), (1, 1), (9, 8), (4, 23)])
@@ -48,3 +49,5 @@ def test_strip_order_bijection_and_xcd_affinity(n_rt, nstrip):
             owner.setdefault(strip, set()).add(w % 8)
     assert len(seen) == n_rt * nstrip
     assert all(len(x) == 1 for x in owner.values())     # a dealt strip stays on one XCD
+    plain = [xcd_strip_tile(w, n_rt, nstrip, False) for w in range(n_rt * nstrip)]
+    assert plain == [(w % n_rt, w // n_rt) for w in range(n_rt * nstrip)]   # row tile fastest
