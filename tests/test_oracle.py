@@ -476,3 +476,28 @@ def test_open_shell_loss_gradient_pins():
     gc = og.exact_gradient(p.xyz, p.w, p.phi, np.array([0, 1]), c, D, G)
     ge = og.exact_gradient_open(p.xyz, p.w, p.phi, g1, g1, c, (D / 2, D / 2), (G / 3, G / 3, G / 3))
     assert np.abs(ge - gc).max() < 1e-12 * max(1, np.abs(gc).max())
+
+
+def test_zero_body_term_needs_only_the_occupied_block_of_K():
+    """The closed-shell zero-body term written with the occupied-occupied block
+    of K alone (k, l, m occupied; rb = sum_k rho_kk, kb = sum_k K_kk):
+      E0 = -sum_g [4 rb |kb|^2 - 4 (sum_kl rho_kl K_kl) . kb - 2 rb sum_kl |K_kl|^2
+                   + 2 sum_x sum_klm rho_km K^x_ml K^x_lk]
+    equals -(2/3) sum_k h1_kk of the Appendix-B equations; so a K whose
+    occupied block is exact gives the exact E0 whatever the rest of K.  Also
+    with a random occupied set and E0 = 0 for a single occupied orbital."""
+    p = inputs.make_problem(8, 3, 400, 2, "pair", "pade", seed=91)
+    for occ in (np.array([0, 1, 2]), np.array([1, 4, 6]), np.array([5])):
+        V2, h1, E0 = fb.closed_shell(p.xyz, p.w, p.phi, occ, p.jastrow)
+        K = fb.grid_K(p.xyz, p.w, p.phi, p.jastrow, slice(0, p.Ng))[:, :, occ][:, :, :, occ]   # [3][g][k][l]
+        rho = (p.w[:, None, None] * p.phi[occ].T[:, :, None] * p.phi[occ].T[:, None, :])      # [g][k][l]
+        rb = np.einsum("gkk->g", rho)
+        kb = np.einsum("xgkk->xg", K)
+        e = (4 * rb * np.einsum("xg,xg->g", kb, kb)
+             - 4 * np.einsum("gkl,xgkl,xg->g", rho, K, kb)
+             - 2 * rb * np.einsum("xgkl,xgkl->g", K, K)
+             + 2 * np.einsum("gkm,xgml,xglk->g", rho, K, K))
+        E0_occ = -float(e.sum())
+        assert abs(E0_occ - E0) < 1e-14 * max(1.0, abs(E0)), (occ, E0_occ, E0)
+        if len(occ) == 1:
+            assert abs(E0_occ) < 1e-16
