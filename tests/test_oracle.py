@@ -501,3 +501,31 @@ def test_zero_body_term_needs_only_the_occupied_block_of_K():
         assert abs(E0_occ - E0) < 1e-14 * max(1.0, abs(E0)), (occ, E0_occ, E0)
         if len(occ) == 1:
             assert abs(E0_occ) < 1e-16
+
+
+def test_one_body_direct_grid_reduction():
+    """The one-body term as the direct grid reduction the HIP path evaluates
+    in FP64 (eq. tcmf:2el substituted into Appendix B's one-body equation),
+      h1_pq = sum_g [rho_pq a + K_pq . b + rb A_pq + kb . B_pq]
+              - 1/2 sum_g sum_k [rho_pk A_kq + K_pk . B_kq + rho_kq A_pk + K_kq . B_pk],
+    a = sum_k A_kk, b = sum_k B_kk, rb = sum_k rho_kk, kb = sum_k K_kk (k occupied),
+    equals the oracle's h1 obtained from V2."""
+    p = inputs.make_problem(8, 3, 400, 2, "pair", "power16", seed=92)
+    occ = np.array([0, 2, 5])
+    V2, h1, E0 = fb.closed_shell(p.xyz, p.w, p.phi, occ, p.jastrow)
+    g = np.zeros((8, 8))
+    g[occ, occ] = 1.0
+    K = fb.grid_K(p.xyz, p.w, p.phi, p.jastrow, slice(0, p.Ng))                   # [3][g][N][N]
+    rho = p.w[:, None, None] * p.phi.T[:, :, None] * p.phi.T[:, None, :]             # [g][N][N]
+    A, B = fb.intermediates(rho, K, g)
+    o = occ
+    a = np.einsum("gkk->g", A[:, o][:, :, o])
+    b = np.einsum("xgkk->xg", B[:, :, o][:, :, :, o])
+    rb = np.einsum("gkk->g", rho[:, o][:, :, o])
+    kb = np.einsum("xgkk->xg", K[:, :, o][:, :, :, o])
+    d = (np.einsum("gpq,g->pq", rho, a) + np.einsum("xgpq,xg->pq", K, b)
+         + np.einsum("g,gpq->pq", rb, A) + np.einsum("xg,xgpq->pq", kb, B))
+    x = (np.einsum("gpk,gkq->pq", rho[:, :, o], A[:, o, :]) + np.einsum("xgpk,xgkq->pq", K[:, :, :, o], B[:, :, o, :])
+         + np.einsum("gkq,gpk->pq", rho[:, o, :], A[:, :, o]) + np.einsum("xgkq,xgpk->pq", K[:, :, o, :], B[:, :, :, o]))
+    h1_direct = d - 0.5 * x
+    assert np.abs(h1_direct - h1).max() < 1e-14 * max(1.0, np.abs(h1).max())
