@@ -19,13 +19,13 @@ from __future__ import annotations
 
 import numpy as np
 
-from .jastrow import grad1, grad1_basis
+from .jastrow import grad1
 
 
-def grid_K(xyz, w, phi, jas, rows, grad=None):
+def grid_K(xyz, w, phi, jas, rows):
     """V_r^s(i) for the grid rows ``rows`` (a slice), [3][len][N][N]:
     sum_j w_j phi_r(j) grad_1 u(r_i, r_j) phi_s(j)."""
-    d = grad1(xyz[rows], xyz, jas) if grad is None else grad(xyz[rows], xyz)
+    d = grad1(xyz[rows], xyz, jas)
     N = phi.shape[0]
     rho_j = ((phi * w)[:, None, :] * phi[None, :, :]).reshape(N * N, -1)   # [rs][j]
     K = np.einsum("xij,aj->xia", d, rho_j, optimize=True)
@@ -50,7 +50,7 @@ def intermediates(rho, K, gamma):
     return A, B
 
 
-def closed_shell(xyz, w, phi, gamma, jas, block=512, grad=None, return_f=False):
+def closed_shell(xyz, w, phi, gamma, jas, block=512, return_f=False):
     """V2 [N]^4 (V2[p,q,r,s] = Delta U_{pr}^{qs}), h1 [N][N] and E0.
 
     ``gamma`` may be an (N x N) matrix or an index array of occupied orbitals."""
@@ -59,7 +59,7 @@ def closed_shell(xyz, w, phi, gamma, jas, block=512, grad=None, return_f=False):
     f = np.zeros((N * N, N * N))
     for i0 in range(0, Ng, block):
         rows = slice(i0, min(Ng, i0 + block))
-        K = grid_K(xyz, w, phi, jas, rows, grad)
+        K = grid_K(xyz, w, phi, jas, rows)
         rho = w[rows, None, None] * phi[:, rows].T[:, :, None] * phi[:, rows].T[:, None, :]
         A, B = intermediates(rho, K, gamma)
         nb = rho.shape[0]
@@ -91,7 +91,7 @@ def intermediates_spin(rho, K, g_tau, g_tot):
     return A, B
 
 
-def open_shell(xyz, w, phi, gamma_a, gamma_b, jas, block=512, grad=None):
+def open_shell(xyz, w, phi, gamma_a, gamma_b, jas, block=512):
     """Restricted open-shell working equations (Appendix A): same spatial
     orbitals and Jastrow for both spins, spin-specific densities.
 
@@ -108,7 +108,7 @@ def open_shell(xyz, w, phi, gamma_a, gamma_b, jas, block=512, grad=None):
     f = [np.zeros((N * N, N * N)), np.zeros((N * N, N * N))]
     for i0 in range(0, Ng, block):
         rows = slice(i0, min(Ng, i0 + block))
-        K = grid_K(xyz, w, phi, jas, rows, grad)
+        K = grid_K(xyz, w, phi, jas, rows)
         rho = w[rows, None, None] * phi[:, rows].T[:, :, None] * phi[:, rows].T[:, None, :]
         nb = rho.shape[0]
         for t in range(2):
@@ -170,7 +170,3 @@ def subset(phi, occ, extra):
     S = [int(k) for k in occ] + [int(k) for k in extra if int(k) not in set(map(int, occ))]
     return np.array(S), np.arange(len(occ))
 
-
-def basis_grad(k):
-    """Gradient generator for the k-th power basis function, for grid_K(grad=...)."""
-    return lambda xa, xb: grad1_basis(xa, xb, k)

@@ -41,13 +41,6 @@ def du_dr(r, kind: str, b: float = 1.0, coef=()):
     raise ValueError(kind)
 
 
-def basis_du_dr(r, k: int):
-    """d/dr of the k-th power basis function t^k (k >= 1): k t^(k-1)/(1+r)^2."""
-    r = np.asarray(r, dtype=np.float64)
-    t = r / (1.0 + r)
-    return k * t ** (k - 1) / (1.0 + r) ** 2
-
-
 def grad1(xa: np.ndarray, xb: np.ndarray, jas) -> np.ndarray:
     """grad_1 u(r_a, r_b) for all pairs: array [3][len(xa)][len(xb)].
 
@@ -56,16 +49,6 @@ def grad1(xa: np.ndarray, xb: np.ndarray, jas) -> np.ndarray:
     d = xa[:, None, :] - xb[None, :, :]            # [na][nb][3]
     r = np.sqrt(np.sum(d * d, axis=2))
     up = du_dr(r, jas.kind, jas.b, jas.coef)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        f = np.where(r > 0.0, up / np.where(r > 0.0, r, 1.0), 0.0)
-    return np.moveaxis(d * f[:, :, None], 2, 0)
-
-
-def grad1_basis(xa: np.ndarray, xb: np.ndarray, k: int) -> np.ndarray:
-    """grad_1 of the k-th power basis function, [3][na][nb], zero at r == 0."""
-    d = xa[:, None, :] - xb[None, :, :]
-    r = np.sqrt(np.sum(d * d, axis=2))
-    up = basis_du_dr(r, k)
     with np.errstate(divide="ignore", invalid="ignore"):
         f = np.where(r > 0.0, up / np.where(r > 0.0, r, 1.0), 0.0)
     return np.moveaxis(d * f[:, :, None], 2, 0)

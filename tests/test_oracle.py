@@ -529,3 +529,95 @@ def test_one_body_direct_grid_reduction():
          + np.einsum("gkq,gpk->pq", rho[:, o, :], A[:, :, o]) + np.einsum("xgkq,xgpk->pq", K[:, :, o, :], B[:, :, :, o]))
     h1_direct = d - 0.5 * x
     assert np.abs(h1_direct - h1).max() < 1e-14 * max(1.0, np.abs(h1).max())
+
+
+# ----------------------------------------------------------------- Loewdin --
+# The oracle's symmetric orthonormalisation (phi = S^{-1/2} chi under the grid
+# weights) pinned by what characterises it: C = S^{-1/2} is symmetric positive
+# definite with C S C = I, the orbitals are orthonormal under the weights, the
+# cross overlap phi W chi^T is symmetric positive definite (polar
+# decomposition), which makes phi the orthonormal set closest to chi, and the
+# two-function case has a closed form.
+from oracle import lowdin as ol
+
+
+@pytest.fixture(scope="module")
+def lowdin_case():
+    p = inputs.make_problem(24, 3, 4000, 3, "chain", "pade", seed=31)
+    phi, C, lam = ol.lowdin(p.chi, p.w)
+    S = (p.chi * p.w) @ p.chi.T
+    return p, phi, C, lam, S
+
+
+def test_lowdin_matrix_is_symmetric_positive_definite_inverse_square_root(lowdin_case):
+    p, phi, C, lam, S = lowdin_case
+    cond = lam.max() / lam.min()
+    eps = np.finfo(float).eps
+    assert np.allclose(lam, np.linalg.eigvalsh(S), rtol=1e-12, atol=0)
+    assert np.abs(C - C.T).max() <= 10 * eps * np.abs(C).max()
+    assert np.linalg.eigvalsh(0.5 * (C + C.T)).min() > 0
+    # C S C = I and (C C) S = I: C is S^{-1/2}, not S^{-1} or a non-symmetric root
+    assert np.abs(C @ S @ C - np.eye(24)).max() < 50 * eps * cond
+    assert np.abs(C @ C @ S - np.eye(24)).max() < 50 * eps * cond
+
+
+def test_lowdin_orbitals_orthonormal_under_weights(lowdin_case):
+    p, phi, C, lam, S = lowdin_case
+    cond = lam.max() / lam.min()
+    O = (phi * p.w) @ phi.T
+    assert np.abs(O - np.eye(24)).max() < 50 * np.finfo(float).eps * cond
+
+
+def test_lowdin_is_the_closest_orthonormal_set(lowdin_case):
+    """The cross overlap M = phi W chi^T is symmetric positive definite with
+    M^2 = S, and sum_m ||phi_m - chi_m||_w^2 is below that of Gram-Schmidt
+    (Cholesky) orthonormalisation and of every rotated set Q phi."""
+    p, phi, C, lam, S = lowdin_case
+    cond = lam.max() / lam.min()
+    M = (phi * p.w) @ p.chi.T
+    assert np.abs(M - M.T).max() < 50 * np.finfo(float).eps * cond * np.abs(M).max()
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+    assert np.abs(M @ M - S).max() < 1e-10 * np.abs(S).max()
+
+    def dist(psi):
+        return float(np.sum(p.w * (psi - p.chi) ** 2))
+
+    d0 = dist(phi)
+    Lc = np.linalg.cholesky(S)
+    gs = np.linalg.solve(Lc, p.chi)                 # Gram-Schmidt in the given order
+    assert np.abs((gs * p.w) @ gs.T - np.eye(24)).max() < 1e-6
+    assert dist(gs) > d0 * (1 + 1e-6)
+    rng = np.random.default_rng(5)
+    for t in (1e-3, 1e-1, 1.0):
+        A = rng.standard_normal((24, 24))
+        Q = np.linalg.qr(np.eye(24) + t * (A - A.T))[0]
+        Q = Q * np.sign(np.diag(Q))                  # near the identity for small t
+        assert dist(Q @ phi) > d0
+
+
+def test_lowdin_two_function_closed_form():
+    """Two normalised functions with overlap s: S^{-1/2} = [[a, b], [b, a]],
+    a, b = ((1+s)^{-1/2} +- (1-s)^{-1/2}) / 2."""
+    rng = np.random.default_rng(6)
+    Ng = 500
+    w = rng.uniform(0.5, 2.0, Ng)
+    X = rng.standard_normal((2, Ng))
+    e = np.linalg.solve(np.linalg.cholesky((X * w) @ X.T), X)   # orthonormal under w
+    for s in (0.1, -0.6, 0.95):
+        chi = np.array([e[0], s * e[0] + np.sqrt(1 - s * s) * e[1]])
+        phi, C, lam = ol.lowdin(chi, w)
+        a = 0.5 * ((1 + s) ** -0.5 + (1 - s) ** -0.5)
+        b = 0.5 * ((1 + s) ** -0.5 - (1 - s) ** -0.5)
+        assert np.allclose(C, [[a, b], [b, a]], rtol=0, atol=1e-12 / (1 - abs(s)))
+        assert np.allclose(np.sort(lam), np.sort([1 - s, 1 + s]), rtol=0, atol=1e-13)
+
+
+def test_lowdin_fixes_orthonormal_sets_and_is_rotation_covariant(lowdin_case):
+    p, phi, C, lam, S = lowdin_case
+    phi2, C2, lam2 = ol.lowdin(phi, p.w)
+    assert np.abs(C2 - np.eye(24)).max() < 1e-9 and np.abs(phi2 - phi).max() < 1e-9 * np.abs(phi).max()
+    rng = np.random.default_rng(7)
+    Q = np.linalg.qr(rng.standard_normal((24, 24)))[0]
+    phiQ, _, _ = ol.lowdin(Q @ p.chi, p.w)
+    cond = lam.max() / lam.min()
+    assert np.abs(phiQ - Q @ phi).max() < 100 * np.finfo(float).eps * cond * np.abs(phi).max()
