@@ -231,7 +231,8 @@ xtc_status xtc_contract_1body_0body(const xtc_problem *pb, const double *K,
  * two accumulators M^a, M^b get separate, non-symmetric adjoints.
  * The K recompute follows prec (reduced forms keep the occupied block FP64);
  * the adjoint GEMMs and the coefficient contraction are FP64.
- * Errors: XTC_E_UNSUPPORTED for a Pade Jastrow or nocc > 24. */
+ * Errors: XTC_E_UNSUPPORTED for a Pade Jastrow.  The occupied set has the
+ * forward's limits (nocc <= 128, nocc * N <= 5088). */
 xtc_status xtc_backward(const xtc_problem *pb, const xtc_jastrow *jas, int32_t prec,
                         const double *gV2, const double *gh1, double gE0, double *gcoef,
                         void *ws, size_t ws_bytes, void *stream);
@@ -246,7 +247,11 @@ xtc_status xtc_backward(const xtc_problem *pb, const xtc_jastrow *jas, int32_t p
  * chi, phi: device [N][Ng]; w: device [Ng]; lambda: device [N] (eigenvalues
  * of S, unordered) or NULL.  Workspace of xtc_lowdin_workspace_size(N, Ng)
  * bytes, 256-byte aligned; no state is kept in it after the call.
- * 1 <= N <= 256 and Ng >= 1 (XTC_E_ARG), Ng <= 2^28 (XTC_E_UNSUPPORTED). */
+ * 1 <= N <= 256 and Ng >= 1 (XTC_E_ARG), Ng <= 2^28 (XTC_E_UNSUPPORTED).
+ * Unlike the other calls it synchronises `stream` once, after the eigensolver,
+ * to check it: XTC_E_ARG if the Jacobi sweeps did not converge or S is not
+ * positive definite (smallest eigenvalue <= 0 or NaN); phi and lambda are not
+ * written then. */
 size_t xtc_lowdin_workspace_size(int32_t N, int32_t Ng);
 xtc_status xtc_lowdin(int32_t N, int32_t Ng, const double *chi, const double *w, double *phi,
                       double *lambda, void *ws, size_t ws_bytes, void *stream);

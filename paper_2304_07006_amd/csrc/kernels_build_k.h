@@ -99,10 +99,12 @@ __global__ __launch_bounds__(256) void k_build_K_f64(const d4* __restrict__ pos,
 // rho_occ[g'][ldO] of the occupied pairs, one segment [blockIdx.y * seg_len,
 // ...) of the sum over g' per grid.y, written to part[seg][x][r][ldO].
 // Workgroup: 64 rows x 16 NBLK columns; each wave owns 16 rows and NBLK
-// 16-column blocks of all 3 components.  The host picks NBLK to minimise the
-// column padding (136 occupied pairs: 2 tiles of 80 columns).
+// 16-column blocks of all 3 components, so each FP64 d^x value a lane
+// generates feeds 3 NBLK MFMAs.  From 8 blocks on the 24 NBLK accumulator
+// registers per block column leave room for two waves per SIMD only (the
+// second wave hides the operand loads of the first).  The host picks NBLK.
 template <int KIND, int NBLK>
-__global__ __launch_bounds__(256) void k_build_K_occ(const d4* __restrict__ pos, const double* __restrict__ rho_occ,
+__global__ __launch_bounds__(256, NBLK >= 8 ? 2 : 1) void k_build_K_occ(const d4* __restrict__ pos, const double* __restrict__ rho_occ,
                                                      int ldO, int ngp, int g0, int rows, int n_rt, JasDev J,
                                                      double* __restrict__ part, int seg_len) {
     const int lane = threadIdx.x & 63;

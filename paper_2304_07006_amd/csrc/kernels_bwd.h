@@ -32,7 +32,9 @@
 
 namespace xtc {
 
-constexpr int kMaxOccAdj = 24;   // occupied orbitals supported by the adjoint
+// occupied orbitals whose T columns one thread of k_adj_T keeps in registers
+// at a time (larger sets are taken in groups of this many)
+constexpr int kAdjOccGroup = 24;
 
 // ---------------------------------------------------------------- seeds --
 // Effective seed Gt[a,b,c,d] (see the header comment); occw[p] = n_p, 0 for
@@ -267,11 +269,14 @@ __global__ __launch_bounds__(256) void k_adj_T(const double* __restrict__ rho_ro
                 Wbar[(size_t)g * 3 + x] = accumulate ? Wbar[(size_t)g * 3 + x] + v : v;
             }
         }
-        // T rows: one thread per r, all occupied columns in registers
-        for (int r = threadIdx.x; r < N; r += blockDim.x) {
-            double t0[kMaxOccAdj], t1[kMaxOccAdj], t2[kMaxOccAdj];
+        // T rows: one thread per (r, group of kAdjOccGroup occupied columns),
+        // the group's columns in registers
+        const int ngrp = (n + kAdjOccGroup - 1) / kAdjOccGroup;
+        for (int rq = threadIdx.x; rq < N * ngrp; rq += blockDim.x) {
+            const int r = rq % N, k0 = (rq / N) * kAdjOccGroup;
+            double t0[kAdjOccGroup], t1[kAdjOccGroup], t2[kAdjOccGroup];
 #pragma unroll
-            for (int kk = 0; kk < kMaxOccAdj; ++kk) t0[kk] = t1[kk] = t2[kk] = 0.0;
+            for (int kk = 0; kk < kAdjOccGroup; ++kk) t0[kk] = t1[kk] = t2[kk] = 0.0;
             const double* bx = Y + 4 * ystride + (size_t)g * ldP;
             const double* by = Y + 5 * ystride + (size_t)g * ldP;
             const double* bz = Y + 6 * ystride + (size_t)g * ldP;
@@ -280,9 +285,9 @@ __global__ __launch_bounds__(256) void k_adj_T(const double* __restrict__ rho_ro
                 const double h = r == s ? 1.0 : 0.5;
                 const double a = h * ag[R], b0 = h * bx[R], b1 = h * by[R], b2 = h * bz[R];
 #pragma unroll
-                for (int kk = 0; kk < kMaxOccAdj; ++kk) {
-                    if (kk < n) {
-                        const d4 e = locc[kk * N + s];      // (rho_sk, K_sk)
+                for (int kk = 0; kk < kAdjOccGroup; ++kk) {
+                    if (k0 + kk < n) {
+                        const d4 e = locc[(k0 + kk) * N + s];      // (rho_sk, K_sk)
                         t0[kk] = fma(a, e.y, fma(b0, e.x, t0[kk]));
                         t1[kk] = fma(a, e.z, fma(b1, e.x, t1[kk]));
                         t2[kk] = fma(a, e.w, fma(b2, e.x, t2[kk]));
@@ -291,10 +296,10 @@ __global__ __launch_bounds__(256) void k_adj_T(const double* __restrict__ rho_ro
             }
             double* tg = T + (size_t)g * 3 * N * n;
 #pragma unroll
-            for (int kk = 0; kk < kMaxOccAdj; ++kk) {
-                if (kk < n) {
-                    const double m2n = -2.0 * occ.w[kk];
-                    double* t = tg + r * n + kk;
+            for (int kk = 0; kk < kAdjOccGroup; ++kk) {
+                if (k0 + kk < n) {
+                    const double m2n = -2.0 * occ.w[k0 + kk];
+                    double* t = tg + r * n + k0 + kk;
                     t[(size_t)0 * N * n] = (accumulate ? t[(size_t)0 * N * n] : 0.0) + m2n * t0[kk];
                     t[(size_t)1 * N * n] = (accumulate ? t[(size_t)1 * N * n] : 0.0) + m2n * t1[kk];
                     t[(size_t)2 * N * n] = (accumulate ? t[(size_t)2 * N * n] : 0.0) + m2n * t2[kk];

@@ -194,6 +194,20 @@ __global__ __launch_bounds__(256) void k_apply_X(const double* __restrict__ X, c
     phi[(size_t)i * Ng + g] = s;
 }
 
+// Convergence record of the Jacobi solve: out[0] = sweeps taken, out[1] = the
+// smallest eigenvalue (NaN if any is NaN).
+__global__ void k_lowdin_status(const double* __restrict__ S, int N, const int* __restrict__ sweeps,
+                                double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double m = S[0];
+    for (int i = 1; i < N; ++i) {
+        const double v = S[(size_t)i * N + i];
+        m = (v < m || v != v) ? v : m;
+    }
+    out[0] = (double)*sweeps;
+    out[1] = m;
+}
+
 __global__ void k_diag_copy(const double* __restrict__ S, int N, double* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < N) out[i] = S[(size_t)i * N + i];

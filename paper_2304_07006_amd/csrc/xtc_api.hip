@@ -117,15 +117,14 @@ int form_of(int prec) {
 }
 
 
-// 16-column blocks per wave of the FP64 occupied-block kernel, in [1, 7]
-// (8 needs more than 256 registers):
+// 16-column blocks per wave of the FP64 occupied-block kernel, in [1, 9]:
 // the count minimising padded columns x (1 + 1/(2 nb)), i.e. the MFMA work
 // plus the FP64 generation of the d tile, which each wave repeats for its
-// nb blocks (measured at 136 pairs: 3 blocks < 5 < 4 < 6 in time).
+// nb blocks.
 int occ_blocks(int nOP) {
     int best = 1;
     double best_cost = 1e300;
-    for (int nb = 1; nb <= 7; ++nb) {
+    for (int nb = 1; nb <= 9; ++nb) {
         const double cost = (double)align_up((size_t)nOP, (size_t)16 * nb) * (1.0 + 0.5 / nb);
         if (cost < best_cost) {
             best = nb;
@@ -456,7 +455,9 @@ int launch_build_occ(const Layout& L, int g0, int rows, int n_rt, const JasDev& 
         case 4: return launch_build_occ_nb<KIND, 4>(L, g0, rows, n_rt, J, ws, st);
         case 5: return launch_build_occ_nb<KIND, 5>(L, g0, rows, n_rt, J, ws, st);
         case 6: return launch_build_occ_nb<KIND, 6>(L, g0, rows, n_rt, J, ws, st);
-        default: return launch_build_occ_nb<KIND, 7>(L, g0, rows, n_rt, J, ws, st);
+        case 7: return launch_build_occ_nb<KIND, 7>(L, g0, rows, n_rt, J, ws, st);
+        case 8: return launch_build_occ_nb<KIND, 8>(L, g0, rows, n_rt, J, ws, st);
+        default: return launch_build_occ_nb<KIND, 9>(L, g0, rows, n_rt, J, ws, st);
     }
 }
 
@@ -680,10 +681,16 @@ xtc_status xtc_prepare(const xtc_problem* pb, int32_t prec, int32_t chunk_rows, 
                                  (size_t)L.ngp * L.ldP, st)) != XTC_OK)
             return s;
     }
-    // zero the accumulators and the chunk buffers (padding columns of D stay 0)
-    if ((s = fill(at<double>(ws, L.M), (size_t)L.ldP * L.ldP, st)) != XTC_OK) return s;
-    if ((s = fill(at<double>(ws, L.h1acc), (size_t)L.ldP, st)) != XTC_OK) return s;
-    if ((s = fill(at<double>(ws, L.D), (size_t)4 * L.cap * L.ldP, st)) != XTC_OK) return s;
+    // zero the accumulators of every spin channel and the chunk buffers of the
+    // intermediates (their padding columns are never written afterwards and
+    // must read as 0: the adjoint sums over all ldP columns of D)
+    if ((s = fill(at<double>(ws, L.M), (size_t)L.nspin * L.ldP * L.ldP, st)) != XTC_OK) return s;
+    if ((s = fill(at<double>(ws, L.h1acc), (size_t)L.nspin * L.ldP, st)) != XTC_OK) return s;
+    if ((s = fill(at<double>(ws, L.D), (size_t)L.nspin * 4 * L.cap * L.ldP, st)) != XTC_OK) return s;
+    if (L.tc2) {
+        if ((s = fill(at<double>(ws, L.Atc), (size_t)L.ldP * L.ldP, st)) != XTC_OK) return s;
+        if ((s = fill(at<double>(ws, L.Btc), (size_t)L.ldN * L.ldP, st)) != XTC_OK) return s;
+    }
     return XTC_OK;
 }
 
@@ -780,6 +787,14 @@ xtc_status xtc_contract_1body_0body(const xtc_problem* pb, const double* K, int3
     int nsplit_e = std::max(1, std::min(kESplitMax, 1024 / (nbk * nbk)));
     nsplit_e = std::min(nsplit_e, rows);
     const size_t lds = (size_t)2 * L.nocc * kEBlk * sizeof(double);
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_onebody_E,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(XTC_E_HIP, "onebody_E LDS attribute: %s", hipGetErrorString(e));
+        }
+    }
     const double* S = at<double>(ws, L.S);
     const size_t sstride = (size_t)L.cap * 8;
     // per spin channel (T1 and E are scratch of one channel at a time)
@@ -818,7 +833,6 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
     if (!(prec & XTC_WITH_BACKWARD)) return fail(XTC_E_ARG, "prec must carry XTC_WITH_BACKWARD");
     if (!gcoef) return fail(XTC_E_ARG, "gcoef is NULL");
     if (!std::isfinite(gE0)) return fail(XTC_E_ARG, "gE0 not finite");
-    if (pb->nocc > kMaxOccAdj) return fail(XTC_E_UNSUPPORTED, "the adjoint supports nocc <= %d", kMaxOccAdj);
     Layout L = make_layout(pb, prec);
     place_chunk(L, ws_bytes);
     if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
@@ -985,7 +999,7 @@ constexpr int kLowdinSeg = 4096;
 constexpr int kJacobiMaxSweeps = 40;
 struct LowdinLayout {
     int ldS, nseg;
-    size_t part, S, U, X, sweeps, total;
+    size_t part, S, U, X, sweeps, status, total;
 };
 LowdinLayout lowdin_layout(int N, int Ng) {
     LowdinLayout L{};
@@ -997,10 +1011,23 @@ LowdinLayout lowdin_layout(int N, int Ng) {
     L.U = off;      off = align_up(off + (size_t)N * N * sizeof(double), kAlign);
     L.X = off;      off = align_up(off + (size_t)N * N * sizeof(double), kAlign);
     L.sweeps = off; off = align_up(off + sizeof(int), kAlign);
+    L.status = off; off = align_up(off + 2 * sizeof(double), kAlign);
     L.total = off;
     return L;
 }
+
+xtc_status check_lowdin_args(int N, int Ng, const double* chi, const double* w, const double* phi) {
+    if (N < 1 || N > kMaxN || Ng < 1) return fail(XTC_E_ARG, "N=%d or Ng=%d out of range", N, Ng);
+    if (Ng > kMaxNg) return fail(XTC_E_UNSUPPORTED, "Ng=%d above %d", Ng, kMaxNg);
+    if (!chi || !w || !phi) return fail(XTC_E_ARG, "NULL array");
+    return XTC_OK;
+}
+
+xtc_status run_lowdin(const LowdinLayout& L, int N, int Ng, const double* chi, const double* w, double* phi,
+                      double* lambda, void* ws, hipStream_t st);
+
 }  // namespace
+
 
 xtc_status xtc_tc_2body(const xtc_problem* pb, const xtc_jastrow* jas, const double* dphi, const double* K,
                         int32_t g0, int32_t g1, int32_t prec, int32_t flags, double* K2, void* ws, size_t ws_bytes,
@@ -1149,14 +1176,20 @@ size_t xtc_lowdin_workspace_size(int32_t N, int32_t Ng) {
 
 xtc_status xtc_lowdin(int32_t N, int32_t Ng, const double* chi, const double* w, double* phi, double* lambda,
                       void* ws, size_t ws_bytes, void* stream) {
-    if (N < 1 || N > kMaxN || Ng < 1) return fail(XTC_E_ARG, "N=%d or Ng=%d out of range", N, Ng);
-    if (Ng > kMaxNg) return fail(XTC_E_UNSUPPORTED, "Ng=%d above %d", Ng, kMaxNg);
-    if (!chi || !w || !phi) return fail(XTC_E_ARG, "NULL array");
+    xtc_status s;
+    if ((s = check_lowdin_args(N, Ng, chi, w, phi)) != XTC_OK) return s;
     if (!ws) return fail(XTC_E_WORKSPACE, "workspace is NULL");
     if ((uintptr_t)ws % kAlign) return fail(XTC_E_WORKSPACE, "workspace not 256-byte aligned");
     const LowdinLayout L = lowdin_layout(N, Ng);
     if (ws_bytes < L.total) return fail(XTC_E_WORKSPACE, "workspace of %zu bytes < %zu", ws_bytes, L.total);
-    hipStream_t st = (hipStream_t)stream;
+    return run_lowdin(L, N, Ng, chi, w, phi, lambda, ws, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+xtc_status run_lowdin(const LowdinLayout& L, int N, int Ng, const double* chi, const double* w, double* phi,
+                      double* lambda, void* ws, hipStream_t st) {
     xtc_status s;
     const int n_t = L.ldS / 64;
     hipLaunchKernelGGL(k_syrk_w_part, dim3(n_t * n_t, L.nseg), dim3(256), 0, st, chi, w, N, Ng, L.ldS, n_t,
@@ -1169,6 +1202,20 @@ xtc_status xtc_lowdin(int32_t N, int32_t Ng, const double* chi, const double* w,
     hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(kJacobiThreads), 0, st, at<double>(ws, L.S), at<double>(ws, L.U), N,
                        kJacobiMaxSweeps, at<int>(ws, L.sweeps));
     if ((s = launched("jacobi")) != XTC_OK) return s;
+    // convergence and positive definiteness are checked before anything is
+    // written to phi or lambda (one synchronisation of the stream)
+    hipLaunchKernelGGL(k_lowdin_status, dim3(1), dim3(64), 0, st, at<double>(ws, L.S), N, at<int>(ws, L.sweeps),
+                       at<double>(ws, L.status));
+    if ((s = launched("lowdin_status")) != XTC_OK) return s;
+    double stat[2] = {0.0, 0.0};
+    hipError_t e = hipMemcpyAsync(stat, at<double>(ws, L.status), sizeof stat, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(XTC_E_HIP, "lowdin status read-back: %s", hipGetErrorString(e));
+    if (stat[0] >= kJacobiMaxSweeps)
+        return fail(XTC_E_ARG, "Jacobi eigensolver of the grid overlap did not converge in %d sweeps",
+                    kJacobiMaxSweeps);
+    if (!(stat[1] > 0.0))
+        return fail(XTC_E_ARG, "grid overlap matrix is not positive definite (smallest eigenvalue %g)", stat[1]);
     hipLaunchKernelGGL(k_inv_sqrt, dim3((NN + 255) / 256), dim3(256), 0, st, at<double>(ws, L.S), at<double>(ws, L.U),
                        N, at<double>(ws, L.X));
     if ((s = launched("inv_sqrt")) != XTC_OK) return s;
@@ -1181,5 +1228,4 @@ xtc_status xtc_lowdin(int32_t N, int32_t Ng, const double* chi, const double* w,
     }
     return XTC_OK;
 }
-
-}  // extern "C"
+}  // namespace

@@ -198,11 +198,6 @@ def test_backward_validation(lib):
     st = lib.xtc_backward(ctypes.byref(c), ctypes.byref(j), xtc.XTC_WITH_BACKWARD | 0x100, None, None, 1.0,
                           ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000), n, None)
     assert st == xtc.XTC_E_ARG                                         # unknown prec bits
-    c25, keep25 = _problem(N=32, occ=tuple(range(25)))
-    n25 = lib.xtc_workspace_size(ctypes.byref(c25), xtc.XTC_WITH_BACKWARD, 50)
-    st = lib.xtc_backward(ctypes.byref(c25), ctypes.byref(j), xtc.XTC_WITH_BACKWARD, None, None, 1.0,
-                          ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000), n25, None)
-    assert st == xtc.XTC_E_UNSUPPORTED and "24" in xtc.last_error()   # more occupied than the adjoint holds
 
 
 def test_reduced_occ_flag_only_for_build_K(lib):

@@ -68,12 +68,13 @@ def test_gradient_euler_and_fd(torch_cuda):
         assert abs(fd - g[k]) < 1e-8 * max(1.0, abs(g[k])), (k, fd, g[k])
 
 
-def test_gradient_at_the_largest_occupied_set(torch_cuda):
-    """nocc = 24, the most the adjoint's local kernels hold in registers:
-    Euler identity and GPU central differences (N=32, ragged chunks)."""
-    occ = inputs.random_occ(32, 24, seed=9)
-    p, coef, D, G = _case(32, 24, 900, 4, 37, occ=occ)
-    _note("case: backward N=32 n=24 (largest supported) chunk=320")
+def test_gradient_with_more_occupied_than_one_register_group(torch_cuda):
+    """nocc = 32: the adjoint's local kernel takes the occupied columns in two
+    groups (24 + 8): Euler identity and GPU central differences (N=40,
+    ragged chunks)."""
+    occ = inputs.random_occ(40, 32, seed=9)
+    p, coef, D, G = _case(40, 32, 900, 5, 37, occ=occ)
+    _note("case: backward N=40 n=32 chunk=320")
     g = _gpu_grad(torch_cuda, p, coef, D, G, chunk_rows=320)
     L = _gpu_loss(torch_cuda, p, coef, D, G)
     assert abs(np.dot(coef, g) - 2 * L) < 1e-9 * max(1.0, abs(L))
@@ -83,6 +84,21 @@ def test_gradient_at_the_largest_occupied_set(torch_cuda):
         e[k] = h
         fd = (_gpu_loss(torch_cuda, p, coef + e, D, G) - _gpu_loss(torch_cuda, p, coef - e, D, G)) / (2 * h)
         assert abs(fd - g[k]) < 1e-8 * max(1.0, abs(g[k])), (k, fd, g[k])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_gradient_matches_oracle_with_32_occupied(torch_cuda, prec):
+    """nocc = 32 against the oracle's exact gradient (4 coefficients, N=40): FP64
+    1e-10 relative, split BF16 x3 1e-5 of max|g|."""
+    from oracle import gradient as og
+    occ = inputs.random_occ(40, 32, seed=10)
+    p, coef, D, G = _case(40, 32, 500, 5, 38, occ=occ, ncoef=4)
+    _note(f"case: backward N=40 n=32 Ng=500 chunk=256 {prec} vs oracle")
+    go = og.exact_gradient(p.xyz, p.w, p.phi, p.occ, coef, D, G)
+    gg = _gpu_grad(torch_cuda, p, coef, D, G, prec=prec, chunk_rows=256)
+    scale = np.abs(go).max()
+    _note(f"  max |dg| {np.abs(gg - go).max():.3e}  scale {scale:.3e}")
+    assert np.abs(gg - go).max() < (1e-10 * max(1.0, scale) if prec == "fp64" else 1e-5 * scale)
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16x6", "fp32"])
