@@ -17,6 +17,10 @@ of V2 and h1 and the exact E0.
 """
 from __future__ import annotations
 
+import os
+from collections import deque
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 from .jastrow import grad1
@@ -30,6 +34,45 @@ def grid_K(xyz, w, phi, jas, rows):
     rho_j = ((phi * w)[:, None, :] * phi[None, :, :]).reshape(N * N, -1)   # [rs][j]
     K = np.einsum("xij,aj->xia", d, rho_j, optimize=True)
     return K.reshape(3, -1, N, N)
+
+
+def _threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def grid_K_blocks(xyz, w, phi, jas, block):
+    """(rows, V) for the successive row blocks [i0, i0 + block) of the grid, V
+    as in grid_K.  Only the evaluation order differs: the Jastrow gradients of
+    the next blocks are computed ahead on a thread pool (numpy's array loops
+    release the interpreter lock), and the sums over j run in block order.
+    Blocks shrink on large grids so that the gradients in flight stay within
+    a few GB."""
+    N, Ng = phi.shape
+    block = max(16, min(block, (1 << 25) // max(1, Ng)))
+    rho_j = ((phi * w)[:, None, :] * phi[None, :, :]).reshape(N * N, -1)   # [rs][j]
+    starts = iter(range(0, Ng, block))
+    nt = _threads()
+    with ThreadPoolExecutor(nt) as pool:
+        pending = deque()
+
+        def submit():
+            i0 = next(starts, None)
+            if i0 is not None:
+                rows = slice(i0, min(Ng, i0 + block))
+                pending.append((rows, pool.submit(grad1, xyz[rows], xyz, jas)))
+
+        for _ in range(nt + 1):
+            submit()
+        while pending:
+            rows, fut = pending.popleft()
+            d = fut.result()
+            submit()
+            nb = d.shape[1]
+            yield rows, (d.reshape(3 * nb, Ng) @ rho_j.T).reshape(3, nb, N, N)
 
 
 def intermediates(rho, K, gamma):
@@ -57,9 +100,7 @@ def closed_shell(xyz, w, phi, gamma, jas, block=512, return_f=False):
     N, Ng = phi.shape
     gamma = _as_gamma(gamma, N)
     f = np.zeros((N * N, N * N))
-    for i0 in range(0, Ng, block):
-        rows = slice(i0, min(Ng, i0 + block))
-        K = grid_K(xyz, w, phi, jas, rows)
+    for rows, K in grid_K_blocks(xyz, w, phi, jas, block):
         rho = w[rows, None, None] * phi[:, rows].T[:, :, None] * phi[:, rows].T[:, None, :]
         A, B = intermediates(rho, K, gamma)
         nb = rho.shape[0]
@@ -106,9 +147,7 @@ def open_shell(xyz, w, phi, gamma_a, gamma_b, jas, block=512):
     gs = (ga, gb)
     gtot = ga + gb
     f = [np.zeros((N * N, N * N)), np.zeros((N * N, N * N))]
-    for i0 in range(0, Ng, block):
-        rows = slice(i0, min(Ng, i0 + block))
-        K = grid_K(xyz, w, phi, jas, rows)
+    for rows, K in grid_K_blocks(xyz, w, phi, jas, block):
         rho = w[rows, None, None] * phi[:, rows].T[:, :, None] * phi[:, rows].T[:, None, :]
         nb = rho.shape[0]
         for t in range(2):

@@ -46,12 +46,14 @@ def grad1(xa: np.ndarray, xb: np.ndarray, jas) -> np.ndarray:
 
     ``jas`` has attributes kind, b, coef.  Zero where r_a == r_b exactly.
     """
-    d = xa[:, None, :] - xb[None, :, :]            # [na][nb][3]
-    r = np.sqrt(np.sum(d * d, axis=2))
+    d = np.empty((3, len(xa), len(xb)))            # [3][na][nb], C order
+    np.subtract(np.ascontiguousarray(xa.T)[:, :, None], np.ascontiguousarray(xb.T)[:, None, :], out=d)
+    r = np.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])
     up = du_dr(r, jas.kind, jas.b, jas.coef)
     with np.errstate(divide="ignore", invalid="ignore"):
         f = np.where(r > 0.0, up / np.where(r > 0.0, r, 1.0), 0.0)
-    return np.moveaxis(d * f[:, :, None], 2, 0)
+    d *= f
+    return d
 
 
 def d2u_dr2(r, kind: str, b: float = 1.0, coef=()):

@@ -208,7 +208,9 @@ def basis_gradients(xyz: np.ndarray, centres: np.ndarray, shells) -> np.ndarray:
 def orbital_gradients(p: "Problem") -> np.ndarray:
     """grad phi on the grid, [3][N][Ng]: the Loewdin transform of the analytic
     basis gradients (phi = X chi, so grad phi = X grad chi)."""
-    X = lowdin_matrix(p.chi, p.w)
+    X = p.meta.get("lowdin")
+    if X is None:
+        X = lowdin_matrix(p.chi, p.w)
     dchi = basis_gradients(p.xyz, p.centres, p.meta["shells"])
     return np.ascontiguousarray(np.einsum("ij,xjg->xig", X, dchi))
 
@@ -227,7 +229,12 @@ def make_jastrow(kind: str, aux_seed: int) -> Jastrow:
 
 def make_problem(N: int, nocc: int, Ng: int, n_centres: int, layout: str = "chain",
                  jastrow_kind: str = "pade", seed: int = 0, aux_seed: int | None = None,
-                 occ: np.ndarray | None = None) -> Problem:
+                 occ: np.ndarray | None = None, lowdin: np.ndarray | None = None) -> Problem:
+    """One seeded problem.  ``lowdin``: a stored orthonormalisation matrix X
+    (phi = X chi) to use instead of computing S^{-1/2} here.  S^{-1/2} is
+    ill-conditioned (cond(S) reaches 2e8 at N=128), so eigen-solvers on
+    different hosts give orbitals that differ by about cond(S) x 1e-16; a
+    stored X reproduces stored oracle values to about 1e-12 on any host."""
     if N % n_centres != 0:
         raise ValueError("N must be a multiple of the number of centres")
     if not (1 <= nocc <= N):
@@ -238,22 +245,38 @@ def make_problem(N: int, nocc: int, Ng: int, n_centres: int, layout: str = "chai
         raise ValueError("layout 'pair' has exactly two centres")
     xyz, w = sample_grid(centres, Ng, rng)
     chi, shells = basis_values(xyz, centres, N // n_centres, rng)
-    phi = orthonormalise_inputs(chi, w)
+    if lowdin is None:
+        phi = orthonormalise_inputs(chi, w)
+    else:
+        if np.shape(lowdin) != (N, N):
+            raise ValueError(f"lowdin matrix must be [{N}][{N}]")
+        phi = np.ascontiguousarray(np.asarray(lowdin, dtype=np.float64) @ chi)
     if occ is None:
         occ = np.arange(nocc, dtype=np.int32)
     occ = np.asarray(occ, dtype=np.int32)
     jas = make_jastrow(jastrow_kind, 2000 + seed if aux_seed is None else aux_seed)
     return Problem(xyz=xyz, w=w, chi=chi, phi=phi, occ=occ, centres=centres, jastrow=jas,
-                   meta=dict(seed=seed, shells=shells, layout=layout))
+                   meta=dict(seed=seed, shells=shells, layout=layout, lowdin=lowdin))
 
 
-def make_workload(name: str, Ng: int | None = None) -> Problem:
-    """One of WORKLOADS, optionally on a smaller grid (same generator, same seed)."""
+def make_workload(name: str, Ng: int | None = None, lowdin: np.ndarray | None = None) -> Problem:
+    """One of WORKLOADS, optionally on a smaller grid (same generator, same
+    seed) or with a stored orthonormalisation matrix (see make_problem)."""
     wl = WORKLOADS[name]
     p = make_problem(wl.N, wl.nocc, wl.Ng if Ng is None else Ng, wl.n_centres, wl.layout,
-                     wl.jastrow_kind, wl.seed, wl.aux_seed)
+                     wl.jastrow_kind, wl.seed, wl.aux_seed, lowdin=lowdin)
     p.meta["workload"] = name
     return p
+
+
+def input_fingerprint(p: Problem) -> np.ndarray:
+    """Checksums of the drawn inputs (positions, weights, raw functions), to
+    check that a host regenerates the inputs a stored result was computed
+    from.  Compared to a relative tolerance: the exponentials may differ in
+    the last bit between hosts, which moves these sums by about 1e-16."""
+    u = np.random.default_rng(12345).standard_normal(p.Ng)
+    return np.concatenate([p.xyz.sum(axis=0), [p.w.sum(), (p.w * np.sum(p.xyz ** 2, axis=1)).sum()],
+                           p.chi.sum(axis=1), (p.chi * p.chi * p.w).sum(axis=1), p.chi @ u])
 
 
 def random_occ(N: int, nocc: int, seed: int) -> np.ndarray:
