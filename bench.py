@@ -150,12 +150,97 @@ def apply_density(problem, spec):
     raise SystemExit(f"unknown --density {spec}")
 
 
-def run_gpu(problem, prec, steps, warmup, chunk):
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def load_golden(workload):
+    """The oracle's outputs on an orbital subset of the workload (written by
+    tests/golden/make_subset_golden.py), or None."""
+    import numpy as np
+    path = os.path.join(GOLDEN_DIR, f"{workload}_subset.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path, allow_pickle=False)
+    return {k: g[k] for k in g.files}
+
+
+def golden_inputs_match(problem, golden, rtol=1e-12):
+    import numpy as np
+    from paper_2304_07006_amd import inputs
+    fp = inputs.input_fingerprint(problem)
+    return bool(np.all(np.abs(fp - golden["fingerprint"]) <= rtol * np.abs(golden["fingerprint"])))
+
+
+def golden_errors(golden, V2, h1, E0):
+    """Max-abs error of device outputs against the stored oracle values on
+    the subset S: V2 over its unique entries, h1 on S x S, E0."""
+    import numpy as np
+    import torch
+    S = golden["S"].astype(np.int64)
+    Sv = torch.as_tensor(S[golden["idx"].astype(np.int64)], device=V2.device)
+    v = V2[Sv[:, 0], Sv[:, 1], Sv[:, 2], Sv[:, 3]].cpu().numpy()
+    s = torch.as_tensor(S, device=h1.device)
+    h = h1[s][:, s].cpu().numpy()
+    return {"V2": float(np.abs(v - golden["V2u"]).max()), "h1": float(np.abs(h - golden["h1"]).max()),
+            "E0": abs(float(E0.reshape(-1)[0].item()) - float(golden["E0"][0])),
+            "orbitals": int(len(S))}
+
+
+def short_kernel_name(name):
+    """'void xtc::k_build_K_lp<0, 3, 3>(double const*, ...)' -> 'k_build_K_lp'."""
+    return name.split("(")[0].replace("void ", "").split("::")[-1].split("<")[0].strip()
+
+
+def profile_kernels(fn):
+    """Device time per kernel (short name -> (launches, total seconds)) of
+    the work fn() launches, from the torch profiler's device activity trace."""
+    import torch
+    from torch.profiler import ProfilerActivity, profile
+    with profile(activities=[ProfilerActivity.CUDA]) as prof:
+        fn()
+        torch.cuda.synchronize()
+    out = {}
+    for ev in prof.events():
+        if getattr(ev, "device_type", None) is None or str(ev.device_type) != "DeviceType.CUDA":
+            continue
+        k = short_kernel_name(ev.name)
+        n, t = out.get(k, (0, 0.0))
+        out[k] = (n + 1, t + ev.time_range.elapsed_us() * 1e-6)
+    return out
+
+
+def kernel_rooflines(times, N, nocc, Ng, chunk, prec):
+    """Per-kernel algorithmic rate and fraction of the relevant peak for the
+    contraction kernels of one step (flops per launch: K build 6 rows Ng Npair,
+    FP64 occupied block 6 rows Ng nOP, two-body GEMM 8 rows Npair^2)."""
+    P = N * (N + 1) // 2
+    nOP = nocc * (nocc + 1) // 2
+    rows = chunk
+    table = {"k_build_K_lp": (6 * rows * Ng * P, PEAK[prec]), "k_build_K_f64": (6 * rows * Ng * P, PEAK["fp64"]),
+             "k_build_K_occ": (6 * rows * Ng * nOP, PEAK["fp64"]),
+             "k_gemm_tn_lds": (8 * rows * P * P, PEAK[prec]), "k_gemm_tn_lp": (8 * rows * P * P, PEAK[prec]),
+             "k_gemm2b_f64": (8 * rows * P * P, PEAK["fp64"])}
+    out = {}
+    for k, (n, t) in sorted(times.items(), key=lambda kv: -kv[1][1]):
+        e = {"launches": n, "avg_ms": t / n * 1e3, "share_of_step": None}
+        if k in table:
+            f, peak = table[k]
+            e.update(flop_per_launch=f, tflops=f / (t / n) / 1e12, peak_tflops=peak, frac=f / (t / n) / 1e12 / peak)
+        out[k] = e
+    tot = sum(t for _, t in times.values())
+    for k in out:
+        out[k]["share_of_step"] = times[k][1] / tot
+    return out
+
+
+def run_gpu(problem, prec, steps, warmup, chunk, profile=False):
     import torch
     from paper_2304_07006_amd import xtc
     dp = xtc.device_problem(problem.xyz, problem.w, problem.phi, problem.occ,
-                            occ_n=getattr(problem, "occ_n", None))
+                            occ_n=getattr(problem, "occ_n", None), occ_n_beta=getattr(problem, "occ_n_beta", None))
     ps = xtc.Pass(dp, xtc.PRECISIONS[prec], chunk)
+    # the spin-resolved equations write three V2 blocks (aa, ab, bb) and two h1
+    assert tuple(ps.V2.shape[:-4]) == ((3,) if dp.open_shell else ()), ps.V2.shape
     jas = xtc.make_jastrow(problem.jastrow)
     stream = torch.cuda.current_stream()
     kev = []
@@ -186,7 +271,13 @@ def run_gpu(problem, prec, steps, warmup, chunk):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     kt = [(a.elapsed_time(b) * 1e-3, rows) for a, b, rows in kev]
-    return dict(sec=dt, kbuild=kt, outputs=(ps.V2, ps.h1, ps.E0), ws_bytes=ps.ws.numel())
+    times = None
+    if profile:                       # one more step, untimed, under the profiler
+        try:
+            times = profile_kernels(lambda: step(False))
+        except Exception as e:        # the breakdown is optional
+            print(f"[bench] kernel profile unavailable: {e}", file=sys.stderr, flush=True)
+    return dict(sec=dt, kbuild=kt, outputs=(ps.V2, ps.h1, ps.E0), ws_bytes=ps.ws.numel(), kernel_times=times)
 
 
 def probe(problem, prec, chunk):
@@ -232,18 +323,12 @@ def f_backward(N, Ng, nspin=1):
     return 12 * Ng * Ng * P + nspin * 14 * Ng * P * P
 
 
-def run_backward(problem, prec, chunk, aux_seed, steps, warmup):
-    """Forward pass and adjoint (xtc_backward, K recomputed) of the loss
-    L = E0 + <h1, D> + <V2, G>, D symmetric and G 8-fold symmetric, seeded on
-    the device (open shell: one D per spin and one G per block aa, ab, bb).
-    Returns seconds per forward and per backward, the gradient, and the Euler
-    check |c . dL/dc - 2 L| / |2 L| (L is homogeneous of degree 2 in the
-    power-Jastrow coefficients)."""
+def loss_weights_device(N, aux_seed, open_shell=False):
+    """Seeded loss weights on the device: D symmetric [N][N] and G 8-fold
+    symmetric [N]^4 (open shell: [2][N][N] and [3][N]^4, one per spin and
+    per block aa, ab, bb)."""
     import torch
-    from paper_2304_07006_amd import xtc
-    N = problem.N
-    occ_n, occ_nb = getattr(problem, "occ_n", None), getattr(problem, "occ_n_beta", None)
-    nD, nG = (2, 3) if occ_nb is not None else (1, 1)
+    nD, nG = (2, 3) if open_shell else (1, 1)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(aux_seed + 7)
     X = torch.randn((nD, N, N), generator=gen, device="cuda", dtype=torch.float64)
@@ -253,6 +338,26 @@ def run_backward(problem, prec, chunk, aux_seed, steps, warmup):
     G = (0.5 * (G + G.permute(0, 3, 4, 1, 2))).contiguous()
     if nD == 1:
         D, G = D[0].contiguous(), G[0].contiguous()
+    return D, G
+
+
+def loss_value(V2, h1, E0, D, G):
+    """E0 + <h1, D> + <V2, G> (device tensors), on the host."""
+    return E0.reshape(-1)[0].item() + (h1 * D).sum().item() + (V2 * G).sum().item()
+
+
+def run_backward(problem, prec, chunk, aux_seed, steps, warmup, keep=None):
+    """Forward pass and adjoint (xtc_backward, K recomputed) of the loss
+    L = E0 + <h1, D> + <V2, G>, D symmetric and G 8-fold symmetric, seeded on
+    the device (open shell: one D per spin and one G per block aa, ab, bb).
+    Returns seconds per forward and per backward, the gradient, and the Euler
+    check |c . dL/dc - 2 L| / |2 L| (L is homogeneous of degree 2 in the
+    power-Jastrow coefficients).  `keep`: a dict that receives host copies of
+    the forward outputs and the loss."""
+    import torch
+    from paper_2304_07006_amd import xtc
+    occ_n, occ_nb = getattr(problem, "occ_n", None), getattr(problem, "occ_n_beta", None)
+    D, G = loss_weights_device(problem.N, aux_seed, occ_nb is not None)
     coef = [float(c) for c in problem.jastrow.coef]
     jas = xtc.power_jastrow(coef)
     dp = xtc.device_problem(problem.xyz, problem.w, problem.phi, problem.occ, occ_n=occ_n, occ_n_beta=occ_nb)
@@ -271,7 +376,9 @@ def run_backward(problem, prec, chunk, aux_seed, steps, warmup):
     # (at N=160 each holds about half of the device memory)
     ps = xtc.Pass(dp, xtc.PRECISIONS[prec], chunk)
     tf = timed(lambda: ps.run(jas))
-    L = ps.E0[0].item() + (ps.h1 * D).sum().item() + (ps.V2 * G).sum().item()
+    L = loss_value(ps.V2, ps.h1, ps.E0, D, G)
+    if keep is not None:              # host copies of the forward outputs
+        keep.update(V2=ps.V2.cpu().numpy(), h1=ps.h1.cpu().numpy(), E0=float(ps.E0.cpu()[0]), L=L)
     del ps
     torch.cuda.empty_cache()
     pb = xtc.PRECISIONS[prec] | xtc.XTC_WITH_BACKWARD
@@ -316,26 +423,57 @@ def gemm_calibration(reps=10):
     return rows
 
 
-def cpu_baseline(name, budget_rows):
-    """The oracle (Appendix-B equations, numpy FP64) on the same workload's
-    orbitals and generator, on a reduced grid of `budget_rows` points."""
+def host_info():
+    """CPU model, cores this process may use and the BLAS threads numpy runs."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas = sum(int(i.get("num_threads", 0)) for i in threadpool_info() if i.get("user_api") == "blas") or None
+    except Exception:
+        pass
+    return {"cpu_model": model, "cores": len(os.sched_getaffinity(0)), "blas_threads": blas}
+
+
+def cpu_baseline(name, budget_rows, nvirt=8):
+    """The oracle (Appendix-B equations, numpy FP64) on the workload's orbital
+    subset occ + `nvirt` virtual orbitals (exact for that subset) on a
+    `budget_rows`-point grid of the same generator, where, as in the whole
+    workload, the K build dominates the work.  Its rate (algorithmic flops of
+    the subset problem over the wall time) is extrapolated to the whole
+    workload, labelled as such."""
     import numpy as np
     from paper_2304_07006_amd import inputs
     from oracle import factorised
     wl = inputs.WORKLOADS[name]
     p = inputs.make_workload(name, Ng=budget_rows)
+    occ = [int(k) for k in p.occ]
+    rest = np.array([k for k in range(p.N) if k not in set(occ)])
+    virt = np.sort(np.random.default_rng(7).choice(rest, nvirt, replace=False))
+    S = np.array(occ + [int(k) for k in virt])
     t0 = time.perf_counter()
-    factorised.closed_shell(p.xyz, p.w, p.phi, p.occ, p.jastrow)
+    factorised.closed_shell(p.xyz, p.w, p.phi[S], np.arange(len(occ)), p.jastrow)
     dt = time.perf_counter() - t0
-    F = f_alg(wl.N, wl.nocc, budget_rows)
-    cores = len(os.sched_getaffinity(0))
-    return {"value": F / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": f"N={wl.N} n={wl.nocc} on a {budget_rows}-point grid from the same generator "
-                      f"(full orbital set, Appendix-B equations in numpy FP64); {dt:.1f} s wall; "
-                      f"rate = F_alg(sample)/time",
-            "seconds": dt,
-            # F_alg of the whole workload at the sample's rate (extrapolated, not run)
-            "full_workload_seconds_extrapolated": f_alg(wl.N, wl.nocc, wl.Ng) / (F / dt)}
+    F = f_alg(len(S), wl.nocc, budget_rows)
+    info = host_info()
+    rate = F / dt
+    return {"value": rate / 1e9, "unit": "GFLOP/s", "cores": info["cores"], "kind": "oracle",
+            "sample": f"Appendix-B oracle (numpy FP64) on orbitals occ+{nvirt} virtual ({len(S)} of {wl.N}; "
+                      f"exact for that subset) of {name}'s generator on a {budget_rows}-point grid; "
+                      f"{dt:.1f} s wall; rate = F_alg(N={len(S)}, n={wl.nocc}, Ng={budget_rows}) / time",
+            "seconds": dt, "cpu_model": info["cpu_model"], "blas_threads": info["blas_threads"],
+            "oracle_threads": min(16, info["cores"]),
+            "k_build_share_of_sample_flops": f_kbuild(len(S), budget_rows, budget_rows) / F,
+            # the whole workload's F_alg at the sample's rate (extrapolated, not run)
+            "full_workload_seconds_extrapolated": f_alg(wl.N, wl.nocc, wl.Ng) / rate}
 
 
 def main():
@@ -348,10 +486,10 @@ def main():
     ap.add_argument("--compare", default="fp64", help="form run once beside the headline one ('none' to skip)")
     ap.add_argument("--chunk", type=int, default=None,
                     help="grid rows per chunk (default: Ng/10 for FP64, Ng/20 for the reduced forms: equal launches)")
-    ap.add_argument("--cpu-rows", type=int, default=400,
-                    help="grid points of the CPU oracle sample, about 10-15 s on the host (0: skip)")
+    ap.add_argument("--cpu-rows", type=int, default=30000,
+                    help="grid points of the CPU oracle sample (orbital subset), 10-30 s on the host (0: skip)")
     ap.add_argument("--density", default="closed",
-                    help="reference density: closed | sa:ND,NS | natural:NACT (see apply_density)")
+                    help="reference density: closed | sa:ND,NS | open:ND,NS | natural:NACT (see apply_density)")
     ap.add_argument("--tc2", action="store_true",
                     help="time the two-body TC integrals (K build + xtc_tc_2body) instead of the xTC folding")
     ap.add_argument("--backward", action="store_true",
@@ -387,7 +525,12 @@ def main():
     if args.backward and args.workload == ap.get_default("workload"):
         args.workload = "N96-occ12-Ng100k"
     wl = inputs.WORKLOADS[args.workload]
-    problem = inputs.make_workload(args.workload)
+    golden = load_golden(args.workload) if args.density == "closed" else None
+    problem = inputs.make_workload(args.workload, lowdin=golden["X"] if golden else None)
+    if golden and not golden_inputs_match(problem, golden):
+        print("[bench] regenerated inputs differ from the stored oracle values' inputs: no oracle errors",
+              file=sys.stderr, flush=True)
+        golden = None
     density = apply_density(problem, args.density)
     nref = len(problem.occ)
     chunk = args.chunk or default_chunk(wl.Ng, args.prec)
@@ -432,21 +575,30 @@ def main():
         return
     print(f"[bench] {args.workload} prec={args.prec} chunk={chunk} warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
-    r = run_gpu(problem, args.prec, args.steps, args.warmup, chunk)
+    r = run_gpu(problem, args.prec, args.steps, args.warmup, chunk, profile=True)
     nspin = 2 if getattr(problem, "occ_n_beta", None) is not None else 1
     F = f_alg(wl.N, nref, wl.Ng, nspin)
     forms = {args.prec: {"s_per_step": r["sec"], "gflops": F / r["sec"] / 1e9}}
+    if golden:
+        forms[args.prec]["max_abs_err_vs_oracle"] = golden_errors(golden, *r["outputs"])
+        print(f"[bench] {args.prec} vs oracle subset: {forms[args.prec]['max_abs_err_vs_oracle']}",
+              file=sys.stderr, flush=True)
     if args.compare != "none" and args.compare != args.prec:
         cchunk = default_chunk(wl.Ng, args.compare)
         print(f"[bench] comparison form {args.compare}: one step", file=sys.stderr, flush=True)
         V2h, h1h, E0h = (t.clone() for t in r["outputs"])
         del r["outputs"]
         torch.cuda.empty_cache()
-        rc = run_gpu(problem, args.compare, 1, 0, cchunk)
+        rc = run_gpu(problem, args.compare, 1, 0, cchunk, profile=args.compare == "fp64")
+        if rc.get("kernel_times"):
+            forms[args.compare + "_kernels"] = kernel_rooflines(rc["kernel_times"], wl.N, nref, wl.Ng, cchunk,
+                                                                args.compare)
         V2c, h1c, E0c = rc["outputs"]
         err = {"V2": (V2h - V2c).abs().max().item(), "h1": (h1h - h1c).abs().max().item(),
                "E0": (E0h - E0c).abs().max().item()}
         forms[args.compare] = {"s_per_step": rc["sec"], "gflops": F / rc["sec"] / 1e9}
+        if golden:
+            forms[args.compare]["max_abs_err_vs_oracle"] = golden_errors(golden, V2c, h1c, E0c)
         forms[args.prec]["max_abs_err_vs_" + args.compare] = err
         forms[args.prec]["speedup_vs_" + args.compare] = rc["sec"] / r["sec"]
         print(f"[bench] {args.compare}: {rc['sec']:.3f} s/step; max|err| {err}", file=sys.stderr, flush=True)
@@ -488,6 +640,8 @@ def main():
                      "per_launch_flop": tot_f / nl, "avg_launch_ms": tot_t / nl * 1e3,
                      "executed_mfma_frac": achieved * TERMS[args.prec] / peak},
         "forms": forms,
+        "kernels": (kernel_rooflines(r["kernel_times"], wl.N, nref, wl.Ng, chunk, args.prec)
+                    if r.get("kernel_times") else None),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

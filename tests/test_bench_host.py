@@ -56,3 +56,12 @@ def test_traffic_from_counter_runs(tmp_path):
     assert abs(per["k_build_K_lp"]["fetch"] - 20e9) < 1 and abs(per["k_reduce_K"]["write"] - 0.5e9) < 1
     assert abs(rec["bytes_per_launch"] - (20e9 + 6e9 + 1e9 + 0.5e9)) < 4
     assert rec["sources"] == bench.kernel_sources_hash()
+
+
+def test_host_info_and_cpu_baseline_fields():
+    info = bench.host_info()
+    assert info["cores"] >= 1 and isinstance(info["cpu_model"], (str, type(None)))
+    cb = bench.cpu_baseline("N128-occ16-Ng150k", 600)
+    assert cb["kind"] == "oracle" and cb["cores"] == info["cores"] and cb["value"] > 0
+    assert "24 of 128" in cb["sample"] and cb["full_workload_seconds_extrapolated"] > cb["seconds"]
+    assert 0.5 < cb["k_build_share_of_sample_flops"] < 1.0

@@ -1,10 +1,15 @@
 """The hot path at the full sizes of the measured workloads, in the launch
 configuration bench.py times (N=128, 16 occupied, Ng=150 000, 20 chunks of
-7500 rows in split BF16 x3, 10 in FP64): sampled K entries against their exact
-grid sums, the antisymmetry of the pair contraction of K, the split-BF16
-and FP32 outputs against the FP64 path to the bars, bitwise symmetry and determinism;
-and the adjoint at N=96, Ng=100 000 (closed and open shell) through the
-Euler identity of the quadratic loss."""
+7500 rows in the reduced forms, 10 in FP64): sampled K entries against their
+exact grid sums, the antisymmetry of the pair contraction of K, every form's
+outputs against the oracle's values on an orbital subset (written by
+tests/golden/make_subset_golden.py, which calls only the oracle) and the
+reduced forms against the FP64 path, bitwise symmetry and determinism; the
+adjoint at N=96, Ng=100 000 (closed and open shell) through the Euler
+identity of the quadratic loss and central differences of the FP64 forward;
+and forward + adjoint at N=160, Ng=250 000 with its peak device memory."""
+import os
+
 import numpy as np
 import pytest
 
@@ -13,6 +18,8 @@ from paper_2304_07006_amd import inputs
 pytestmark = pytest.mark.gpu
 
 WORKLOAD = "N128-occ16-Ng150k"
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{WORKLOAD}_subset.npz")
+BARS = (1e-6, 1e-6, 1e-8)
 
 
 def _note(msg):
@@ -28,8 +35,36 @@ def torch_cuda():
 
 
 @pytest.fixture(scope="module")
-def problem():
-    return inputs.make_workload(WORKLOAD)
+def golden():
+    """The oracle's subset values; the workload regenerated with the stored
+    orthonormalisation matrix must reproduce the stored input fingerprint."""
+    g = np.load(GOLDEN, allow_pickle=False)
+    return {k: g[k] for k in g.files}
+
+
+@pytest.fixture(scope="module")
+def problem(golden):
+    p = inputs.make_workload(WORKLOAD, lowdin=golden["X"])
+    fp = inputs.input_fingerprint(p)
+    dev = np.abs(fp - golden["fingerprint"]) / np.maximum(np.abs(golden["fingerprint"]), 1e-300)
+    assert dev.max() < 1e-12, f"regenerated inputs differ from the stored ones: {dev.max():.2e}"
+    return p
+
+
+def _against_golden(golden, V2, h1, E0, prec):
+    """Max-abs differences of the subset outputs from the stored oracle values
+    (V2 over its unique entries), checked against the bars."""
+    S, idx = golden["S"], golden["idx"].astype(np.int64)
+    Sv = S[idx]
+    eV = float(np.abs(V2[Sv[:, 0], Sv[:, 1], Sv[:, 2], Sv[:, 3]] - golden["V2u"]).max())
+    eh = float(np.abs(h1[np.ix_(S, S)] - golden["h1"]).max())
+    E0o = float(golden["E0"][0])
+    eE = abs(E0 - E0o)
+    _note(f"  {prec} vs oracle on {len(S)} orbitals: |dV2| {eV:.2e} |dh1| {eh:.2e} |dE0| {eE:.2e} (E0 {E0o:.10f})")
+    if prec == "fp64":
+        assert eV < 1e-11 and eh < 1e-11 and eE < max(1e-11, 1e-12 * abs(E0o)), (eV, eh, eE)
+    else:
+        assert eV < BARS[0] and eh < BARS[1] and eE < BARS[2], (prec, eV, eh, eE)
 
 
 def _chunk(prec, Ng):
@@ -122,25 +157,28 @@ def test_full_size_pair_antisymmetry(torch_cuda, problem):
     assert np.all(asym <= 2.0**-15 * bound + 1e-15)
 
 
-def test_full_size_forward_against_fp64(torch_cuda, problem):
-    """Split BF16 x3 at the bench configuration, and the FP32 form in the same
-    chunks, against the FP64 path: the 1e-6 Eh two-body bar (one-body 1e-6,
-    zero-body 1e-8); bitwise symmetry of V2 and h1, bitwise determinism of two
-    split-BF16 runs."""
+def test_full_size_forward_against_oracle_and_fp64(torch_cuda, problem, golden):
+    """Every form at the bench configuration against the oracle's values on
+    the 24-orbital subset (FP64: 1e-11; reduced forms: the 1e-6 Eh two-body,
+    1e-6 one-body and 1e-8 zero-body bars), the reduced forms also against the
+    FP64 path over all N^4 entries; bitwise symmetry of V2 and h1, bitwise
+    determinism of two split-BF16 runs."""
     from paper_2304_07006_amd import xtc
     p = problem
-    _note(f"case: {WORKLOAD} forward bf16x3 (x2) and fp32 vs fp64")
+    _note(f"case: {WORKLOAD} forward bf16x3 (x2), bf16x6, fp32, fp64 vs oracle subset and fp64")
     out = {}
-    for prec, tag in (("bf16x3", "a"), ("bf16x3", "b"), ("fp32", "f"), ("fp64", "r")):
+    for prec, tag in (("bf16x3", "a"), ("bf16x3", "b"), ("bf16x6", "s"), ("fp32", "f"), ("fp64", "r")):
         V2, h1, E0 = xtc.forward(p, prec=prec, chunk_rows=_chunk(prec, p.Ng))
         out[tag] = (V2.cpu().numpy(), h1.cpu().numpy(), float(E0.cpu()[0]))
         del V2, h1, E0
         torch_cuda.cuda.empty_cache()
+        if tag != "b":
+            _against_golden(golden, *out[tag], prec)
     (Va, ha, Ea), (Vb, hb, Eb), (Vr, hr, Er) = out["a"], out["b"], out["r"]
-    for tag in ("a", "f"):
+    for tag, prec in (("a", "bf16x3"), ("s", "bf16x6"), ("f", "fp32")):
         V, h, E = out[tag]
         eV, eh, eE = np.abs(V - Vr).max(), np.abs(h - hr).max(), abs(E - Er)
-        _note(f"  {'bf16x3' if tag == 'a' else 'fp32'}: |dV2| {eV:.2e} |dh1| {eh:.2e} |dE0| {eE:.2e} (E0 = {Er:.10f})")
+        _note(f"  {prec} vs fp64: |dV2| {eV:.2e} |dh1| {eh:.2e} |dE0| {eE:.2e} (E0 = {Er:.10f})")
         assert eV < 1e-6 and eh < 1e-6 and eE < 1e-8, tag
     assert np.array_equal(Va, Vb) and np.array_equal(ha, hb) and Ea == Eb
     for V in (Va, Vr):
@@ -193,3 +231,74 @@ def test_full_size_open_shell_adjoint_euler(torch_cuda):
     tf, tb, g, euler, _ = bench.run_backward(p, "bf16x3", _chunk("bf16x3", p.Ng), wl.aux_seed, 1, 0)
     _note(f"  |c.g - 2L| / |2L| = {euler:.2e}; forward {tf:.2f} s, adjoint {tb:.2f} s")
     assert np.all(np.isfinite(g)) and euler < 1e-5
+
+
+def test_full_size_adjoint_central_differences(torch_cuda):
+    """N=96, Ng=100 000, FP64: the adjoint against central differences of the
+    FP64 forward with step 1e-5 on two coefficients (the loss is quadratic in
+    the coefficients, so the difference quotient is exact up to rounding),
+    1e-8 relative."""
+    import bench
+    from paper_2304_07006_amd import xtc
+    wl = inputs.WORKLOADS["N96-occ12-Ng100k"]
+    p = inputs.make_workload(wl.name)
+    _note("case: N96-occ12-Ng100k adjoint fp64 vs central differences (h = 1e-5, k = 0, 5)")
+    keep = {}
+    _, _, g, euler, _ = bench.run_backward(p, "fp64", _chunk("fp64", p.Ng), wl.aux_seed, 1, 0, keep)
+    D, G = bench.loss_weights_device(p.N, wl.aux_seed)
+    coef = np.array(p.jastrow.coef)
+    h = 1e-5
+
+    def loss(c):
+        jas = inputs.Jastrow("power", coef=tuple(float(x) for x in c))
+        V2, h1, E0 = xtc.forward(p, prec="fp64", chunk_rows=_chunk("fp64", p.Ng), jastrow=jas)
+        L = bench.loss_value(V2, h1, E0, D, G)
+        del V2, h1, E0
+        return L
+
+    _note(f"  L = {keep['L']:.12e}, |c.g - 2L|/|2L| = {euler:.2e}")
+    assert euler < 1e-10
+    for k in (0, 5):
+        e = np.zeros_like(coef)
+        e[k] = h
+        fd = (loss(coef + e) - loss(coef - e)) / (2 * h)
+        rel = abs(fd - g[k]) / max(abs(g[k]), 1e-300)
+        _note(f"  k={k}: adjoint {g[k]:.12e}, central difference {fd:.12e}, relative {rel:.2e}")
+        assert rel < 1e-8, (k, fd, g[k])
+
+
+def test_largest_workload_forward_and_adjoint(torch_cuda):
+    """N=160, 20 occupied, Ng=250 000, split BF16 x3 in 20 chunks (bench.py
+    --backward --workload N160-occ20-Ng250k): forward outputs against the FP64
+    path to the bars, c . dL/dc = 2 L to 1e-5 with K recomputed in the
+    adjoint, and the peak device memory of the split-BF16 forward + adjoint
+    within its stated bound (the larger of the two workspaces plus the
+    outputs, the loss weights and the K chunk, plus 2%)."""
+    import bench
+    from paper_2304_07006_amd import xtc
+    wl = inputs.WORKLOADS["N160-occ20-Ng250k"]
+    p = inputs.make_workload(wl.name)
+    chunk = _chunk("bf16x3", p.Ng)
+    _note(f"case: {wl.name} forward + adjoint bf16x3, chunk={chunk}")
+    torch_cuda.cuda.reset_peak_memory_stats()
+    keep = {}
+    tf, tb, g, euler, peak = bench.run_backward(p, "bf16x3", chunk, wl.aux_seed, 1, 0, keep)
+    dp = xtc.device_problem(p.xyz, p.w, p.phi, p.occ)
+    N, ldP = p.N, xtc.xtc_pair_ld(p.N)
+    ws_f = xtc.xtc_workspace_size(dp, xtc.XTC_BF16X3, chunk)
+    ws_b = xtc.xtc_workspace_size(dp, xtc.XTC_BF16X3 | xtc.XTC_WITH_BACKWARD, chunk)
+    inputs_b = (p.Ng * 4 + N * p.Ng) * 8
+    outs = (2 * N ** 4 + N * N + 1) * 8 + 3 * chunk * ldP * 8     # V2, G (seed), h1, D, E0; K chunk
+    bound = 1.02 * (max(ws_f, ws_b) + outs + inputs_b)
+    _note(f"  forward {tf:.2f} s, adjoint {tb:.2f} s, |c.g - 2L|/|2L| = {euler:.2e}, "
+          f"peak {peak / 1e9:.1f} GB (bound {bound / 1e9:.1f} GB; workspaces {ws_f / 1e9:.1f} / {ws_b / 1e9:.1f} GB)")
+    assert np.all(np.isfinite(g)) and euler < 1e-5
+    assert peak <= bound
+    del dp
+    torch_cuda.cuda.empty_cache()
+    V2r, h1r, E0r = xtc.forward(p, prec="fp64", chunk_rows=_chunk("fp64", p.Ng))
+    eV = np.abs(keep["V2"] - V2r.cpu().numpy()).max()
+    eh = np.abs(keep["h1"] - h1r.cpu().numpy()).max()
+    eE = abs(keep["E0"] - float(E0r.cpu()[0]))
+    _note(f"  bf16x3 vs fp64: |dV2| {eV:.2e} |dh1| {eh:.2e} |dE0| {eE:.2e} (E0 {float(E0r.cpu()[0]):.10f})")
+    assert eV < BARS[0] and eh < BARS[1] and eE < BARS[2]
