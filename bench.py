@@ -209,23 +209,23 @@ def profile_kernels(fn):
     return out
 
 
-def kernel_rooflines(times, N, nocc, Ng, chunk, prec):
+def kernel_rooflines(times, N, nocc, Ng, prec):
     """Per-kernel algorithmic rate and fraction of the relevant peak for the
-    contraction kernels of one step (flops per launch: K build 6 rows Ng Npair,
-    FP64 occupied block 6 rows Ng nOP, two-body GEMM 8 rows Npair^2)."""
+    contraction kernels of one step: the kernel's algorithmic flops per step
+    (K build 6 Ng^2 Npair, FP64 occupied block 6 Ng^2 nOP, two-body GEMM
+    8 Ng Npair^2) over its summed device time in that step."""
     P = N * (N + 1) // 2
     nOP = nocc * (nocc + 1) // 2
-    rows = chunk
-    table = {"k_build_K_lp": (6 * rows * Ng * P, PEAK[prec]), "k_build_K_f64": (6 * rows * Ng * P, PEAK["fp64"]),
-             "k_build_K_occ": (6 * rows * Ng * nOP, PEAK["fp64"]),
-             "k_gemm_tn_lds": (8 * rows * P * P, PEAK[prec]), "k_gemm_tn_lp": (8 * rows * P * P, PEAK[prec]),
-             "k_gemm2b_f64": (8 * rows * P * P, PEAK["fp64"])}
+    table = {"k_build_K_lp": (6 * Ng * Ng * P, PEAK[prec]), "k_build_K_f64": (6 * Ng * Ng * P, PEAK["fp64"]),
+             "k_build_K_occ": (6 * Ng * Ng * nOP, PEAK["fp64"]),
+             "k_gemm_tn_lds": (8 * Ng * P * P, PEAK[prec]), "k_gemm_tn_lp": (8 * Ng * P * P, PEAK[prec]),
+             "k_gemm2b_f64": (8 * Ng * P * P, PEAK["fp64"])}
     out = {}
     for k, (n, t) in sorted(times.items(), key=lambda kv: -kv[1][1]):
-        e = {"launches": n, "avg_ms": t / n * 1e3, "share_of_step": None}
+        e = {"launches": n, "avg_ms": t / n * 1e3, "total_ms": t * 1e3, "share_of_step": None}
         if k in table:
             f, peak = table[k]
-            e.update(flop_per_launch=f, tflops=f / (t / n) / 1e12, peak_tflops=peak, frac=f / (t / n) / 1e12 / peak)
+            e.update(flop_per_step=f, tflops=f / t / 1e12, peak_tflops=peak, frac=f / t / 1e12 / peak)
         out[k] = e
     tot = sum(t for _, t in times.values())
     for k in out:
@@ -591,8 +591,7 @@ def main():
         torch.cuda.empty_cache()
         rc = run_gpu(problem, args.compare, 1, 0, cchunk, profile=args.compare == "fp64")
         if rc.get("kernel_times"):
-            forms[args.compare + "_kernels"] = kernel_rooflines(rc["kernel_times"], wl.N, nref, wl.Ng, cchunk,
-                                                                args.compare)
+            forms[args.compare + "_kernels"] = kernel_rooflines(rc["kernel_times"], wl.N, nref, wl.Ng, args.compare)
         V2c, h1c, E0c = rc["outputs"]
         err = {"V2": (V2h - V2c).abs().max().item(), "h1": (h1h - h1c).abs().max().item(),
                "E0": (E0h - E0c).abs().max().item()}
@@ -640,7 +639,7 @@ def main():
                      "per_launch_flop": tot_f / nl, "avg_launch_ms": tot_t / nl * 1e3,
                      "executed_mfma_frac": achieved * TERMS[args.prec] / peak},
         "forms": forms,
-        "kernels": (kernel_rooflines(r["kernel_times"], wl.N, nref, wl.Ng, chunk, args.prec)
+        "kernels": (kernel_rooflines(r["kernel_times"], wl.N, nref, wl.Ng, args.prec)
                     if r.get("kernel_times") else None),
         "cpu_baseline": cpu,
     }

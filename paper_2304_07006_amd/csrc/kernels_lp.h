@@ -485,9 +485,10 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
         }
 }
 
-// K[c][r][P] = sum_s part[s][c][r][P] in FP64 (fixed order), for c < nc, r < rows, P < ldP.
+// K[c][r][P] = sum_s part[s][c][r][P] in FP64 (fixed order), for c < nc, r < rows, P < ldP;
+// K's components are krows rows apart (a piece of a longer chunk).
 __global__ void k_reduce_K(const float* __restrict__ part, int nseg, int cap, int ldL, int rows, int ldP,
-                           double* __restrict__ K, int nc) {
+                           double* __restrict__ K, int krows, int nc) {
     // four consecutive pairs per thread (ldP, ldL and the component strides are
     // multiples of 4): 16-byte partial loads, 32-byte stores, same summation order
     const size_t n4 = (size_t)nc * rows * (ldP / 4);
@@ -502,7 +503,7 @@ __global__ void k_reduce_K(const float* __restrict__ part, int nseg, int cap, in
             const f4 v = *(const f4*)(part + (size_t)q * nc * cstride + o);
             s += (d4){(double)v[0], (double)v[1], (double)v[2], (double)v[3]};
         }
-        *(d4*)(K + cr * ldP + P) = s;
+        *(d4*)(K + ((size_t)c * krows + r) * ldP + P) = s;
     }
 }
 

@@ -13,9 +13,9 @@
 //   E      [kESplit][N][N] doubles    per-split partials (one-body, exchange)
 //   S      [cap][8] doubles           per-point scalars of the current chunk
 //   D      [4][cap][ldP] doubles      A, Bx, By, Bz of the current chunk
-//   Kpart  [nsegK][3][cap][ldL] f32   K-build segment partials     (prec != FP64)
+//   Kpart  [nsegK][3][kcap][ldL] f32  K-build segment partials of kcap rows (prec != FP64)
 //   CDlp   [8][NS][cap/8][ldL][8]     C and D of the chunk, k8-packed (prec != FP64)
-//   Mpart  [ceil(cap/segM)][4][ldL][ldL] f32   two-body partials   (prec != FP64)
+//   Mpart  [kMSegGroup][4][ldL][ldL] f32  two-body partials of a group of row segments
 // and with XTC_WITH_BACKWARD in prec (the adjoint reuses M for Gbar):
 //   Kc [3][cap][ldP], Y [7][cap][ldP], T [cap][3][N][nocc], Wbar [cap][3],
 //   gpart [ceil(cap/32) * ngp/128][16], gacc [16], occw [N] f64, kidx [N],
@@ -28,7 +28,12 @@
 //   Rg [3][cap][ldN] (w phi grad phi of the chunk)
 // ldL = ldP rounded up to 512.  The chunk capacity `cap` is the largest
 // multiple of 32 rows that fits in the bytes the caller passes, so every call
-// with the same ws_bytes agrees on it.
+// with the same ws_bytes agrees on it.  The segment partials of the reduced
+// forms are bounded: the K build runs over a chunk in row pieces of at most
+// kcap rows (kcap = min(cap, the multiple of 1024 rows whose partials fit
+// kKpartBudget bytes, at least 1024)), and the two-body GEMM over groups of
+// kMSegGroup row segments, each piece reduced into its FP64 result before the
+// next one reuses the partial buffer.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -95,6 +100,9 @@ constexpr int kSegK = 8192, kSegKF32 = 1024;
 constexpr int kSegM = 2048, kSegMF32 = 512;
 constexpr int kRowQuant = 32;
 constexpr int kOccSegMax = 32;  // most segments of the FP64 occupied-block sum over g'
+constexpr size_t kKpartBudget = (size_t)8 << 30;   // bytes of K-build segment partials
+constexpr int kKpartQuant = 1024;                  // rows: 32 row tiles, one XCD's resident set
+constexpr int kMSegGroup = 2;                      // row segments per two-body GEMM launch
 
 struct Layout {
     int N, Ng, nocc, ldP, ngp, Npair, prec;
@@ -103,9 +111,13 @@ struct Layout {
     bool tc2;
     bool bwd;
     size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, occw, kidx, rhoR, GsL, Atc, Btc, GT;
-    size_t fixed;        // bytes before S (plus the Mpart remainder reserve)
-    size_t per_row;      // bytes per chunk row
+    size_t fixed;        // bytes of everything that does not scale with the chunk rows (plus reserves)
+    size_t chunk0;       // offset of the first chunk buffer (S)
+    size_t per_row;      // bytes per chunk row (without the K-build partials)
+    size_t kpart_row;    // bytes per row of the K-build partials
+    int kcap_max;        // most rows of one K-build piece
     int cap;             // chunk rows that fit (multiple of kRowQuant)
+    int kcap;            // rows of the K-build partial buffer: min(cap, kcap_max)
     size_t mslab;        // bytes of the two-body partials of one segM-row segment
     size_t cdw;          // packed operand elements per row and split (CDlp)
     size_t S, D, Kpart, CDlp, Mpart, Kocc, Kc, Y, T, Wbar, gpart, KbL, Ftc, Rg, end;
@@ -190,11 +202,13 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     // w phi grad phi (3 of ldN) and K (3 of ldL) of the TC integrals
     L.cdw = std::max((size_t)8 * L.ldL, L.tc2 ? (size_t)3 * L.ldN + (size_t)3 * L.ldL : 0);
     const size_t mslab = L.mslab;
-    L.fixed = off + mslab + (L.bwd ? gslab : 0) + 16 * kAlign;
+    L.chunk0 = off;
+    L.fixed = off + (size_t)kMSegGroup * mslab + (L.bwd ? gslab : 0) + 16 * kAlign;
     L.per_row = (size_t)L.nspin * (8 * sizeof(double) + (size_t)4 * L.ldP * sizeof(double));
     if (lp) L.per_row += (size_t)kOccSegMax * 3 * L.ldO * sizeof(double);
-    if (lp)
-        L.per_row += (size_t)L.nsegK * 3 * L.ldL * sizeof(float) + L.cdw * L.ns * L.es + (mslab + L.segM - 1) / L.segM;
+    if (lp) L.per_row += L.cdw * L.ns * L.es;
+    L.kpart_row = lp ? (size_t)L.nsegK * 3 * L.ldL * sizeof(float) : 0;
+    L.kcap_max = lp ? (int)std::max<size_t>(kKpartQuant, kKpartBudget / L.kpart_row / kKpartQuant * kKpartQuant) : 0;
     if (L.tc2) L.per_row += (size_t)L.ldP * sizeof(double) + (size_t)3 * L.ldN * sizeof(double);
     if (L.bwd)
         L.per_row += (size_t)(3 + L.nY) * L.ldP * sizeof(double) + (size_t)3 * L.N * L.nocc * sizeof(double) +
@@ -203,21 +217,34 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     return L;
 }
 
-// Chunk capacity that `bytes` allows, and the offsets of the chunk buffers for it.
+// Bytes of a workspace for chunks of `rows` rows (a multiple of kRowQuant).
+size_t layout_bytes(const Layout& L, size_t rows) {
+    return L.fixed + rows * L.per_row + std::min(rows, (size_t)L.kcap_max) * L.kpart_row;
+}
+
+// Chunk capacity that `bytes` allows (the inverse of layout_bytes), and the
+// offsets of the chunk buffers for it.
 void place_chunk(Layout& L, size_t bytes) {
-    long cap = bytes > L.fixed ? (long)((bytes - L.fixed) / L.per_row) : 0;
+    long cap = 0;
+    if (bytes > L.fixed) {
+        const size_t b = bytes - L.fixed;
+        const size_t c1 = b / (L.per_row + L.kpart_row);   // rows, if the partials cover all of them
+        if (c1 <= (size_t)L.kcap_max) cap = (long)c1;
+        else cap = (long)((b - (size_t)L.kcap_max * L.kpart_row) / L.per_row);
+    }
     cap = cap / kRowQuant * kRowQuant;
     const long most = (long)align_up((size_t)L.Ng, kRowQuant);
     if (cap > most) cap = most;
     L.cap = (int)cap;
+    L.kcap = std::min(L.cap, L.kcap_max);
     const bool lp = L.form != 0;
     const size_t gslab = (size_t)(L.ngp / 128) * kGradMax * sizeof(double);
-    size_t off = L.fixed - 16 * kAlign - L.mslab - (L.bwd ? gslab : 0);
+    size_t off = L.chunk0;
     L.S = off;       off = align_up(off + (size_t)L.nspin * cap * 8 * sizeof(double), kAlign);
     L.D = off;       off = align_up(off + (size_t)L.nspin * 4 * cap * L.ldP * sizeof(double), kAlign);
-    L.Kpart = off;   off = align_up(off + (lp ? (size_t)L.nsegK * 3 * cap * L.ldL * sizeof(float) : 0), kAlign);
+    L.Kpart = off;   off = align_up(off + (lp ? (size_t)L.kcap * L.kpart_row : 0), kAlign);
     L.CDlp = off;    off = align_up(off + (lp ? L.cdw * L.ns * cap * L.es : 0), kAlign);
-    L.Mpart = off;   off = align_up(off + (size_t)((cap + L.segM - 1) / L.segM) * L.mslab, kAlign);
+    L.Mpart = off;   off = align_up(off + (size_t)kMSegGroup * L.mslab, kAlign);
     L.Kocc = off;    off = align_up(off + (lp ? (size_t)kOccSegMax * 3 * cap * L.ldO * sizeof(double) : 0), kAlign);
     const bool b = L.bwd;
     L.Kc = off;      off = align_up(off + (b ? (size_t)3 * cap * L.ldP * sizeof(double) : 0), kAlign);
@@ -300,7 +327,7 @@ xtc_status check_ws(const Layout& L, void* ws, size_t bytes) {
     if ((uintptr_t)ws % kAlign) return fail(XTC_E_WORKSPACE, "workspace not 256-byte aligned");
     if (L.cap < kRowQuant)
         return fail(XTC_E_WORKSPACE, "workspace of %zu bytes holds no chunk (need >= %zu)", bytes,
-                    L.fixed + kRowQuant * L.per_row);
+                    layout_bytes(L, kRowQuant));
     return XTC_OK;
 }
 
@@ -404,7 +431,7 @@ void launch_build_lp(const Layout& L, int g0, int rows, const JasDev& J, void* w
     const int n_ct = (L.ldL + cols - 1) / cols;
     hipLaunchKernelGGL((k_build_K_lp<KIND, FORM, NC>), dim3(n_rt * n_ct * L.nsegK), dim3(kLpThreads), 0, st,
                        at<d4>(ws, L.pos), at<void>(ws, L.rho_lp), (size_t)L.ngp * L.ldL, L.ldL, L.ngp, g0, rows, n_rt,
-                       L.segK, J, at<float>(ws, L.Kpart), L.cap, L.ldP, n_ct, L.nsegK);
+                       L.segK, J, at<float>(ws, L.Kpart), L.kcap, L.ldP, n_ct, L.nsegK);
 }
 
 // Segments of the g' sum for a grid of `tiles` workgroups per segment: the
@@ -461,24 +488,37 @@ int launch_build_occ(const Layout& L, int g0, int rows, int n_rt, const JasDev& 
     }
 }
 
+// The split K build of rows [g0, g0 + rows) (nc = 3: K, or nc = 1: F of the
+// TC integrals) in pieces of at most kcap rows: segment partials, then their
+// FP64 sum into out[c][r][P] (component stride `rows` rows).
+template <int NC>
+xtc_status build_lp_pieces(const Layout& L, int g0, int rows, const JasDev& J, double* out, void* ws, hipStream_t st) {
+    xtc_status s;
+    for (int r0 = 0; r0 < rows; r0 += L.kcap) {
+        const int nr = std::min(L.kcap, rows - r0);
+        if (J.kind == 0) {
+            if (L.form == 1) launch_build_lp<0, 1, NC>(L, g0 + r0, nr, J, ws, st);
+            else if (L.form == 3) launch_build_lp<0, 3, NC>(L, g0 + r0, nr, J, ws, st);
+            else launch_build_lp<0, 6, NC>(L, g0 + r0, nr, J, ws, st);
+        } else {
+            if (L.form == 1) launch_build_lp<1, 1, NC>(L, g0 + r0, nr, J, ws, st);
+            else if (L.form == 3) launch_build_lp<1, 3, NC>(L, g0 + r0, nr, J, ws, st);
+            else launch_build_lp<1, 6, NC>(L, g0 + r0, nr, J, ws, st);
+        }
+        if ((s = launched(NC == 3 ? "build_K_lp" : "build_F_lp")) != XTC_OK) return s;
+        const size_t n4 = (size_t)NC * nr * L.ldP / 4;   // k_reduce_K: four pairs per thread
+        const unsigned blocks = (unsigned)std::min<size_t>((n4 + 255) / 256, 16384);
+        hipLaunchKernelGGL(k_reduce_K, dim3(blocks), dim3(256), 0, st, at<float>(ws, L.Kpart), L.nsegK, L.kcap,
+                           L.ldL, nr, L.ldP, out + (size_t)r0 * L.ldP, rows, NC);
+        if ((s = launched("reduce_K")) != XTC_OK) return s;
+    }
+    return XTC_OK;
+}
+
 xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double* K, bool occ64, void* ws,
                       hipStream_t st) {
-    if (J.kind == 0) {
-        if (L.form == 1) launch_build_lp<0, 1>(L, g0, rows, J, ws, st);
-        else if (L.form == 3) launch_build_lp<0, 3>(L, g0, rows, J, ws, st);
-        else launch_build_lp<0, 6>(L, g0, rows, J, ws, st);
-    } else {
-        if (L.form == 1) launch_build_lp<1, 1>(L, g0, rows, J, ws, st);
-        else if (L.form == 3) launch_build_lp<1, 3>(L, g0, rows, J, ws, st);
-        else launch_build_lp<1, 6>(L, g0, rows, J, ws, st);
-    }
     xtc_status s;
-    if ((s = launched("build_K_lp")) != XTC_OK) return s;
-    const size_t n4 = (size_t)3 * rows * L.ldP / 4;   // k_reduce_K: four pairs per thread
-    const unsigned blocks = (unsigned)std::min<size_t>((n4 + 255) / 256, 16384);
-    hipLaunchKernelGGL(k_reduce_K, dim3(blocks), dim3(256), 0, st, at<float>(ws, L.Kpart), L.nsegK, L.cap, L.ldL,
-                       rows, L.ldP, K, 3);
-    if ((s = launched("reduce_K")) != XTC_OK) return s;
+    if ((s = build_lp_pieces<3>(L, g0, rows, J, K, ws, st)) != XTC_OK) return s;
     if (!occ64) return XTC_OK;
     // occupied-occupied pairs in FP64, written over the reduced-precision values:
     // segments of the sum over g' (enough, and evenly enough, to fill the chip),
@@ -536,6 +576,28 @@ xtc_status reduce_parts(const float* part, int nparts, int ldC, int ldD, int pma
     return launched("reduce_M");
 }
 
+// M (+)= C^T D over rows32 packed operand rows (reduced forms), launched in
+// groups of kMSegGroup row segments of segM rows: each group's FP32 partials
+// are summed in FP64 into M before the next group reuses the partial buffer.
+xtc_status gemm_tn_grouped(const Layout& L, const char* C, int ldC, size_t c_split, const char* D, int ldD,
+                           size_t d_split, int rows32, int pmax, int rmax, int ncomp, int cpw, double* M, int ldM,
+                           int accumulate, void* ws, hipStream_t st) {
+    xtc_status s;
+    float* part = at<float>(ws, L.Mpart);
+    const int group = kMSegGroup * L.segM;
+    for (int q0 = 0; q0 < rows32; q0 += group) {
+        const int nr = std::min(group, rows32 - q0);
+        const size_t shift = (size_t)(q0 / 8) * 8 * L.es;   // bytes per packed row group and column
+        int np = 0;
+        if ((s = gemm_tn_lp(L.form, C + shift * ldC, ldC, c_split, D + shift * ldD, ldD, d_split, nr, pmax, rmax,
+                            ncomp, cpw, L.segM, part, &np, st)) != XTC_OK)
+            return s;
+        if ((s = reduce_parts(part, np, ldC, ldD, pmax, rmax, M, ldM, q0 == 0 ? accumulate : 1, st)) != XTC_OK)
+            return s;
+    }
+    return XTC_OK;
+}
+
 xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int accumulate, void* ws, hipStream_t st) {
     xtc_status s;
     const int rows32 = (int)align_up((size_t)rows, kRowQuant);
@@ -549,7 +611,6 @@ xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int acc
         if ((s = pack_any(L.form, src, rows, L.ldP, L.ldP, n8, L.ldL, cd + c * comp_bytes, split_stride, st)) != XTC_OK)
             return s;
     }
-    float* part = at<float>(ws, L.Mpart);
     // one spin channel at a time: its D into the operand buffer, GEMM, reduction into M^s
     for (int sp = 0; sp < L.nspin; ++sp) {
         const double* D = at<double>(ws, L.D) + (size_t)sp * 4 * L.cap * L.ldP;
@@ -558,12 +619,9 @@ xtc_status gemm2b_lp(const Layout& L, const double* K, int g0, int rows, int acc
                               cd + (4 + c) * comp_bytes, split_stride, st)) != XTC_OK)
                 return s;
         }
-        int np = 0;
-        if ((s = gemm_tn_lp(L.form, cd, L.ldL, split_stride, cd + 4 * comp_bytes, L.ldL, split_stride, rows32, L.ldP,
-                            L.ldP, 4, 1, L.segM, part, &np, st)) != XTC_OK)
-            return s;
-        if ((s = reduce_parts(part, np, L.ldL, L.ldL, L.ldP, L.ldP, at<double>(ws, L.M) + (size_t)sp * L.ldP * L.ldP,
-                              L.ldP, accumulate, st)) != XTC_OK)
+        if ((s = gemm_tn_grouped(L, cd, L.ldL, split_stride, cd + 4 * comp_bytes, L.ldL, split_stride, rows32, L.ldP,
+                                 L.ldP, 4, 1, at<double>(ws, L.M) + (size_t)sp * L.ldP * L.ldP, L.ldP, accumulate,
+                                 ws, st)) != XTC_OK)
             return s;
     }
     return XTC_OK;
@@ -639,8 +697,7 @@ size_t xtc_workspace_size(const xtc_problem* pb, int32_t prec, int32_t chunk_row
         return 0;
     }
     Layout L = make_layout(pb, prec);
-    const size_t rows = align_up((size_t)chunk_rows, kRowQuant);
-    return L.fixed + rows * L.per_row;
+    return layout_bytes(L, align_up((size_t)chunk_rows, kRowQuant));
 }
 
 xtc_status xtc_prepare(const xtc_problem* pb, int32_t prec, int32_t chunk_rows, void* ws, size_t ws_bytes,
@@ -1061,20 +1118,8 @@ xtc_status xtc_tc_2body(const xtc_problem* pb, const xtc_jastrow* jas, const dou
         else
             hipLaunchKernelGGL((k_build_F_f64<1, 8>), gF, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho),
                                L.ldP, L.ngp, g0, rows, n_rt, J, F);
-    } else {
-        if (J.kind == 0) {
-            if (L.form == 1) launch_build_lp<0, 1, 1>(L, g0, rows, J, ws, st);
-            else if (L.form == 3) launch_build_lp<0, 3, 1>(L, g0, rows, J, ws, st);
-            else launch_build_lp<0, 6, 1>(L, g0, rows, J, ws, st);
-        } else {
-            if (L.form == 1) launch_build_lp<1, 1, 1>(L, g0, rows, J, ws, st);
-            else if (L.form == 3) launch_build_lp<1, 3, 1>(L, g0, rows, J, ws, st);
-            else launch_build_lp<1, 6, 1>(L, g0, rows, J, ws, st);
-        }
-        if ((s = launched("build_F_lp")) != XTC_OK) return s;
-        const size_t n4 = (size_t)rows * L.ldP / 4;
-        hipLaunchKernelGGL(k_reduce_K, dim3((unsigned)std::min<size_t>((n4 + 255) / 256, 16384)), dim3(256), 0, st,
-                           at<float>(ws, L.Kpart), L.nsegK, L.cap, L.ldL, rows, L.ldP, F, 1);
+    } else if ((s = build_lp_pieces<1>(L, g0, rows, J, F, ws, st)) != XTC_OK) {
+        return s;
     }
     if ((s = launched("build_F")) != XTC_OK) return s;
     double* Rg = at<double>(ws, L.Rg);
@@ -1101,16 +1146,13 @@ xtc_status xtc_tc_2body(const xtc_problem* pb, const xtc_jastrow* jas, const dou
         const int rows32 = (int)align_up((size_t)rows, kRowQuant);
         const int n8 = rows32 / 8;
         char* cd = at<char>(ws, L.CDlp);
-        float* part = at<float>(ws, L.Mpart);
         const size_t sL = (size_t)L.cap * L.ldL, sN = (size_t)L.cap * L.ldN;   // elements of one split
         const size_t cL = (size_t)L.ns * sL * L.es, cN = (size_t)L.ns * sN * L.es;   // bytes of one component
-        int np = 0;
         if ((s = pack_any(L.form, rho_rows, rows, L.ldP, L.ldP, n8, L.ldL, cd, sL, st)) != XTC_OK) return s;
         if ((s = pack_any(L.form, F, rows, L.ldP, L.ldP, n8, L.ldL, cd + cL, sL, st)) != XTC_OK) return s;
-        if ((s = gemm_tn_lp(L.form, cd, L.ldL, sL, cd + cL, L.ldL, sL, rows32, L.ldP, L.ldP, 1, 1, L.segM,
-                            part, &np, st)) != XTC_OK)
+        if ((s = gemm_tn_grouped(L, cd, L.ldL, sL, cd + cL, L.ldL, sL, rows32, L.ldP, L.ldP, 1, 1, Atc, L.ldP, acc, ws,
+                                 st)) != XTC_OK)
             return s;
-        if ((s = reduce_parts(part, np, L.ldL, L.ldL, L.ldP, L.ldP, Atc, L.ldP, acc, st)) != XTC_OK) return s;
         char* kd = cd + 3 * cN;
         for (int x = 0; x < 3; ++x) {
             if ((s = pack_any(L.form, Rg + x * xs, rows, L.ldN, L.ldN, n8, L.ldN, cd + x * cN, sN, st)) != XTC_OK)
@@ -1120,10 +1162,9 @@ xtc_status xtc_tc_2body(const xtc_problem* pb, const xtc_jastrow* jas, const dou
                 return s;
         }
         // the three components of rhog_pq . K_R summed inside each workgroup
-        if ((s = gemm_tn_lp(L.form, cd, L.ldN, sN, kd, L.ldL, sL, rows32, L.N * L.N, L.ldP, 3, 3, L.segM,
-                            part, &np, st)) != XTC_OK)
+        if ((s = gemm_tn_grouped(L, cd, L.ldN, sN, kd, L.ldL, sL, rows32, L.N * L.N, L.ldP, 3, 3, Btc, L.ldP, acc, ws,
+                                 st)) != XTC_OK)
             return s;
-        if ((s = reduce_parts(part, np, L.ldN, L.ldL, L.N * L.N, L.ldP, Btc, L.ldP, acc, st)) != XTC_OK) return s;
     }
     if (flags & XTC_FINALIZE) {
         const int NN = L.N * L.N;

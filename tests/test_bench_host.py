@@ -65,3 +65,19 @@ def test_host_info_and_cpu_baseline_fields():
     assert cb["kind"] == "oracle" and cb["cores"] == info["cores"] and cb["value"] > 0
     assert "24 of 128" in cb["sample"] and cb["full_workload_seconds_extrapolated"] > cb["seconds"]
     assert 0.5 < cb["k_build_share_of_sample_flops"] < 1.0
+
+
+def test_kernel_rooflines_from_per_step_totals():
+    """Per-kernel rates use the kernel's algorithmic flops per step over its
+    summed device time, whatever the number of launches."""
+    P = 128 * 129 // 2
+    t_lp = 2.4                      # seconds of k_build_K_lp in one step, over 40 launches
+    times = {"k_build_K_lp": (40, t_lp), "k_build_K_occ": (20, 0.35), "k_gemm_tn_lds": (40, 0.23),
+             "k_reduce_K": (40, 0.06)}
+    r = bench.kernel_rooflines(times, 128, 16, 150000, "bf16x3")
+    assert abs(r["k_build_K_lp"]["tflops"] - 6 * 150000 ** 2 * P / t_lp / 1e12) < 1e-9
+    assert abs(r["k_build_K_lp"]["frac"] - r["k_build_K_lp"]["tflops"] / 2500.0) < 1e-12
+    assert abs(r["k_build_K_occ"]["tflops"] - 6 * 150000 ** 2 * 136 / 0.35 / 1e12) < 1e-9
+    assert r["k_build_K_occ"]["peak_tflops"] == 78.6 and "frac" not in r["k_reduce_K"]
+    assert abs(sum(e["share_of_step"] for e in r.values()) - 1.0) < 1e-12
+    assert abs(r["k_build_K_lp"]["avg_ms"] - t_lp / 40 * 1e3) < 1e-9
