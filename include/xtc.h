@@ -256,6 +256,25 @@ size_t xtc_lowdin_workspace_size(int32_t N, int32_t Ng);
 xtc_status xtc_lowdin(int32_t N, int32_t Ng, const double *chi, const double *w, double *phi,
                       double *lambda, void *ws, size_t ws_bytes, void *stream);
 
+/* xtc_lowdin for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, with the scratch taken from a file-scope device
+ * array of XTC_LOWDIN_NOALLOC_BYTES instead of a caller workspace.  Each
+ * device the library runs on holds its own copy of that array until the
+ * process ends; the call allocates nothing.  The array's device address is
+ * looked up on the first call on each device (with that device current).
+ * Sizes whose workspace (xtc_lowdin_workspace_size) exceeds the array return
+ * XTC_E_UNSUPPORTED before anything is launched; N = 128 fits up to
+ * Ng ~ 2 x 10^6 grid points, N = 256 up to Ng ~ 5 x 10^5.
+ * Every call on a device shares that device's array, so calls that overlap
+ * on one device (other streams or host threads) race and give undefined
+ * results; calls on one stream are ordered.  Nothing in the array needs to
+ * start at zero (every scratch word is written before it is read).
+ * Like xtc_lowdin it synchronises `stream` once to check the eigensolver. */
+#define XTC_LOWDIN_NOALLOC_BYTES ((size_t)64 << 20)
+xtc_status xtc_lowdin_noalloc(int32_t N, int32_t Ng, const double *chi, const double *w, double *phi,
+                              double *lambda, void *stream);
+
 /* Two-body transcorrelated integrals on the grid (Theory, definition of K):
  *   K_pr^qs = 1/2 <pr| P^1_2 (lap_1 u + (grad_1 u)^2 + 2 grad_1 u . grad_1) |qs>
  * with both electrons on the grid, written as K2[p][q][r][s] = K_pr^qs

@@ -40,6 +40,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1083,8 +1084,41 @@ xtc_status check_lowdin_args(int N, int Ng, const double* chi, const double* w, 
 xtc_status run_lowdin(const LowdinLayout& L, int N, int Ng, const double* chi, const double* w, double* phi,
                       double* lambda, void* ws, hipStream_t st);
 
+// Scratch of xtc_lowdin_noalloc: a file-scope device array, one copy per
+// device the library runs on (held until the process ends).  In host code
+// `scratch` names the symbol only; its device address on each device comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kNoAllocBytes = XTC_LOWDIN_NOALLOC_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
 }  // namespace
 
+static __device__ __align__(256) unsigned char scratch[XTC_LOWDIN_NOALLOC_BYTES];
+
+namespace {
+xtc_status scratch_of_current_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(XTC_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    if (dev < 0 || dev >= kMaxDevices) return fail(XTC_E_UNSUPPORTED, "device %d above %d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(XTC_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return XTC_OK;
+}
+}  // namespace
 
 xtc_status xtc_tc_2body(const xtc_problem* pb, const xtc_jastrow* jas, const double* dphi, const double* K,
                         int32_t g0, int32_t g1, int32_t prec, int32_t flags, double* K2, void* ws, size_t ws_bytes,
@@ -1226,6 +1260,18 @@ xtc_status xtc_lowdin(int32_t N, int32_t Ng, const double* chi, const double* w,
     return run_lowdin(L, N, Ng, chi, w, phi, lambda, ws, (hipStream_t)stream);
 }
 
+xtc_status xtc_lowdin_noalloc(int32_t N, int32_t Ng, const double* chi, const double* w, double* phi,
+                              double* lambda, void* stream) {
+    xtc_status s;
+    if ((s = check_lowdin_args(N, Ng, chi, w, phi)) != XTC_OK) return s;
+    const LowdinLayout L = lowdin_layout(N, Ng);
+    if (L.total > kNoAllocBytes)
+        return fail(XTC_E_UNSUPPORTED, "N=%d, Ng=%d needs %zu bytes of scratch, above the %zu of the static array", N,
+                    Ng, L.total, kNoAllocBytes);
+    void* ws = nullptr;
+    if ((s = scratch_of_current_device(&ws)) != XTC_OK) return s;
+    return run_lowdin(L, N, Ng, chi, w, phi, lambda, ws, (hipStream_t)stream);
+}
 }  // extern "C"
 
 namespace {

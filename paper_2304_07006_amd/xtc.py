@@ -73,6 +73,8 @@ _SIGS = {
     "xtc_lowdin": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p]),
+    "xtc_lowdin_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 _lib = None
@@ -266,6 +268,15 @@ def xtc_lowdin(N, Ng, chi, w, phi, lam, ws, stream=None):
     _dev(lam, N, "lambda", required=False)
     _check(load().xtc_lowdin(N, Ng, _ptr(chi), _ptr(w), _ptr(phi), _ptr(lam), _ptr(ws), ws.numel(),
                              _stream(stream)))
+
+
+def xtc_lowdin_noalloc(N, Ng, chi, w, phi, lam, stream=None):
+    """xtc_lowdin with the library's static device scratch (no workspace)."""
+    _dev(chi, N * Ng, "chi")
+    _dev(w, Ng, "w")
+    _dev(phi, N * Ng, "phi")
+    _dev(lam, N, "lambda", required=False)
+    _check(load().xtc_lowdin_noalloc(N, Ng, _ptr(chi), _ptr(w), _ptr(phi), _ptr(lam), _stream(stream)))
 
 
 def lowdin(chi, w, device="cuda"):

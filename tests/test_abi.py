@@ -234,3 +234,15 @@ def test_lowdin_validation(lib):
     st = lib.xtc_lowdin(8, 100, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x4000), None,
                         ctypes.c_void_p(0x100000), n - 1, None)
     assert st == xtc.XTC_E_WORKSPACE
+
+
+def test_lowdin_noalloc_validation(lib):
+    """xtc_lowdin_noalloc rejects bad sizes, NULL arrays and problems whose
+    scratch exceeds the static array before any HIP call (fake pointers)."""
+    f = ctypes.c_void_p(0x1000)
+    assert lib.xtc_lowdin_noalloc(0, 100, f, f, f, None, None) == xtc.XTC_E_ARG
+    assert lib.xtc_lowdin_noalloc(8, 100, None, f, f, None, None) == xtc.XTC_E_ARG
+    assert lib.xtc_lowdin_noalloc(8, (1 << 28) + 1, f, f, f, None, None) == xtc.XTC_E_UNSUPPORTED
+    assert lib.xtc_lowdin_workspace_size(256, 1 << 20) > (64 << 20)
+    st = lib.xtc_lowdin_noalloc(256, 1 << 20, f, f, f, None, None)
+    assert st == xtc.XTC_E_UNSUPPORTED and "static array" in xtc.last_error()
