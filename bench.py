@@ -275,7 +275,11 @@ def run_gpu(problem, prec, steps, warmup, chunk, profile=False):
     if profile:                       # one more step, untimed, under the profiler
         try:
             times = profile_kernels(lambda: step(False))
+            busy = sum(t for _, t in times.values())
+            if busy < 0.5 * dt:       # another profiler holds the device activity trace
+                raise RuntimeError(f"kernel time {busy:.3f} s of a {dt:.3f} s step")
         except Exception as e:        # the breakdown is optional
+            times = None
             print(f"[bench] kernel profile unavailable: {e}", file=sys.stderr, flush=True)
     return dict(sec=dt, kbuild=kt, outputs=(ps.V2, ps.h1, ps.E0), ws_bytes=ps.ws.numel(), kernel_times=times)
 

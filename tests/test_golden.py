@@ -1,8 +1,9 @@
-"""The stored oracle values on an orbital subset of the headline workload
-(tests/golden/make_subset_golden.py): the file regenerates its inputs, and
+"""The stored oracle values on orbital subsets of the measured workloads
+(tests/golden/make_subset_golden.py): each file regenerates its inputs, and
 its numbers obey relations of Appendix B that the script did not use to
 write them (the one-body term from the two-body term, the zero-body term
 from the one-body term, the chemist symmetries of the unique entries)."""
+import json
 import os
 
 import numpy as np
@@ -11,12 +12,14 @@ import pytest
 from paper_2304_07006_amd import inputs
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-GOLDEN = os.path.join(HERE, "golden", "N128-occ16-Ng150k_subset.npz")
+STORED = ["N128-occ16-Ng150k", "N96-occ12-Ng100k"]
 
 
-@pytest.fixture(scope="module")
-def golden():
-    g = np.load(GOLDEN, allow_pickle=False)
+def _load(name):
+    path = os.path.join(HERE, "golden", f"{name}_subset.npz")
+    if not os.path.exists(path):
+        pytest.fail(f"{path} is missing")
+    g = np.load(path, allow_pickle=False)
     return {k: g[k] for k in g.files}
 
 
@@ -32,25 +35,33 @@ def _full_block(g):
     return V
 
 
-def test_golden_regenerates_its_inputs(golden):
-    p = inputs.make_workload("N128-occ16-Ng150k", lowdin=golden["X"])
+@pytest.mark.parametrize("name", STORED)
+def test_stored_values_regenerate_their_inputs(name):
+    g = _load(name)
+    meta = json.loads(str(g["meta"]))
+    wl = inputs.WORKLOADS[name]
+    assert meta["workload"] == name and meta["N"] == wl.N and meta["Ng"] == wl.Ng
+    p = inputs.make_workload(name, lowdin=g["X"])
     fp = inputs.input_fingerprint(p)
-    assert np.all(np.abs(fp - golden["fingerprint"]) <= 1e-12 * np.abs(golden["fingerprint"]))
+    assert np.all(np.abs(fp - g["fingerprint"]) <= 1e-12 * np.abs(g["fingerprint"]))
     # the stored orthonormalisation matrix orthonormalises the regenerated functions
     O = (p.phi * p.w) @ p.phi.T
     assert np.abs(O - np.eye(p.N)).max() < 1e-6
-    S = golden["S"]
-    assert len(S) == 24 and list(S[:16]) == list(range(16)) and len(set(S.tolist())) == 24
+    S = g["S"]
+    assert len(S) == wl.nocc + meta["virtuals"] and list(S[:wl.nocc]) == list(range(wl.nocc))
+    assert len(set(S.tolist())) == len(S)
 
 
-def test_golden_obeys_appendix_b_relations(golden):
-    V = _full_block(golden)
+@pytest.mark.parametrize("name", STORED)
+def test_stored_values_obey_appendix_b_relations(name):
+    g = _load(name)
+    V = _full_block(g)
     assert not np.isnan(V).any()
-    nocc = 16
+    nocc = inputs.WORKLOADS[name].nocc
     k = np.arange(nocc)
     # Delta h_pq = -1/2 (2 sum_k V2[p,q,k,k] - sum_k V2[p,k,k,q]) on the subset
     h = -0.5 * (2.0 * np.einsum("pqkk->pq", V[:, :, k][:, :, :, k]) - np.einsum("pkkq->pq", V[:, k][:, :, k]))
-    assert np.abs(h - golden["h1"]).max() < 1e-12 * max(1.0, np.abs(golden["h1"]).max())
-    E0 = -(2.0 / 3.0) * np.trace(golden["h1"][:nocc, :nocc])
-    assert abs(E0 - golden["E0"][0]) < 1e-12 * abs(E0)
-    assert np.abs(golden["h1"] - golden["h1"].T).max() < 1e-12
+    assert np.abs(h - g["h1"]).max() < 1e-12 * max(1.0, np.abs(g["h1"]).max())
+    E0 = -(2.0 / 3.0) * np.trace(g["h1"][:nocc, :nocc])
+    assert abs(E0 - g["E0"][0]) < 1e-12 * abs(E0)
+    assert np.abs(g["h1"] - g["h1"].T).max() < 1e-12

@@ -18,8 +18,23 @@ from paper_2304_07006_amd import inputs
 pytestmark = pytest.mark.gpu
 
 WORKLOAD = "N128-occ16-Ng150k"
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{WORKLOAD}_subset.npz")
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 BARS = (1e-6, 1e-6, 1e-8)
+
+
+def _load_golden(workload):
+    g = np.load(os.path.join(GOLDEN_DIR, f"{workload}_subset.npz"), allow_pickle=False)
+    return {k: g[k] for k in g.files}
+
+
+def _regenerate(workload, golden):
+    """The workload with the stored orthonormalisation matrix; its drawn
+    inputs must reproduce the stored fingerprint."""
+    p = inputs.make_workload(workload, lowdin=golden["X"])
+    fp = inputs.input_fingerprint(p)
+    dev = np.abs(fp - golden["fingerprint"]) / np.maximum(np.abs(golden["fingerprint"]), 1e-300)
+    assert dev.max() < 1e-12, f"regenerated inputs differ from the stored ones: {dev.max():.2e}"
+    return p
 
 
 def _note(msg):
@@ -36,19 +51,13 @@ def torch_cuda():
 
 @pytest.fixture(scope="module")
 def golden():
-    """The oracle's subset values; the workload regenerated with the stored
-    orthonormalisation matrix must reproduce the stored input fingerprint."""
-    g = np.load(GOLDEN, allow_pickle=False)
-    return {k: g[k] for k in g.files}
+    """The oracle's subset values of the headline workload."""
+    return _load_golden(WORKLOAD)
 
 
 @pytest.fixture(scope="module")
 def problem(golden):
-    p = inputs.make_workload(WORKLOAD, lowdin=golden["X"])
-    fp = inputs.input_fingerprint(p)
-    dev = np.abs(fp - golden["fingerprint"]) / np.maximum(np.abs(golden["fingerprint"]), 1e-300)
-    assert dev.max() < 1e-12, f"regenerated inputs differ from the stored ones: {dev.max():.2e}"
-    return p
+    return _regenerate(WORKLOAD, golden)
 
 
 def _against_golden(golden, V2, h1, E0, prec):
@@ -212,11 +221,14 @@ def test_full_size_adjoint_euler(torch_cuda):
     Ng=100 000, split BF16 x3 in 20 chunks (bench.py --backward)."""
     import bench
     wl = inputs.WORKLOADS["N96-occ12-Ng100k"]
-    p = inputs.make_workload(wl.name)
-    _note("case: N96-occ12-Ng100k adjoint bf16x3, Euler identity")
-    tf, tb, g, euler, _ = bench.run_backward(p, "bf16x3", _chunk("bf16x3", p.Ng), wl.aux_seed, 1, 0)
+    gold = _load_golden(wl.name)
+    p = _regenerate(wl.name, gold)
+    _note("case: N96-occ12-Ng100k adjoint bf16x3, Euler identity; forward vs the stored oracle values")
+    keep = {}
+    tf, tb, g, euler, _ = bench.run_backward(p, "bf16x3", _chunk("bf16x3", p.Ng), wl.aux_seed, 1, 0, keep)
     _note(f"  |c.g - 2L| / |2L| = {euler:.2e}; forward {tf:.2f} s, adjoint {tb:.2f} s")
     assert np.all(np.isfinite(g)) and euler < 1e-5
+    _against_golden(gold, keep["V2"], keep["h1"], keep["E0"], "bf16x3")
 
 
 def test_full_size_open_shell_adjoint_euler(torch_cuda):
@@ -241,10 +253,12 @@ def test_full_size_adjoint_central_differences(torch_cuda):
     import bench
     from paper_2304_07006_amd import xtc
     wl = inputs.WORKLOADS["N96-occ12-Ng100k"]
-    p = inputs.make_workload(wl.name)
-    _note("case: N96-occ12-Ng100k adjoint fp64 vs central differences (h = 1e-5, k = 0, 5)")
+    gold = _load_golden(wl.name)
+    p = _regenerate(wl.name, gold)
+    _note("case: N96-occ12-Ng100k adjoint fp64 vs central differences (h = 1e-5, k = 0, 5); forward vs oracle")
     keep = {}
     _, _, g, euler, _ = bench.run_backward(p, "fp64", _chunk("fp64", p.Ng), wl.aux_seed, 1, 0, keep)
+    _against_golden(gold, keep["V2"], keep["h1"], keep["E0"], "fp64")
     D, G = bench.loss_weights_device(p.N, wl.aux_seed)
     coef = np.array(p.jastrow.coef)
     h = 1e-5
