@@ -95,28 +95,67 @@ __global__ __launch_bounds__(256) void k_build_K_f64(const d4* __restrict__ pos,
 }
 
 // Occupied-occupied block of K in FP64, for the reduced-precision forms: the
-// same contraction as k_build_K_f64 over the gathered pair densities
-// rho_occ[g'][ldO] of the occupied pairs, one segment [blockIdx.y * seg_len,
-// ...) of the sum over g' per grid.y, written to part[seg][x][r][ldO].
-// Workgroup: 64 rows x 16 NBLK columns; each wave owns 16 rows and NBLK
-// 16-column blocks of all 3 components, so each FP64 d^x value a lane
-// generates feeds 3 NBLK MFMAs.  From 8 blocks on the 24 NBLK accumulator
-// registers per block column leave room for two waves per SIMD only (the
-// second wave hides the operand loads of the first).  The host picks NBLK.
+// same contraction as k_build_K_f64 over the gathered pair densities of the
+// occupied pairs (column tiles of 16 NBLK pairs, tile-major:
+// rho_occ[ct][ngp][16 NBLK]), one segment [blockIdx.y * seg_len, ...) of the
+// sum over g' per grid.y (seg_len a multiple of 32), written to
+// part[seg][x][r][ldO].  Workgroup: 64 rows x 16 NBLK columns; each wave owns
+// 16 rows and NBLK 16-column blocks of all 3 components, so each FP64 d^x
+// value a lane generates feeds 3 NBLK MFMAs (the host picks NBLK).  Each
+// 32-point stage of the tile (32 x 16 NBLK doubles, contiguous) and its 32
+// positions are copied by direct 16-byte global-to-LDS loads (no registers
+// involved), issued one stage ahead into the other of two buffers and shared
+// by the four waves, which read their operands from LDS; one barrier per
+// stage.  (Operand loads from global memory issued by each wave were consumed
+// in the k-step that issued them, the compiler rematerialising any prefetch,
+// so the waves waited on them.)  The compiler still waits for the direct
+// loads before a stage's first LDS read, as it cannot tell the buffers apart
+// (naming them statically needs the stage loop unrolled twice, which spills
+// the accumulators); two workgroups per CU cover that wait for each other.
+template <int NBLK> struct OccLds {
+    static constexpr int kSG = 32;                                    // grid points per stage
+    static constexpr int kRowB = 128 * NBLK;                          // bytes of one tile row
+    static constexpr int kChunks = kSG * kRowB / 1024;                // 1 KB direct-load chunks per stage
+    static constexpr int kStageB = kChunks * 1024 + 1024;             // + 32 positions of 32 bytes
+    static_assert(kChunks % 4 == 0, "chunks are dealt to 4 waves");
+};
+
 template <int KIND, int NBLK>
-__global__ __launch_bounds__(256, NBLK >= 8 ? 2 : 1) void k_build_K_occ(const d4* __restrict__ pos, const double* __restrict__ rho_occ,
-                                                     int ldO, int ngp, int g0, int rows, int n_rt, JasDev J,
-                                                     double* __restrict__ part, int seg_len) {
+__global__ __launch_bounds__(256, 2) void k_build_K_occ(const d4* __restrict__ pos,
+                                                            const double* __restrict__ rho_occ, int ldO, int ngp,
+                                                            int g0, int rows, int n_rt, JasDev J,
+                                                            double* __restrict__ part, int seg_len) {
+    typedef OccLds<NBLK> C;
+    typedef __attribute__((address_space(3))) void* lds_ptr;
+    __shared__ __attribute__((aligned(1024))) char sm[2][C::kStageB];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int rt = blockIdx.x % n_rt;
     const int ct = blockIdx.x / n_rt;
     const int gs = blockIdx.y * seg_len, ge = min(ngp, gs + seg_len);
+    const int nst = (ge - gs) / C::kSG;
     const int rloc0 = rt * kKRows + wave * kKRowsPerWave;   // first local row of this wave
     const int my = min(rloc0 + (lane & 15), rows - 1);      // row whose d^x this lane generates
     const d4 pg = pos[g0 + my];
-    const int kq = lane >> 4;
-    const int col = ct * 16 * NBLK + (lane & 15);
+    const int kq = lane >> 4, l16 = lane & 15;
+    const int col = ct * 16 * NBLK + l16;
+
+    // direct loads: chunk wave + 4 i of a stage is its bytes [1024 chunk, +1024),
+    // lane l the 16 of them at 1024 chunk + 16 l, in global memory and in LDS
+    // (uniform base addresses plus one 32-bit lane offset)
+    constexpr int kPer = C::kChunks / 4;
+    const char* tile0 = (const char*)(rho_occ + (size_t)ct * ngp * 16 * NBLK);
+    const uint32_t loff = 16 * lane;
+    auto issue = [&](int st, int buf) {
+        const char* ub = tile0 + (size_t)(gs + C::kSG * st) * C::kRowB + 1024 * wave;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i)
+            __builtin_amdgcn_global_load_lds((const void*)(ub + 4096 * i + loff),
+                                             (lds_ptr)(&sm[buf][1024 * (wave + 4 * i)]), 16, 0, 0);
+        if (wave == 0)
+            __builtin_amdgcn_global_load_lds((const void*)((const char*)(pos + gs + C::kSG * st) + loff),
+                                             (lds_ptr)(&sm[buf][1024 * C::kChunks]), 16, 0, 0);
+    };
 
     d4 acc[3][NBLK];
 #pragma unroll
@@ -124,48 +163,37 @@ __global__ __launch_bounds__(256, NBLK >= 8 ? 2 : 1) void k_build_K_occ(const d4
 #pragma unroll
         for (int c = 0; c < NBLK; ++c) acc[x][c] = (d4){0.0, 0.0, 0.0, 0.0};
 
-    // operands of the next two k-steps in flight (a k-step's MFMAs are too short
-    // to cover the load latency of the one after it); near the end of the
-    // segment the last k-step is re-read into the slot that is never consumed
-    const double* bp = rho_occ + (size_t)(gs + kq) * ldO + col;
-    const d4* pp = pos + gs + kq;
-    const int kl = ge - 4;                // last k-step of the segment
-    double b0[NBLK], b1[NBLK];
-    d4 p0, p1;
-#pragma unroll
-    for (int c = 0; c < NBLK; ++c) b0[c] = bp[16 * c];
-    p0 = *pp;
-    {
-        const size_t o = (size_t)(min(gs + 4, kl) - gs);
-#pragma unroll
-        for (int c = 0; c < NBLK; ++c) b1[c] = bp[o * ldO + 16 * c];
-        p1 = pp[o];
+    if (nst > 0) {
+        issue(0, 0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
     }
-    for (int kk = gs; kk < ge; kk += 4) {
-        double cb[NBLK];
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nst) issue(st + 1, buf ^ 1);
+        const char* tile = sm[buf];
+        const d4* sp = (const d4*)(tile + 1024 * C::kChunks);
+#pragma unroll 1
+        for (int t = 0; t < C::kSG / 4; ++t) {
+            const int k = 4 * t + kq;                      // this lane's point of the k-step
+            const d4 cp = sp[k];
+            const double* brow = (const double*)(tile + k * C::kRowB) + l16;
+            double cb[NBLK];
 #pragma unroll
-        for (int c = 0; c < NBLK; ++c) {
-            cb[c] = b0[c];
-            b0[c] = b1[c];
-        }
-        const d4 cp = p0;
-        p0 = p1;
-        {
-            const size_t o = (size_t)(min(kk + 8, kl) - gs);
+            for (int c = 0; c < NBLK; ++c) cb[c] = brow[16 * c];
+            const double dx = pg.x - cp.x, dy = pg.y - cp.y, dz = pg.z - cp.z;
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            const double f = du_over_r<KIND>(r2, J);
+            const double ax = dx * f, ay = dy * f, az = dz * f;
 #pragma unroll
-            for (int c = 0; c < NBLK; ++c) b1[c] = bp[o * ldO + 16 * c];
-            p1 = pp[o];
+            for (int c = 0; c < NBLK; ++c) {
+                acc[0][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, cb[c], acc[0][c], 0, 0, 0);
+                acc[1][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, cb[c], acc[1][c], 0, 0, 0);
+                acc[2][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, cb[c], acc[2][c], 0, 0, 0);
+            }
         }
-        const double dx = pg.x - cp.x, dy = pg.y - cp.y, dz = pg.z - cp.z;
-        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        const double f = du_over_r<KIND>(r2, J);
-        const double ax = dx * f, ay = dy * f, az = dz * f;
-#pragma unroll
-        for (int c = 0; c < NBLK; ++c) {
-            acc[0][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, cb[c], acc[0][c], 0, 0, 0);
-            acc[1][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, cb[c], acc[1][c], 0, 0, 0);
-            acc[2][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, cb[c], acc[2][c], 0, 0, 0);
-        }
+        __builtin_amdgcn_s_waitcnt(0);                     // this wave's loads of the next stage
+        __syncthreads();                                   // everyone's, and this stage read by all
     }
     double* out = part + (size_t)blockIdx.y * 3 * rows * ldO;
 #pragma unroll

@@ -54,6 +54,19 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 (&t)[NS]) {
     }
 }
 
+// split_bf16 for two values at once (packed round-to-nearest conversions).
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+template <int NS>
+__device__ __forceinline__ void split_bf16_pair(f2 x, bf2 (&t)[NS]) {
+    t[0] = __builtin_convertvector(x, bf2);
+    if constexpr (NS > 1) {
+        const f2 r1 = x - __builtin_convertvector(t[0], f2);
+        t[1] = __builtin_convertvector(r1, bf2);
+        if constexpr (NS > 2) t[2] = __builtin_convertvector(r1 - __builtin_convertvector(t[1], f2), bf2);
+    }
+}
+
 // The split products of a form as (A-term, B-term) index pairs.  Callers loop
 // over terms outermost, so consecutive MFMAs write different accumulators and
 // never wait on each other's results.
@@ -144,6 +157,32 @@ __global__ __launch_bounds__(256) void k_pack_lp(const double* __restrict__ src,
 // 2^-16 .. 2^-24 relative error, so IEEE division and square root would buy
 // nothing).  Exactly 0 at r^2 == 0.
 template <int KIND>
+__device__ __forceinline__ float du_over_r_fast(float r2, const JasDev& J);
+
+// The same without the r^2 == 0 branch, for d^x = (x - x') u'(r)/r: the caller
+// passes r^2 + kR2Floor, so the value stays finite at coincident points, where
+// the difference vector it multiplies is exactly zero (d^x = 0 exactly, as the
+// branch gives).  kR2Floor is far below every r^2 the grid produces between
+// distinct points (it moves a distance of 1e-6 bohr by 5e-19 relative).
+constexpr float kR2Floor = 1e-30f;
+template <int KIND>
+__device__ __forceinline__ float du_over_r_nz(float r2, const JasDev& J) {
+    const float rs = __builtin_amdgcn_rsqf(r2);      // 1/r
+    const float r = r2 * rs;
+    if constexpr (KIND == 0) {
+        const float t = __builtin_amdgcn_rcpf(fmaf(J.fb, r, 1.0f));
+        return 0.5f * rs * t * t;
+    } else {
+        const float q = __builtin_amdgcn_rcpf(1.0f + r);
+        const float t = r * q;
+        float p = J.fdcoef[15];
+#pragma unroll
+        for (int k = 14; k >= 0; --k) p = fmaf(p, t, J.fdcoef[k]);
+        return p * q * q * rs;
+    }
+}
+
+template <int KIND>
 __device__ __forceinline__ float du_over_r_fast(float r2, const JasDev& J) {
     const float rs = __builtin_amdgcn_rsqf(r2);      // 1/r
     const float r = r2 * rs;
@@ -232,8 +271,14 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
     // positions of the 32 g' of one k-step as x[], y[], z[], pad[] (double
     // buffered).  Each wave stages its own copy with one coalesced 16-byte load
     // per lane; a wave's LDS accesses execute in order, so no barrier is
-    // involved, and the copy replaces 32-fold redundant global loads.
-    typedef double PTile[4][kLpK];
+    // involved, and the copy replaces 32-fold redundant global loads.  The
+    // split-BF16 forms keep them in FP32 and form the differences in FP32:
+    // rounding a position (|x| < 20 bohr) to FP32 moves it by at most 1e-6
+    // bohr, a relative change of d below 1e-6 for r > 1 bohr and below the
+    // 2^-16 of the split operands for r > 0.07 bohr; the FP32 form, whose
+    // operands keep 2^-24, takes the differences in FP64 and rounds them once.
+    typedef typename std::conditional<FORM == 1, double, float>::type PosT;
+    typedef PosT PTile[4][kLpK];
     __shared__ __attribute__((aligned(16))) PTile sP0[kLpThreads / 64];
     __shared__ __attribute__((aligned(16))) PTile sP1[kLpThreads / 64];
 
@@ -268,6 +313,7 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
     const int grow = 4 * (threadIdx.x >> 6) + 2 * ((threadIdx.x >> 4) & 1) + ((threadIdx.x >> 5) & 1);
     const int gk = 2 * (threadIdx.x & 15);
     const d4 pr = pos[g0 + min(rt * kLpRows + grow, rows - 1)];
+    const PosT prx = (PosT)pr.x, pry = (PosT)pr.y, prz = (PosT)pr.z;
     // MFMA role
     const int l16 = lane & 15, lk = lane >> 4;
     const int col0 = ct * kWgCols + wave * 16 * NB + l16;
@@ -286,24 +332,29 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
     // position staging: lane l holds half (x,y or z,pad) of position l/2 of a
     // k-step, loaded one k-step before it is stored to LDS (no branches, so the
     // wait for it does not also wait for the operand prefetch)
+    // (addresses: a uniform base per k-step plus a fixed 32-bit lane offset,
+    // so the address arithmetic stays scalar)
     const int sq = lane >> 1, shalf = lane & 1;
     typedef double dbl2 __attribute__((ext_vector_type(2)));
+    typedef PosT pos2 __attribute__((ext_vector_type(2)));
+    const uint32_t s_off = (uint32_t)((4 * sq + 2 * shalf) * sizeof(double));
     dbl2 pstage;
     auto loadS = [&](int kk) {
-        pstage = *(const dbl2*)((const double*)pos + 4 * (size_t)(kk + sq) + 2 * shalf);
+        const char* ub = (const char*)pos + (size_t)kk * 4 * sizeof(double);
+        pstage = *(const dbl2*)(ub + s_off);
     };
     auto storeS = [&](PTile& P, const dbl2 v) {
-        P[2 * shalf][sq] = v.x;
-        P[2 * shalf + 1][sq] = v.y;
+        P[2 * shalf][sq] = (PosT)v.x;
+        P[2 * shalf + 1][sq] = (PosT)v.y;
     };
     auto gen = [&](const PTile& P, ATile& W) {
-        const dbl2 px = *(const dbl2*)&P[0][gk], py = *(const dbl2*)&P[1][gk], pz = *(const dbl2*)&P[2][gk];
+        const pos2 px = *(const pos2*)&P[0][gk], py = *(const pos2*)&P[1][gk], pz = *(const pos2*)&P[2][gk];
         float a[NC][2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const float dx = (float)(pr.x - px[j]), dy = (float)(pr.y - py[j]), dz = (float)(pr.z - pz[j]);
+            const float dx = (float)(prx - px[j]), dy = (float)(pry - py[j]), dz = (float)(prz - pz[j]);
             if constexpr (NC == 3) {
-                const float f = du_over_r_fast<KIND>(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), J);
+                const float f = du_over_r_nz<KIND>(fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, kR2Floor))), J);
                 a[0][j] = dx * f;
                 a[1][j] = dy * f;
                 a[2][j] = dz * f;
@@ -317,32 +368,31 @@ __global__ __launch_bounds__(kLpThreads) void k_build_K_lp(const d4* __restrict_
                 W[c][0][grow][gk] = a[c][0];
                 W[c][0][grow][gk + 1] = a[c][1];
             } else {
-                __bf16 t0[NS], t1[NS];
-                split_bf16<NS>(a[c][0], t0);
-                split_bf16<NS>(a[c][1], t1);
+                // the two g' of the lane split together: one packed conversion
+                // per piece, and each piece stored as one 32-bit word
+                bf2 t[NS];
+                split_bf16_pair<NS>((f2){a[c][0], a[c][1]}, t);
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    W[c][s][grow][gk] = t0[s];
-                    W[c][s][grow][gk + 1] = t1[s];
-                }
+                for (int s = 0; s < NS; ++s) *(bf2*)&W[c][s][grow][gk] = t[s];
             }
         }
     };
 
     // pair-density operand of the wave's 4 column blocks for one k-step
     typedef typename std::conditional<FORM == 1, f4[NB][2], bf8[NB][NS]>::type BOp;
+    const uint32_t b_off = (uint32_t)(((size_t)lk * ldL + col0) * 8 * sizeof(T));   // lane offset, bytes
     auto loadB = [&](int kk, BOp& out) {
-        const size_t o = ((size_t)(kk / 8 + lk) * ldL + col0) * 8;
+        const char* ub = (const char*)rho_lp + (size_t)(kk / 8) * ldL * 8 * sizeof(T);   // uniform
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             if constexpr (FORM == 1) {
-                const f4* p = (const f4*)((const float*)rho_lp + o + 128 * b);
+                const f4* p = (const f4*)(ub + b_off + 128 * b * sizeof(T));
                 out[b][0] = p[0];
                 out[b][1] = p[1];
             } else {
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
-                    out[b][s] = *(const bf8*)((const __bf16*)rho_lp + s * split_stride + o + 128 * b);
+                    out[b][s] = *(const bf8*)(ub + s * split_stride * sizeof(T) + b_off + 128 * b * sizeof(T));
             }
         }
     };
@@ -740,7 +790,8 @@ __global__ void k_reduce_M(const float* __restrict__ part, int nseg, size_t sstr
 
 // --------------------------------------------------------------------------
 // Occupied-occupied pairs: colmap[j] = pair(occ[a], occ[b]) for a <= b (j in
-// row-major order of (a, b)); rho_occ[g][j] = rho[g][colmap[j]], zero padded.
+// row-major order of (a, b)); rho_occ = rho[g][colmap[j]] in column tiles of
+// tw pairs, tile-major ([ldO / tw][ngp][tw]), zero padded.
 __global__ void k_occ_pairs(OccList occ, int N, int* __restrict__ colmap, int ldO) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= ldO) return;
@@ -769,13 +820,14 @@ __global__ void k_reduce_occ(const double* __restrict__ part, int nseg, int rows
 }
 
 __global__ void k_gather_occ(const double* __restrict__ rho, int ldP, int ngp, const int* __restrict__ colmap,
-                             int ldO, double* __restrict__ rho_occ) {
+                             int ldO, int tw, double* __restrict__ rho_occ) {
+    // column tiles of tw pairs, each [ngp][tw] contiguous: rho_occ[(j / tw) ngp tw + g tw + j % tw]
     const size_t n = (size_t)ngp * ldO;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const int j = (int)(i % ldO);
         const size_t g = i / ldO;
         const int P = colmap[j];
-        rho_occ[i] = P >= 0 ? rho[g * ldP + P] : 0.0;
+        rho_occ[((size_t)(j / tw) * ngp + g) * tw + j % tw] = P >= 0 ? rho[g * ldP + P] : 0.0;
     }
 }
 

@@ -6,7 +6,8 @@
 //   pos    [ngp] x 4 doubles          grid positions (x, y, z, 0)
 //   rho    [ngp][ldP] doubles         weighted pair densities, zero padded
 //   rho_lp [NS][ngp/8][ldL][8]        reduced-precision rho (k8-packed), prec != FP64
-//   rho_occ[ngp][ldO], colmap[ldO]    FP64 rho of the occupied-occupied pairs
+//   rho_occ[ldO/tw][ngp][tw], colmap[ldO]  FP64 rho of the occupied-occupied pairs
+//                                     (column tiles of tw = 16 occNB pairs)
 //   M      [ldP][ldP] doubles         FP64 accumulator of the two-body term
 //   h1acc  [ldP] doubles              FP64 accumulator of the one-body term
 //   T1     [kT1Split][ldP] doubles    per-split partials (one-body, term 1)
@@ -29,9 +30,9 @@
 // ldL = ldP rounded up to 512.  The chunk capacity `cap` is the largest
 // multiple of 32 rows that fits in the bytes the caller passes, so every call
 // with the same ws_bytes agrees on it.  The segment partials of the reduced
-// forms are bounded: the K build runs over a chunk in row pieces of at most
-// kcap rows (kcap = min(cap, the multiple of 1024 rows whose partials fit
-// kKpartBudget bytes, at least 1024)), and the two-body GEMM over groups of
+// forms are bounded: the K build runs over a chunk in equal row pieces of at
+// most kcap rows (kcap = min(cap, the multiple of 1024 rows whose partials
+// fit kKpartBudget bytes, at least 1024)), and the two-body GEMM over groups of
 // kMSegGroup row segments, each piece reduced into its FP64 result before the
 // next one reuses the partial buffer.
 #include <hip/hip_runtime.h>
@@ -101,7 +102,7 @@ constexpr int kSegK = 8192, kSegKF32 = 1024;
 constexpr int kSegM = 2048, kSegMF32 = 512;
 constexpr int kRowQuant = 32;
 constexpr int kOccSegMax = 32;  // most segments of the FP64 occupied-block sum over g'
-constexpr size_t kKpartBudget = (size_t)8 << 30;   // bytes of K-build segment partials
+constexpr size_t kKpartBudget = (size_t)16 << 30;  // bytes of K-build segment partials
 constexpr int kKpartQuant = 1024;                  // rows: 32 row tiles, one XCD's resident set
 constexpr int kMSegGroup = 2;                      // row segments per two-body GEMM launch
 
@@ -466,7 +467,7 @@ int launch_build_occ_nb(const Layout& L, int g0, int rows, int n_rt, const JasDe
         return 0;
     const long tiles = (long)n_rt * (L.ldO / (16 * NB));
     const int want = occ_segments(tiles, (long)std::max(cus, 1) * std::max(per_cu, 1));
-    const int seg_len = (int)align_up((size_t)((L.ngp + want - 1) / want), 4);
+    const int seg_len = (int)align_up((size_t)((L.ngp + want - 1) / want), 32);   // whole 32-point stages
     const int nseg = (L.ngp + seg_len - 1) / seg_len;   // every segment starts inside the grid
     const dim3 grid((unsigned)tiles, nseg);
     hipLaunchKernelGGL((k_build_K_occ<KIND, NB>), grid, dim3(256), 0, st, at<d4>(ws, L.pos), at<double>(ws, L.rho_occ),
@@ -490,13 +491,17 @@ int launch_build_occ(const Layout& L, int g0, int rows, int n_rt, const JasDev& 
 }
 
 // The split K build of rows [g0, g0 + rows) (nc = 3: K, or nc = 1: F of the
-// TC integrals) in pieces of at most kcap rows: segment partials, then their
-// FP64 sum into out[c][r][P] (component stride `rows` rows).
+// TC integrals) in equal pieces (multiples of 32 rows) of at most kcap rows:
+// segment partials, then their FP64 sum into out[c][r][P] (component stride
+// `rows` rows).  Each piece costs about a millisecond of launch ramp and tail
+// at N=160, so the pieces are as few as the partial buffer allows.
 template <int NC>
 xtc_status build_lp_pieces(const Layout& L, int g0, int rows, const JasDev& J, double* out, void* ws, hipStream_t st) {
     xtc_status s;
-    for (int r0 = 0; r0 < rows; r0 += L.kcap) {
-        const int nr = std::min(L.kcap, rows - r0);
+    const int npiece = (rows + L.kcap - 1) / L.kcap;
+    const int piece = std::min(L.kcap, (int)align_up((size_t)((rows + npiece - 1) / npiece), kRowQuant));
+    for (int r0 = 0; r0 < rows; r0 += piece) {
+        const int nr = std::min(piece, rows - r0);
         if (J.kind == 0) {
             if (L.form == 1) launch_build_lp<0, 1, NC>(L, g0 + r0, nr, J, ws, st);
             else if (L.form == 3) launch_build_lp<0, 3, NC>(L, g0 + r0, nr, J, ws, st);
@@ -727,7 +732,7 @@ xtc_status xtc_prepare(const xtc_problem* pb, int32_t prec, int32_t chunk_rows, 
                            at<int>(ws, L.colmap), L.ldO);
         if ((s = launched("occ_pairs")) != XTC_OK) return s;
         hipLaunchKernelGGL(k_gather_occ, dim3(4096), dim3(256), 0, st, at<double>(ws, L.rho), L.ldP, L.ngp,
-                           at<int>(ws, L.colmap), L.ldO, at<double>(ws, L.rho_occ));
+                           at<int>(ws, L.colmap), L.ldO, 16 * L.occNB, at<double>(ws, L.rho_occ));
         if ((s = launched("gather_occ")) != XTC_OK) return s;
         // the adjoint's Pi operand: k-packed splits of rho (FP32: row-major)
         if (L.bwd && L.form == 1 &&

@@ -441,8 +441,12 @@ class XtcFunction:
     The backward calls xtc_backward with the incoming output gradients as seeds
     (K is recomputed there, never stored)."""
 
-    @staticmethod
-    def _cls():
+    _F = None         # the torch.autograd.Function subclass, made on first use
+
+    @classmethod
+    def _cls(cls):
+        if cls._F is not None:
+            return cls._F
         import torch
 
         class _F(torch.autograd.Function):
@@ -463,6 +467,7 @@ class XtcFunction:
                              gh1.contiguous() if gh1 is not None else None, gE, ctx.prec, ctx.chunk)
                 return g.to(coef.dtype).to(coef.device), None, None, None
 
+        cls._F = _F
         return _F
 
     @classmethod
