@@ -12,7 +12,7 @@ import pytest
 from paper_2304_07006_amd import inputs
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-STORED = ["N128-occ16-Ng150k", "N96-occ12-Ng100k"]
+STORED = ["N128-occ16-Ng150k", "N96-occ12-Ng100k", "N160-occ20-Ng250k"]
 
 
 def _load(name):

@@ -283,17 +283,19 @@ def test_full_size_adjoint_central_differences(torch_cuda):
 
 def test_largest_workload_forward_and_adjoint(torch_cuda):
     """N=160, 20 occupied, Ng=250 000, split BF16 x3 in 20 chunks (bench.py
-    --backward --workload N160-occ20-Ng250k): forward outputs against the FP64
-    path to the bars, c . dL/dc = 2 L to 1e-5 with K recomputed in the
+    --backward --workload N160-occ20-Ng250k): forward outputs against the
+    stored oracle values on occ + 8 virtual orbitals and the FP64 path to the
+    bars (the FP64 path to the oracle's 1e-11), c . dL/dc = 2 L to 1e-5 with K recomputed in the
     adjoint, and the peak device memory of the split-BF16 forward + adjoint
     within its stated bound (the larger of the two workspaces plus the
     outputs, the loss weights and the K chunk, plus 2%)."""
     import bench
     from paper_2304_07006_amd import xtc
     wl = inputs.WORKLOADS["N160-occ20-Ng250k"]
-    p = inputs.make_workload(wl.name)
+    gold = _load_golden(wl.name)
+    p = _regenerate(wl.name, gold)
     chunk = _chunk("bf16x3", p.Ng)
-    _note(f"case: {wl.name} forward + adjoint bf16x3, chunk={chunk}")
+    _note(f"case: {wl.name} forward + adjoint bf16x3, chunk={chunk}; forward vs the stored oracle values")
     torch_cuda.cuda.reset_peak_memory_stats()
     keep = {}
     tf, tb, g, euler, peak = bench.run_backward(p, "bf16x3", chunk, wl.aux_seed, 1, 0, keep)
@@ -310,9 +312,11 @@ def test_largest_workload_forward_and_adjoint(torch_cuda):
     assert peak <= bound
     del dp
     torch_cuda.cuda.empty_cache()
-    V2r, h1r, E0r = xtc.forward(p, prec="fp64", chunk_rows=_chunk("fp64", p.Ng))
-    eV = np.abs(keep["V2"] - V2r.cpu().numpy()).max()
-    eh = np.abs(keep["h1"] - h1r.cpu().numpy()).max()
-    eE = abs(keep["E0"] - float(E0r.cpu()[0]))
-    _note(f"  bf16x3 vs fp64: |dV2| {eV:.2e} |dh1| {eh:.2e} |dE0| {eE:.2e} (E0 {float(E0r.cpu()[0]):.10f})")
+    _against_golden(gold, keep["V2"], keep["h1"], keep["E0"], "bf16x3")
+    V2r, h1r, E0r = (t.cpu().numpy() for t in xtc.forward(p, prec="fp64", chunk_rows=_chunk("fp64", p.Ng)))
+    _against_golden(gold, V2r, h1r, float(E0r[0]), "fp64")
+    eV = np.abs(keep["V2"] - V2r).max()
+    eh = np.abs(keep["h1"] - h1r).max()
+    eE = abs(keep["E0"] - float(E0r[0]))
+    _note(f"  bf16x3 vs fp64: |dV2| {eV:.2e} |dh1| {eh:.2e} |dE0| {eE:.2e} (E0 {float(E0r[0]):.10f})")
     assert eV < BARS[0] and eh < BARS[1] and eE < BARS[2]
