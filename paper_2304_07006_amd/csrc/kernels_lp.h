@@ -660,27 +660,50 @@ __global__ __launch_bounds__(256) void k_gemm_tn_lp(const void* __restrict__ Clp
 // Workgroup 512 threads = 8 waves as 4 (P) x 2 (R), tile 256 (P) x 256 (R),
 // wave tile 64 x 128 (4 x 8 MFMA blocks, as in k_gemm_tn_lp).  Per k-step (32
 // grid rows) the k8-packed tiles of C and D (256 columns each, all splits)
-// are copied once into LDS through registers (the next k-step's copy is
-// loaded while the current one is multiplied) and read by the 2 (C) and 4 (D)
-// waves that share them, instead of every wave fetching its own.  An LDS row
-// (one 8-row group of one split, 256 columns x 16 bytes) is padded by 128
-// bytes, so each 16-lane phase of a b128 read covers all 64 banks.
+// are copied into LDS by direct 16-byte global-to-LDS loads (no registers
+// involved), issued one k-step ahead, and read by the 2 (C) and 4 (D) waves
+// that share them, instead of every wave fetching its own.  An LDS row (one
+// 8-row group of one split, 256 columns x 16 bytes, 4 KB contiguous in
+// global memory) is padded by 128 bytes, so each 16-lane phase of a b128
+// read covers all 64 banks.  The two k-step buffers are separate objects,
+// each named statically where it is filled or read (the k-step loop runs
+// two k-steps per iteration): the compiler then knows that the reads of one
+// need not wait for the loads into the other.
+// Tiles are dealt to the XCDs (workgroup x runs on XCD x % 8) in contiguous
+// ranges of a banded order (bands of kTnBand P tiles, R fastest within a
+// band), so the ~32 workgroups resident on an XCD cover about 4 P x 8 R
+// tiles and share 12 operand strips through its L2.
 // ldC and ldD are multiples of 256; (component, grid row) k-steps of a
 // workgroup's group and segment run as one sequence.
 constexpr int kTnThreads = 512;
+constexpr int kTnBand = 4;
 template <int FORM>
 __global__ __launch_bounds__(kTnThreads) void k_gemm_tn_lds(const void* __restrict__ Clp, int ldC, size_t c_split,
                                                             const void* __restrict__ Dlp, int ldD, size_t d_split,
-                                                            int rows32, int n_pt, int pmax, int rmax, int cpw,
-                                                            int seg_len, int nseg_r, float* __restrict__ part) {
+                                                            int rows32, int n_pt, int n_rt, int per_xcd, int pmax,
+                                                            int rmax, int cpw, int seg_len, int nseg_r,
+                                                            float* __restrict__ part) {
     static_assert(FORM == 3 || FORM == 6, "split-BF16 forms only");
+    typedef __attribute__((address_space(3))) void* lds_ptr;
     constexpr int NS = Lp<FORM>::NS;
     constexpr int kRowB = 256 * 16 + 128;           // bytes of one (split, 8-row group) LDS row
     constexpr int kTileB = NS * 4 * kRowB;          // one operand's tile of one k-step
-    constexpr int kVec = NS * 4 * 256 / kTnThreads; // 16-byte vectors per thread and operand
-    __shared__ __attribute__((aligned(16))) char sm[2][2][kTileB];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int pt = blockIdx.x % n_pt, rt = blockIdx.x / n_pt;
+    constexpr int kChunks = 2 * NS * 4 * 4;         // 1 KB direct-load chunks per k-step (both operands)
+    constexpr int kPerW = kChunks / 8;              // per wave
+    __shared__ __attribute__((aligned(1024))) char sm0[2 * kTileB];   // C, then D, of even k-steps
+    __shared__ __attribute__((aligned(1024))) char sm1[2 * kTileB];   // odd k-steps
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int pt, rt;
+    {
+        const int loc = blockIdx.x >> 3, t = (blockIdx.x & 7) * per_xcd + loc;
+        if (loc >= per_xcd || t >= n_pt * n_rt) return;
+        const int band = min(t / (kTnBand * n_rt), (n_pt - 1) / kTnBand);
+        const int r = t - band * kTnBand * n_rt;
+        const int gw = min(kTnBand, n_pt - band * kTnBand);
+        pt = band * kTnBand + r % gw;
+        rt = r / gw;
+    }
     if (pt * 256 >= pmax || rt * 256 >= rmax) return;
     const int c0 = (blockIdx.y / nseg_r) * cpw, sg = blockIdx.y % nseg_r;
     const int gs = sg * seg_len, ge = min(rows32, gs + seg_len);
@@ -688,35 +711,23 @@ __global__ __launch_bounds__(kTnThreads) void k_gemm_tn_lds(const void* __restri
     const int nq = nk * cpw;
     const int l16 = lane & 15, lk = lane >> 4;
     const int wp = wave & 3, wr = wave >> 2;
-    const __bf16* Cb = (const __bf16*)Clp;
-    const __bf16* Db = (const __bf16*)Dlp;
+    const uint32_t loff = 16 * lane;
 
-    // loader role: vector v = tid + 512 i is (split s, 8-row group g8, column col)
-    int lcol[kVec], lg8[kVec], ls[kVec];
-#pragma unroll
-    for (int i = 0; i < kVec; ++i) {
-        const int v = threadIdx.x + kTnThreads * i;
-        lcol[i] = v & 255;
-        lg8[i] = (v >> 8) & 3;
-        ls[i] = v >> 10;
-    }
-    bf8 sc[kVec], sd[kVec];
-    auto load = [&](int q) {
+    // chunk j = wave + 8 i (i < kPerW / 2) of each operand's tile: LDS row
+    // (split, 8-row group) j / 4 = wave / 4 + 2 i, its 1 KB piece wave % 4
+    const uint32_t lpiece = 1024 * (wave & 3) + loff;
+    const char* cbase = (const char*)Clp + (size_t)pt * 256 * 16;
+    const char* dbase = (const char*)Dlp + (size_t)rt * 256 * 16;
+    auto issue = [&](int q, char* buf) {
         const int comp = c0 + q / nk, g8 = (gs + kLpK * (q % nk)) / 8;
-        const __bf16* cb = Cb + (size_t)comp * NS * c_split;
-        const __bf16* db = Db + (size_t)comp * NS * d_split;
 #pragma unroll
-        for (int i = 0; i < kVec; ++i) {
-            sc[i] = *(const bf8*)(cb + ls[i] * c_split + ((size_t)(g8 + lg8[i]) * ldC + pt * 256 + lcol[i]) * 8);
-            sd[i] = *(const bf8*)(db + ls[i] * d_split + ((size_t)(g8 + lg8[i]) * ldD + rt * 256 + lcol[i]) * 8);
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < kVec; ++i) {
-            const int o = (ls[i] * 4 + lg8[i]) * kRowB + lcol[i] * 16;
-            *(bf8*)(&sm[buf][0][o]) = sc[i];
-            *(bf8*)(&sm[buf][1][o]) = sd[i];
+        for (int i = 0; i < kPerW / 2; ++i) {
+            const int row = (wave >> 2) + 2 * i, sp = row >> 2, gg = row & 3;
+            const char* cs = cbase + ((size_t)comp * NS + sp) * c_split * 2 + (size_t)(g8 + gg) * ldC * 16;
+            const char* ds = dbase + ((size_t)comp * NS + sp) * d_split * 2 + (size_t)(g8 + gg) * ldD * 16;
+            char* dst = buf + row * kRowB + 1024 * (wave & 3);
+            __builtin_amdgcn_global_load_lds((const void*)(cs + lpiece), (lds_ptr)dst, 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)(ds + lpiece), (lds_ptr)(dst + kTileB), 16, 0, 0);
         }
     };
 
@@ -725,38 +736,44 @@ __global__ __launch_bounds__(kTnThreads) void k_gemm_tn_lds(const void* __restri
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
-    auto multiply = [&](int buf) {
+    auto multiply = [&](const char* buf) {
         bf8 av[4][NS];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int s = 0; s < NS; ++s)
-                av[i][s] = *(const bf8*)&sm[buf][0][(s * 4 + lk) * kRowB + (64 * wp + 16 * i + l16) * 16];
+                av[i][s] = *(const bf8*)&buf[(s * 4 + lk) * kRowB + (64 * wp + 16 * i + l16) * 16];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             bf8 bv[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s)
-                bv[s] = *(const bf8*)&sm[buf][1][(s * 4 + lk) * kRowB + (128 * wr + 16 * j + l16) * 16];
+                bv[s] = *(const bf8*)&buf[kTileB + (s * 4 + lk) * kRowB + (128 * wr + 16 * j + l16) * 16];
 #pragma unroll
             for (int t = 0; t < Terms<FORM>::n; ++t)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     acc[i][j] = mma_bf16(av[i][Terms<FORM>::a[t]], bv[Terms<FORM>::b[t]], acc[i][j]);
         }
+        __builtin_amdgcn_s_waitcnt(0);              // this wave's loads of the next k-step
+        __syncthreads();                            // everyone's, and this k-step read by all
     };
     if (nq > 0) {
-        load(0);
-        store(0);
+        issue(0, sm0);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        for (int q = 0; q < nq; ++q) {
-            const int cur = q & 1;
-            if (q + 1 < nq) load(q + 1);     // uniform branch
-            multiply(cur);
-            if (q + 1 < nq) store(cur ^ 1);
-            __syncthreads();
-        }
     }
+    // even k-steps from sm0, odd ones from sm1, each k-step's successor
+    // loaded into the other buffer while it is multiplied; an odd last k-step
+    // (in sm0) after the loop
+    int q = 0;
+    for (; q + 1 < nq; q += 2) {
+        issue(q + 1, sm1);
+        multiply(sm0);
+        if (q + 2 < nq) issue(q + 2, sm0);
+        multiply(sm1);
+    }
+    if (q < nq) multiply(sm0);
     float* out = part + (size_t)blockIdx.y * ldC * ldD;
 #pragma unroll
     for (int i = 0; i < 4; ++i)

@@ -549,11 +549,13 @@ xtc_status gemm_tn_lp(int form, const void* C, int ldC, size_t c_split, const vo
                       hipStream_t st) {
     const int nseg_r = (rows32 + seg_len - 1) / seg_len;
     if (form == 3 && ldC % 256 == 0 && ldD % 256 == 0) {
-        // both operands staged in LDS (256 x 256 tiles)
-        const int n_pt = ldC / 256, n_rt = ldD / 256;
-        const dim3 grid(n_pt * n_rt, (ncomp / cpw) * nseg_r);
+        // both operands staged in LDS (256 x 256 tiles over [0, pmax) x [0, rmax)),
+        // dealt to the 8 XCDs in ranges of per_xcd tiles
+        const int n_pt = (pmax + 255) / 256, n_rt = (rmax + 255) / 256;
+        const int per_xcd = (n_pt * n_rt + 7) / 8;
+        const dim3 grid(8 * per_xcd, (ncomp / cpw) * nseg_r);
         hipLaunchKernelGGL((k_gemm_tn_lds<3>), grid, dim3(kTnThreads), 0, st, C, ldC, c_split, D, ldD, d_split, rows32,
-                           n_pt, pmax, rmax, cpw, seg_len, nseg_r, part);
+                           n_pt, n_rt, per_xcd, pmax, rmax, cpw, seg_len, nseg_r, part);
         *nparts = (int)grid.y;
         return launched("gemm_tn_lds");
     }
