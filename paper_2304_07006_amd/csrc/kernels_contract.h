@@ -28,13 +28,15 @@ struct OccList {
 // --------------------------------------------------------------------------
 // Intermediates.  One workgroup handles one grid point at a time (grid-stride
 // over the rows of the chunk).  The occupied columns (rho_rk, K_rk) of that
-// point are gathered into LDS as [nocc][N][4]; each thread then owns 4x4
+// point are gathered into LDS as [nocc][N][4] (each thread's loads of up to
+// kIGather entries issued together); each thread then owns 4x4
 // output blocks (r-block <= s-block) of the upper triangle and accumulates
 // Zt and Z over k with register blocking.
 // One spin channel s per launch: Z~ and Z carry the occupations n_k of that
 // spin, W and W~ those of the total density.  Per-point scalars
 // S[g] = (W~/2, W/2 (3), sum_k n_k A_kk, sum_k n_k B_kk (3)) feed the one-body
 // reduction.
+constexpr int kIGather = 4;
 __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict__ rho_rows,
                                                        const double* __restrict__ K, int rows,
                                                        int ldP, int N, OccList occ,
@@ -49,10 +51,21 @@ __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict_
     for (int g = blockIdx.x; g < rows; g += gridDim.x) {
         const double* rg = rho_rows + (size_t)g * ldP;
         const double* kg = K + (size_t)g * ldP;
-        for (int idx = threadIdx.x; idx < n * N; idx += blockDim.x) {
-            const int kk = idx / N, r = idx % N;
-            const int P = pair_sym(r, occ.k[kk], N);
-            locc[idx] = (d4){rg[P], kg[P], kg[kstride + P], kg[2 * kstride + P]};
+        // every thread issues the loads of up to kIGather entries before storing
+        for (int base = threadIdx.x; base < n * N; base += kIGather * 256) {
+            d4 e[kIGather];
+#pragma unroll
+            for (int u = 0; u < kIGather; ++u) {
+                const int idx = base + 256 * u;
+                if (idx < n * N) {
+                    const int kk = idx / N, r = idx % N;
+                    const int P = pair_sym(r, occ.k[kk], N);
+                    e[u] = (d4){rg[P], kg[P], kg[kstride + P], kg[2 * kstride + P]};
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kIGather; ++u)
+                if (base + 256 * u < n * N) locc[base + 256 * u] = e[u];
         }
         __syncthreads();
         if (threadIdx.x < 64) {
