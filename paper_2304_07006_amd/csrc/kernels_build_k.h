@@ -103,15 +103,20 @@ __global__ __launch_bounds__(256) void k_build_K_f64(const d4* __restrict__ pos,
 // 16 rows and NBLK 16-column blocks of all 3 components, so each FP64 d^x
 // value a lane generates feeds 3 NBLK MFMAs (the host picks NBLK).  Each
 // 32-point stage of the tile (32 x 16 NBLK doubles, contiguous) and its 32
-// positions are copied by direct 16-byte global-to-LDS loads (no registers
-// involved), issued one stage ahead into the other of two buffers and shared
-// by the four waves, which read their operands from LDS; one barrier per
-// stage.  (Operand loads from global memory issued by each wave were consumed
-// in the k-step that issued them, the compiler rematerialising any prefetch,
-// so the waves waited on them.)  The compiler still waits for the direct
-// loads before a stage's first LDS read, as it cannot tell the buffers apart
-// (naming them statically needs the stage loop unrolled twice, which spills
-// the accumulators); two workgroups per CU cover that wait for each other.
+// positions are copied by direct 16-byte buffer-to-LDS loads (no registers
+// involved; a buffer descriptor per stage in scalar registers, one 32-bit
+// lane offset), issued one stage ahead into the other of two buffers and
+// shared by the four waves, which read their operands from LDS; one barrier
+// per stage.  The two buffers are separate objects named statically where
+// they are filled or read (the stage loop runs two stages per iteration, with
+// no exit in between), and the positions are read from LDS as scalars: the
+// compiler then knows that a stage's reads need not wait for the loads still
+// filling the other buffer.  (Operand loads from global memory issued by each
+// wave were consumed in the k-step that issued them, the compiler
+// rematerialising any prefetch, so the waves waited on them; with one buffer
+// indexed by stage parity, 64-bit load addresses in vector registers or
+// vector-typed position reads, the compiler waited for the next stage's loads
+// before the first LDS read of each stage.)
 template <int NBLK> struct OccLds {
     static constexpr int kSG = 32;                                    // grid points per stage
     static constexpr int kRowB = 128 * NBLK;                          // bytes of one tile row
@@ -119,6 +124,8 @@ template <int NBLK> struct OccLds {
     static constexpr int kStageB = kChunks * 1024 + 1024;             // + 32 positions of 32 bytes
     static_assert(kChunks % 4 == 0, "chunks are dealt to 4 waves");
 };
+// Word 3 of a raw (untyped, unswizzled) buffer descriptor on gfx9-family GPUs.
+constexpr int kRawBufferWord3 = 0x00020000;
 
 template <int KIND, int NBLK>
 __global__ __launch_bounds__(256, 2) void k_build_K_occ(const d4* __restrict__ pos,
@@ -127,7 +134,8 @@ __global__ __launch_bounds__(256, 2) void k_build_K_occ(const d4* __restrict__ p
                                                             double* __restrict__ part, int seg_len) {
     typedef OccLds<NBLK> C;
     typedef __attribute__((address_space(3))) void* lds_ptr;
-    __shared__ __attribute__((aligned(1024))) char sm[2][C::kStageB];
+    __shared__ __attribute__((aligned(1024))) char sm0[C::kStageB];
+    __shared__ __attribute__((aligned(1024))) char sm1[C::kStageB];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int rt = blockIdx.x % n_rt;
@@ -142,19 +150,21 @@ __global__ __launch_bounds__(256, 2) void k_build_K_occ(const d4* __restrict__ p
 
     // direct loads: chunk wave + 4 i of a stage is its bytes [1024 chunk, +1024),
     // lane l the 16 of them at 1024 chunk + 16 l, in global memory and in LDS
-    // (uniform base addresses plus one 32-bit lane offset)
     constexpr int kPer = C::kChunks / 4;
-    const char* tile0 = (const char*)(rho_occ + (size_t)ct * ngp * 16 * NBLK);
+    const char* seg0 = (const char*)(rho_occ + (size_t)ct * ngp * 16 * NBLK) + (size_t)gs * C::kRowB;
     const uint32_t loff = 16 * lane;
-    auto issue = [&](int st, int buf) {
-        const char* ub = tile0 + (size_t)(gs + C::kSG * st) * C::kRowB + 1024 * wave;
+    auto issue = [&](int st, char* buf) {
+        const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(seg0 + (size_t)st * C::kSG * C::kRowB), (short)0, C::kSG * C::kRowB, kRawBufferWord3);
 #pragma unroll
         for (int i = 0; i < kPer; ++i)
-            __builtin_amdgcn_global_load_lds((const void*)(ub + 4096 * i + loff),
-                                             (lds_ptr)(&sm[buf][1024 * (wave + 4 * i)]), 16, 0, 0);
-        if (wave == 0)
-            __builtin_amdgcn_global_load_lds((const void*)((const char*)(pos + gs + C::kSG * st) + loff),
-                                             (lds_ptr)(&sm[buf][1024 * C::kChunks]), 16, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr)(buf + 1024 * (wave + 4 * i)), 16, loff,
+                                                     1024 * (wave + 4 * i), 0, 0);
+        if (wave == 0) {
+            const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(pos + gs + C::kSG * st), (short)0, C::kSG * (int)sizeof(d4), kRawBufferWord3);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rp, (lds_ptr)(buf + 1024 * C::kChunks), 16, loff, 0, 0, 0);
+        }
     };
 
     d4 acc[3][NBLK];
@@ -163,25 +173,20 @@ __global__ __launch_bounds__(256, 2) void k_build_K_occ(const d4* __restrict__ p
 #pragma unroll
         for (int c = 0; c < NBLK; ++c) acc[x][c] = (d4){0.0, 0.0, 0.0, 0.0};
 
-    if (nst > 0) {
-        issue(0, 0);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-    }
-    for (int st = 0; st < nst; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nst) issue(st + 1, buf ^ 1);
-        const char* tile = sm[buf];
-        const d4* sp = (const d4*)(tile + 1024 * C::kChunks);
+    // the 8 k-steps of the stage in `tile`, then the wait for this wave's
+    // loads of the next stage and the barrier that publishes everyone's (and
+    // ends every wave's reads of this one)
+    auto stage = [&](const char* tile) {
 #pragma unroll 1
         for (int t = 0; t < C::kSG / 4; ++t) {
             const int k = 4 * t + kq;                      // this lane's point of the k-step
-            const d4 cp = sp[k];
+            const double* cq = (const double*)(tile + 1024 * C::kChunks) + 4 * k;
+            const double cx = cq[0], cy = cq[1], cz = cq[2];
             const double* brow = (const double*)(tile + k * C::kRowB) + l16;
             double cb[NBLK];
 #pragma unroll
             for (int c = 0; c < NBLK; ++c) cb[c] = brow[16 * c];
-            const double dx = pg.x - cp.x, dy = pg.y - cp.y, dz = pg.z - cp.z;
+            const double dx = pg.x - cx, dy = pg.y - cy, dz = pg.z - cz;
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
             const double f = du_over_r<KIND>(r2, J);
             const double ax = dx * f, ay = dy * f, az = dz * f;
@@ -192,9 +197,26 @@ __global__ __launch_bounds__(256, 2) void k_build_K_occ(const d4* __restrict__ p
                 acc[2][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, cb[c], acc[2][c], 0, 0, 0);
             }
         }
-        __builtin_amdgcn_s_waitcnt(0);                     // this wave's loads of the next stage
-        __syncthreads();                                   // everyone's, and this stage read by all
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    };
+
+    if (nst > 0) {
+        issue(0, sm0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
     }
+    // even stages from sm0, odd ones from sm1, each stage's successor loaded
+    // into the other buffer while it is consumed; an odd last stage (in sm0)
+    // after the loop
+    int st = 0;
+    for (; st + 1 < nst; st += 2) {
+        issue(st + 1, sm1);
+        stage(sm0);
+        if (st + 2 < nst) issue(st + 2, sm0);
+        stage(sm1);
+    }
+    if (st < nst) stage(sm0);
     double* out = part + (size_t)blockIdx.y * 3 * rows * ldO;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
