@@ -487,7 +487,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="N128-occ16-Ng150k")
     ap.add_argument("--prec", default="bf16x3", choices=list(PEAK))
-    ap.add_argument("--compare", default="fp64", help="form run once beside the headline one ('none' to skip)")
+    ap.add_argument("--compare", default="fp64,fp32",
+                    help="comma-separated forms run once beside the headline one, the first being the reference "
+                         "the others are compared against ('none' to skip; the TC integrals use the first)")
     ap.add_argument("--chunk", type=int, default=None,
                     help="grid rows per chunk (default: Ng/10 for FP64, Ng/20 for the reduced forms: equal launches)")
     ap.add_argument("--cpu-rows", type=int, default=30000,
@@ -570,9 +572,10 @@ def main():
                 "vs_baseline": None, "dtype": DTYPE[args.prec] + "+f64", "data": "synthetic",
                 "config": {"workload": args.workload, "N": wl.N, "Ng": wl.Ng, "prec": args.prec,
                            "chunk_rows": chunk, "F_flop": Ftc}}
-        if args.compare != "none" and args.compare != args.prec:
-            sec_c, K2c = run_tc2(problem, args.compare, default_chunk(wl.Ng, args.compare), 1, 0)
-            line["forms"] = {args.compare: {"s_per_step": sec_c,
+        tc_ref = args.compare.split(",")[0]
+        if tc_ref not in ("", "none", args.prec):
+            sec_c, K2c = run_tc2(problem, tc_ref, default_chunk(wl.Ng, tc_ref), 1, 0)
+            line["forms"] = {tc_ref: {"s_per_step": sec_c,
                                             "max_abs_err": (K2 - K2c).abs().max().item(),
                                             "max_abs": K2c.abs().max().item()}}
         print(json.dumps(line), flush=True)
@@ -593,25 +596,41 @@ def main():
         forms[args.prec]["max_abs_err_vs_oracle"] = golden_errors(golden, *r["outputs"])
         print(f"[bench] {args.prec} vs oracle subset: {forms[args.prec]['max_abs_err_vs_oracle']}",
               file=sys.stderr, flush=True)
-    if args.compare != "none" and args.compare != args.prec:
-        cchunk = default_chunk(wl.Ng, args.compare)
-        print(f"[bench] comparison form {args.compare}: one step", file=sys.stderr, flush=True)
-        V2h, h1h, E0h = (t.clone() for t in r["outputs"])
+    # comparison forms, one step each: the first (FP64 by default) is the
+    # reference the headline form and every later one are compared against
+    cmp = [c for c in args.compare.split(",") if c and c not in ("none", args.prec)]
+    if cmp:
+        def errors(x, y):
+            return {"V2": (x[0] - y[0]).abs().max().item(), "h1": (x[1] - y[1]).abs().max().item(),
+                    "E0": (x[2] - y[2]).abs().max().item()}
+
+        head = tuple(t.clone() for t in r["outputs"])
         del r["outputs"]
         torch.cuda.empty_cache()
-        rc = run_gpu(problem, args.compare, 1, 0, cchunk, profile=args.compare == "fp64")
-        if rc.get("kernel_times"):
-            forms[args.compare + "_kernels"] = kernel_rooflines(rc["kernel_times"], wl.N, nref, wl.Ng, args.compare)
-        V2c, h1c, E0c = rc["outputs"]
-        err = {"V2": (V2h - V2c).abs().max().item(), "h1": (h1h - h1c).abs().max().item(),
-               "E0": (E0h - E0c).abs().max().item()}
-        forms[args.compare] = form_rates(rc["sec"])
-        if golden:
-            forms[args.compare]["max_abs_err_vs_oracle"] = golden_errors(golden, V2c, h1c, E0c)
-        forms[args.prec]["max_abs_err_vs_" + args.compare] = err
-        forms[args.prec]["speedup_vs_" + args.compare] = rc["sec"] / r["sec"]
-        print(f"[bench] {args.compare}: {rc['sec']:.3f} s/step; max|err| {err}", file=sys.stderr, flush=True)
-        del V2h, h1h, E0h, V2c, h1c, E0c, rc
+        ref = ref_sec = ref_name = None
+        for form in cmp:
+            print(f"[bench] comparison form {form}: one step", file=sys.stderr, flush=True)
+            rc = run_gpu(problem, form, 1, 0, default_chunk(wl.Ng, form), profile=form == "fp64")
+            if rc.get("kernel_times"):
+                forms[form + "_kernels"] = kernel_rooflines(rc["kernel_times"], wl.N, nref, wl.Ng, form)
+            outs = rc.pop("outputs")
+            forms[form] = form_rates(rc["sec"])
+            if golden:
+                forms[form]["max_abs_err_vs_oracle"] = golden_errors(golden, *outs)
+            if ref is None:
+                ref, ref_sec, ref_name = outs, rc["sec"], form
+                err = errors(head, ref)
+                forms[args.prec]["max_abs_err_vs_" + form] = err
+                forms[args.prec]["speedup_vs_" + form] = rc["sec"] / r["sec"]
+            else:
+                err = errors(outs, ref)
+                forms[form]["max_abs_err_vs_" + ref_name] = err
+                forms[form]["speedup_vs_" + ref_name] = ref_sec / rc["sec"]
+                del outs
+            print(f"[bench] {form}: {rc['sec']:.3f} s/step; max|err| {err}", file=sys.stderr, flush=True)
+            del rc
+            torch.cuda.empty_cache()
+        del head, ref
         torch.cuda.empty_cache()
     # roofline of the dominant kernel (K build): algorithmic flops per launch over
     # its average launch duration from HIP events on the launch stream
