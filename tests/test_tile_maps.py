@@ -2,7 +2,9 @@
 (xcd_strip_tile in kernels_lp.h), transcribed index for index: every
 workgroup id of the launched grid maps to a distinct (row tile, strip) and
 every tile is covered, for the launch shapes in use and ragged ones; each
-XCD (id % 8) walks whole strips among the first 8 floor(nstrip/8)."""
+XCD (id % 8) walks whole strips among the first 8 floor(nstrip/8).  Also the
+banded XCD ranges of the two-body GEMM (k_gemm_tn_lds) and the pair-sum
+segments of the adjoint's Pi contraction (pi_segments in xtc_api.hip)."""
 import pytest
 
 
@@ -51,3 +53,61 @@ def test_strip_order_bijection_and_xcd_affinity(n_rt, nstrip):
     assert all(len(x) == 1 for x in owner.values())     # a dealt strip stays on one XCD
     plain = [xcd_strip_tile(w, n_rt, nstrip, False) for w in range(n_rt * nstrip)]
     assert plain == [(w % n_rt, w // n_rt) for w in range(n_rt * nstrip)]   # row tile fastest
+
+
+def gemm_tile(wg, n_pt, n_rt, per_xcd, band=4):
+    """The two-body split-BF16 GEMM's (column tile P, column tile R) of
+    workgroup wg (k_gemm_tn_lds): XCD wg % 8 takes the contiguous range
+    [xcd per_xcd, (xcd + 1) per_xcd) of a banded order (bands of `band` P
+    tiles, R fastest within a band); ids past the tiles return None."""
+    loc, t = wg >> 3, (wg & 7) * per_xcd + (wg >> 3)
+    if loc >= per_xcd or t >= n_pt * n_rt:
+        return None
+    b = min(t // (band * n_rt), (n_pt - 1) // band)
+    r = t - b * band * n_rt
+    gw = min(band, n_pt - b * band)
+    return b * band + r % gw, r // gw
+
+
+@pytest.mark.parametrize("n_pt,n_rt", [(33, 33), (1, 1), (5, 3), (4, 9), (9, 4), (17, 2), (2, 17)])
+def test_gemm_tile_map_is_a_bijection_and_xcd_ranges_are_compact(n_pt, n_rt):
+    per = (n_pt * n_rt + 7) // 8
+    tiles = [gemm_tile(w, n_pt, n_rt, per) for w in range(8 * per)]
+    got = [t for t in tiles if t is not None]
+    assert len(got) == n_pt * n_rt and set(got) == {(p, r) for p in range(n_pt) for r in range(n_rt)}
+    # the first 32 tiles an XCD runs (its resident set) span few P and R tiles
+    for x in range(8):
+        first = [tiles[8 * loc + x] for loc in range(min(per, 32)) if tiles[8 * loc + x] is not None]
+        if len(first) >= 32:
+            assert len({p for p, _ in first}) <= 8 and len({r for _, r in first}) <= 9
+
+
+def pi_segments(ldP, ngp, ns=2, es=2, deal_bytes=192 << 20, threads=512):
+    """Segments of the Pi contraction's pair sum (pi_segments in xtc_api.hip)."""
+    n_jt = (ngp + threads - 1) // threads
+    best = 1
+    for n in range(1, 5):
+        if n * n_jt > ngp // 128:
+            break
+        best = n
+        kseg = -(-(-(-ldP // n)) // 64) * 64
+        if 8 * kseg * threads * ns * es <= deal_bytes:
+            break
+    return best
+
+
+@pytest.mark.parametrize("N,ngp", [(160, 250112), (96, 100096), (128, 150016), (24, 2048), (8, 128), (200, 1024)])
+def test_pi_segments_cover_the_pair_range_and_fit_the_partials(N, ngp):
+    ldP = -(-(N * (N + 1) // 2) // 128) * 128
+    n = pi_segments(ldP, ngp)
+    kseg = -(-(-(-ldP // n)) // 64) * 64
+    nseg = -(-ldP // kseg)
+    starts = [s * kseg for s in range(nseg)]
+    ends = [min(ldP, s + kseg) for s in starts]
+    assert starts[0] == 0 and ends[-1] == ldP and all(e > s and (e - s) % 64 == 0 for s, e in zip(starts, ends))
+    n_jt = (ngp + 511) // 512
+    assert nseg * n_jt <= max(1, ngp // 128)        # per-workgroup gradient partials fit one row tile's slab
+    if N == 160:
+        assert nseg == 2                             # 26.5 MB strips do not deal; 13.2 MB ones do
+    if N == 96:
+        assert nseg == 1
