@@ -1009,13 +1009,9 @@ __global__ __launch_bounds__(256) void k_pi_grad_lp(const void* __restrict__ Kb,
 // A: [NC][NS][ldk/8][rows][8] (component stride a_comp, split stride a_split),
 // B: [NS][ldk/8][nB][8] (split stride b_split), both k-packed (k_pack_kmajor):
 // each 16-byte operand vector and each 16-row block of one 8-k group is
-// contiguous.  ldk and kseg are multiples of 64.  The k range runs in
-// segments of kseg (the GRAD epilogue is linear in the products, so each
-// segment's share is summed like any other workgroup's; the other
-// epilogue accumulates into out, so it takes one segment).  Grid: n_rt x
-// (ceil(nB / 512) x segments) in the XCD-aware order of xcd_strip_tile, so
-// the workgroups resident on an XCD share one B strip (512 columns x one
-// segment) through its L2.
+// contiguous.  ldk is a multiple of 64.  Grid: n_rt x ceil(nB / 512) in the
+// XCD-aware order of xcd_strip_tile, so the workgroups resident on an XCD
+// share one B strip through its L2.
 // Epilogues:
 //  GRAD (NC = 3, the Pi contraction Pi^x(g,g') = sum_P Kbar^x[g][P] rho[g'][P]
 //   with i = g - g0, j = g'): the gradient terms of every (g, g'), summed per
@@ -1026,8 +1022,7 @@ constexpr int kPiThreads = 512;
 template <int FORM, int NC, bool GRAD>
 __global__ __launch_bounds__(kPiThreads) void k_nt_bf16(const __bf16* __restrict__ A, size_t a_comp, size_t a_split,
                                                         int rows, const __bf16* __restrict__ B, size_t b_split,
-                                                        int nB, int ldk, int kseg, int n_rt,
-                                                        const d4* __restrict__ pos,
+                                                        int nB, int ldk, int n_rt, const d4* __restrict__ pos,
                                                         int g0, int ncoef, double* __restrict__ out,
                                                         size_t out_comp, int ldo, int accumulate) {
     static_assert(FORM == 3 || FORM == 6, "split-BF16 forms only");
@@ -1042,11 +1037,8 @@ __global__ __launch_bounds__(kPiThreads) void k_nt_bf16(const __bf16* __restrict
     constexpr int kAPer = (kAVec + kPiThreads - 1) / kPiThreads;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int rt, jt;
-    const bool deal = (size_t)8 * kseg * 512 * NS * sizeof(__bf16) <= kDealBytes;
-    xcd_strip_tile(blockIdx.x, n_rt, gridDim.x / n_rt, deal, rt, jt);   // strips: 512 columns x k segment
-    const int n_jt = (nB + kPiThreads - 1) / kPiThreads;
-    const int k0 = (jt / n_jt) * kseg, k1 = min(ldk, k0 + kseg);
-    jt %= n_jt;
+    const bool deal = (size_t)8 * ldk * 512 * NS * sizeof(__bf16) <= kDealBytes;
+    xcd_strip_tile(blockIdx.x, n_rt, gridDim.x / n_rt, deal, rt, jt);   // strips: 512-column tiles of B
     const int l16 = lane & 15, lk = lane >> 4;
 
     // loader role: vector v = tid + 512 i is (component-split cs, 8-k chunk q,
@@ -1120,7 +1112,7 @@ __global__ __launch_bounds__(kPiThreads) void k_nt_bf16(const __bf16* __restrict
     // registers for two k-steps of its operand: it loads the next one after
     // the MFMAs are issued.
     auto step = [&](int k, const ATile& R, ATile& W) {
-        const int kn = min(k + kLpK, k1 - kLpK);
+        const int kn = min(k + kLpK, ldk - kLpK);
         loadA(kn);
         if constexpr (FORM == 3) {
             bf8 bv[NB][NS];
@@ -1136,11 +1128,11 @@ __global__ __launch_bounds__(kPiThreads) void k_nt_bf16(const __bf16* __restrict
         }
         storeA(W);
     };
-    loadA(k0);
-    loadB(k0);
+    loadA(0);
+    loadB(0);
     storeA(sA0);
     __syncthreads();
-    for (int k = k0; k < k1; k += 2 * kLpK) {
+    for (int k = 0; k < ldk; k += 2 * kLpK) {
         step(k, sA0, sA1);
         __syncthreads();
         step(k + kLpK, sA1, sA0);

@@ -658,21 +658,6 @@ xtc_status pack_kmajor_any(int form, const double* src, int nrows, int ld, void*
     return launched("pack_kmajor");
 }
 
-// Segments of the pair sum of the split-BF16 Pi contraction: the fewest (at
-// most 4) whose B strips (512 grid columns x one segment, all splits) can be
-// dealt eight at a time to the XCDs within the last-level cache budget, and
-// whose per-workgroup gradient partials fit the gpart slab of a row tile
-// (ngp / 128 entries).
-int pi_segments(const Layout& L, int n_jt) {
-    int best = 1;
-    for (int n = 1; n <= 4 && n * n_jt <= L.ngp / 128; ++n) {
-        best = n;
-        const size_t kseg = align_up((size_t)((L.ldP + n - 1) / n), 2 * kLpK);
-        if ((size_t)8 * kseg * kPiThreads * L.ns * L.es <= kDealBytes) break;
-    }
-    return best;
-}
-
 // The adjoint's X Gbar products in the split-BF16 3-product form (k_nt_bf16,
 // FP32 accumulation over all pairs): Y_c (+)= X_c Gm^T for NC consecutive
 // components sharing one right operand (X k-packed splits [NC][2][ldP/8][rows][8]
@@ -684,7 +669,7 @@ xtc_status xg_group(const __bf16* X, size_t a_comp, size_t a_split, int rows, co
                     double* Y, size_t ystride, int accumulate, hipStream_t st) {
     const int n_rt = (rows + kLpRows - 1) / kLpRows, n_jt = (ldP + kPiThreads - 1) / kPiThreads;
     hipLaunchKernelGGL((k_nt_bf16<3, NC, false>), dim3(n_rt * n_jt), dim3(kPiThreads), 0, st, X, a_comp, a_split,
-                       rows, Gs, (size_t)ldP * ldP, ldP, ldP, ldP, n_rt, (const d4*)nullptr, 0, 0, Y, ystride, ldP,
+                       rows, Gs, (size_t)ldP * ldP, ldP, ldP, n_rt, (const d4*)nullptr, 0, 0, Y, ystride, ldP,
                        accumulate);
     return launched("gemm_xg_bf16");
 }
@@ -1051,18 +1036,16 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
             } else {
                 const int n_rt = (rows + kLpRows - 1) / kLpRows;
                 const int n_jt = (L.ngp + kPiThreads - 1) / kPiThreads;
-                const int nkseg = pi_segments(L, n_jt);
-                const int kseg = (int)align_up((size_t)((L.ldP + nkseg - 1) / nkseg), 2 * kLpK);
-                nblk_pi = n_rt * n_jt * ((L.ldP + kseg - 1) / kseg);
+                nblk_pi = n_rt * n_jt;
                 const __bf16* kbb = (const __bf16*)kb;
                 const __bf16* rrb = at<__bf16>(ws, L.rhoR);
                 if (L.form == 3)
                     hipLaunchKernelGGL((k_nt_bf16<3, 3, true>), dim3(nblk_pi), dim3(kPiThreads), 0, st, kbb, kb_comp,
-                                       kb_split, rows, rrb, rr_split, L.ngp, L.ldP, kseg, n_rt, at<d4>(ws, L.pos), g0,
+                                       kb_split, rows, rrb, rr_split, L.ngp, L.ldP, n_rt, at<d4>(ws, L.pos), g0,
                                        J.ncoef, at<double>(ws, L.gpart), (size_t)0, 0, 0);
                 else
                     hipLaunchKernelGGL((k_nt_bf16<6, 3, true>), dim3(nblk_pi), dim3(kPiThreads), 0, st, kbb, kb_comp,
-                                       kb_split, rows, rrb, rr_split, L.ngp, L.ldP, kseg, n_rt, at<d4>(ws, L.pos), g0,
+                                       kb_split, rows, rrb, rr_split, L.ngp, L.ldP, n_rt, at<d4>(ws, L.pos), g0,
                                        J.ncoef, at<double>(ws, L.gpart), (size_t)0, 0, 0);
             }
             if ((s = launched("pi_grad_lp")) != XTC_OK) return s;

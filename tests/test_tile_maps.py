@@ -3,8 +3,7 @@
 workgroup id of the launched grid maps to a distinct (row tile, strip) and
 every tile is covered, for the launch shapes in use and ragged ones; each
 XCD (id % 8) walks whole strips among the first 8 floor(nstrip/8).  Also the
-banded XCD ranges of the two-body GEMM (k_gemm_tn_lds) and the pair-sum
-segments of the adjoint's Pi contraction (pi_segments in xtc_api.hip)."""
+banded XCD ranges of the two-body GEMM (k_gemm_tn_lds)."""
 import pytest
 
 
@@ -80,34 +79,3 @@ def test_gemm_tile_map_is_a_bijection_and_xcd_ranges_are_compact(n_pt, n_rt):
         first = [tiles[8 * loc + x] for loc in range(min(per, 32)) if tiles[8 * loc + x] is not None]
         if len(first) >= 32:
             assert len({p for p, _ in first}) <= 8 and len({r for _, r in first}) <= 9
-
-
-def pi_segments(ldP, ngp, ns=2, es=2, deal_bytes=192 << 20, threads=512):
-    """Segments of the Pi contraction's pair sum (pi_segments in xtc_api.hip)."""
-    n_jt = (ngp + threads - 1) // threads
-    best = 1
-    for n in range(1, 5):
-        if n * n_jt > ngp // 128:
-            break
-        best = n
-        kseg = -(-(-(-ldP // n)) // 64) * 64
-        if 8 * kseg * threads * ns * es <= deal_bytes:
-            break
-    return best
-
-
-@pytest.mark.parametrize("N,ngp", [(160, 250112), (96, 100096), (128, 150016), (24, 2048), (8, 128), (200, 1024)])
-def test_pi_segments_cover_the_pair_range_and_fit_the_partials(N, ngp):
-    ldP = -(-(N * (N + 1) // 2) // 128) * 128
-    n = pi_segments(ldP, ngp)
-    kseg = -(-(-(-ldP // n)) // 64) * 64
-    nseg = -(-ldP // kseg)
-    starts = [s * kseg for s in range(nseg)]
-    ends = [min(ldP, s + kseg) for s in starts]
-    assert starts[0] == 0 and ends[-1] == ldP and all(e > s and (e - s) % 64 == 0 for s, e in zip(starts, ends))
-    n_jt = (ngp + 511) // 512
-    assert nseg * n_jt <= max(1, ngp // 128)        # per-workgroup gradient partials fit one row tile's slab
-    if N == 160:
-        assert nseg == 2                             # 26.5 MB strips do not deal; 13.2 MB ones do
-    if N == 96:
-        assert nseg == 1
