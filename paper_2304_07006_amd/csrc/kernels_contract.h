@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_onebody_T1(const double* __restrict__ r
 
 // One-body reduction, exchange term, partial over grid splits:
 //   E[split][p][q] = sum_{g in split} sum_k n_k sum_c C_c[g][pair(p,k)] D_c[g][pair(k,q)]
-// Workgroup: a 64 x 64 block of (p,q), 4 x 4 per thread; the occupied columns
+// Workgroup: a 64 x 64 block of (p,q), 4 x 4 per thread (strided by 16); the occupied columns
 // of C and rows of D for that block are staged in LDS per grid point.
 constexpr int kEBlk = 64;
 __global__ __launch_bounds__(256) void k_onebody_E(const double* __restrict__ rho_rows,
@@ -288,7 +288,10 @@ __global__ __launch_bounds__(256) void k_onebody_E(const double* __restrict__ rh
     const int pb = blockIdx.x % nbk, qb = blockIdx.x / nbk;
     const int split = blockIdx.y, nsplit = gridDim.y;
     const int gb = (int)(((long)rows * split) / nsplit), ge = (int)(((long)rows * (split + 1)) / nsplit);
-    const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;    // 16 x 16 threads, 4 x 4 each
+    // 16 x 16 threads, 4 x 4 each: p = 64 pb + ti + 16 i, q = 64 qb + tj + 16 j
+    // (the 16 lanes of a row read 16 consecutive staged values: no LDS bank
+    // conflicts, where 4 consecutive values per thread conflicted)
+    const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
     const size_t kstride = (size_t)rows * ldP;
     double acc[4][4];
 #pragma unroll
@@ -312,8 +315,8 @@ __global__ __launch_bounds__(256) void k_onebody_E(const double* __restrict__ rh
                 double a[4], b[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    a[i] = cs[kk * kEBlk + 4 * ti + i];
-                    b[i] = ds[kk * kEBlk + 4 * tj + i];
+                    a[i] = cs[kk * kEBlk + ti + 16 * i];
+                    b[i] = ds[kk * kEBlk + tj + 16 * i];
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
@@ -327,7 +330,7 @@ __global__ __launch_bounds__(256) void k_onebody_E(const double* __restrict__ rh
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int p = pb * kEBlk + 4 * ti + i, q = qb * kEBlk + 4 * tj + j;
+            const int p = pb * kEBlk + ti + 16 * i, q = qb * kEBlk + tj + 16 * j;
             if (p < N && q < N) E[split * NN + (size_t)p * N + q] = acc[i][j];
         }
 }
