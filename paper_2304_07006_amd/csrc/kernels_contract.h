@@ -37,12 +37,31 @@ struct OccList {
 // S[g] = (W~/2, W/2 (3), sum_k n_k A_kk, sum_k n_k B_kk (3)) feed the one-body
 // reduction.
 constexpr int kIGather = 4;
+// Staged entry e of the intermediates' LDS array: 32 bytes, and with PAD 16
+// more bytes after every 4 entries, so that the 16 lanes of a b128 read phase
+// that fetch entries 4 apart (consecutive 4x4 tiles) hit distinct banks.
+// (Entries are then 16-byte aligned only: accessed as two 16-byte halves.)
+typedef double dpair __attribute__((ext_vector_type(2)));
+template <bool PAD> __device__ __forceinline__ dpair* staged(char* base, int e) {
+    return (dpair*)(base + 32 * e + (PAD ? 16 * (e >> 2) : 0));
+}
+template <bool PAD> __device__ __forceinline__ d4 ld_staged(char* base, int e) {
+    const dpair* p = staged<PAD>(base, e);
+    const dpair lo = p[0], hi = p[1];
+    return (d4){lo.x, lo.y, hi.x, hi.y};
+}
+template <bool PAD> __device__ __forceinline__ void st_staged(char* base, int e, const d4& v) {
+    dpair* p = staged<PAD>(base, e);
+    p[0] = (dpair){v.x, v.y};
+    p[1] = (dpair){v.z, v.w};
+}
+template <bool PAD>
 __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict__ rho_rows,
                                                        const double* __restrict__ K, int rows,
                                                        int ldP, int N, OccList occ,
                                                        double* __restrict__ D, size_t dstride,
                                                        double* __restrict__ S) {
-    extern __shared__ d4 locc[];                   // [nocc][N] of (rho, Kx, Ky, Kz)
+    extern __shared__ __attribute__((aligned(16))) char lraw[];   // [nocc][N] of (rho, Kx, Ky, Kz)
     __shared__ double sW[4];                       // Wx, Wy, Wz, Wt
     const int n = occ.n;
     const size_t kstride = (size_t)rows * ldP;
@@ -65,7 +84,7 @@ __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict_
             }
 #pragma unroll
             for (int u = 0; u < kIGather; ++u)
-                if (base + 256 * u < n * N) locc[base + 256 * u] = e[u];
+                if (base + 256 * u < n * N) st_staged<PAD>(lraw, base + 256 * u, e[u]);
         }
         __syncthreads();
         if (threadIdx.x < 64) {
@@ -77,7 +96,7 @@ __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict_
             // w0..w2 = W/2, wt = W~/2
             double w0 = 0, w1 = 0, w2 = 0, wt = 0;
             for (int kk = 0; kk < n; ++kk) {           // every lane, same order
-                const d4 e = locc[kk * N + occ.k[kk]];
+                const d4 e = ld_staged<PAD>(lraw, kk * N + occ.k[kk]);
                 const double nk = occ.wt[kk];
                 wt = fma(nk, e.x, wt); w0 = fma(nk, e.y, w0); w1 = fma(nk, e.z, w1); w2 = fma(nk, e.w, w2);
             }
@@ -85,10 +104,10 @@ __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict_
             double a = 0, b0 = 0, b1 = 0, b2 = 0;
             for (int kk = lane; kk < n; kk += 64) {
                 const int k = occ.k[kk];
-                const d4 e = locc[kk * N + k];                      // (rho_kk, K_kk)
+                const d4 e = ld_staged<PAD>(lraw, kk * N + k);       // (rho_kk, K_kk)
                 double zt = 0, z0 = 0, z1 = 0, z2 = 0;
                 for (int ll = 0; ll < n; ++ll) {
-                    const d4 f = locc[ll * N + k];                  // (rho_kl, K_kl)
+                    const d4 f = ld_staged<PAD>(lraw, ll * N + k);   // (rho_kl, K_kl)
                     const double nl = occ.w[ll];
                     zt = fma(nl, f.y * f.y + f.z * f.z + f.w * f.w, zt);
                     z0 = fma(nl, 2.0 * f.x * f.y, z0); z1 = fma(nl, 2.0 * f.x * f.z, z1);
@@ -129,11 +148,14 @@ __global__ __launch_bounds__(256) void k_intermediates(const double* __restrict_
                 sj[i] = min(4 * bj + i, N - 1);
             }
             for (int kk = 0; kk < n; ++kk) {
-                const d4* row = locc + kk * N;
+                const int row = kk * N;
                 const double nk = occ.w[kk];
                 d4 a[4], b[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) { a[i] = row[ri[i]]; b[i] = nk * row[sj[i]]; }
+                for (int i = 0; i < 4; ++i) {
+                    a[i] = ld_staged<PAD>(lraw, row + ri[i]);
+                    b[i] = nk * ld_staged<PAD>(lraw, row + sj[i]);
+                }
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll

@@ -261,7 +261,17 @@ void place_chunk(Layout& L, size_t bytes) {
     if (L.end > bytes) L.cap = 0;   // cannot happen by construction; refuse rather than overrun
 }
 
-size_t lds_intermediates(const Layout& L) { return (size_t)L.nocc * L.N * 4 * sizeof(double); }
+// LDS of k_intermediates: the padded layout (16 bytes after every 4 entries)
+// when it fits, else the plain one (check_problem admits sizes up to the
+// plain layout's limit)
+bool intermediates_padded(const Layout& L) {
+    const size_t e = (size_t)L.nocc * L.N;
+    return e * 32 + ((e + 3) / 4) * 16 <= kLdsMax - kLdsStaticReserve;
+}
+size_t lds_intermediates(const Layout& L) {
+    const size_t e = (size_t)L.nocc * L.N;
+    return e * 32 + (intermediates_padded(L) ? ((e + 3) / 4) * 16 : 0);
+}
 
 xtc_status check_problem(const xtc_problem* pb) {
     if (!pb) return fail(XTC_E_ARG, "problem is NULL");
@@ -389,8 +399,9 @@ xtc_status run_intermediates(const Layout& L, const xtc_problem* pb, const doubl
     const size_t dstride = (size_t)L.cap * L.ldP;
     const int blocks = std::min(rows, 4096);
     const size_t lds = lds_intermediates(L);
+    const bool pad = intermediates_padded(L);
     if (lds > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k_intermediates,
+        const hipError_t e = hipFuncSetAttribute(pad ? (const void*)k_intermediates<true> : (const void*)k_intermediates<false>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) {
             (void)hipGetLastError();   // do not leave the error for the caller's next HIP call
@@ -398,9 +409,14 @@ xtc_status run_intermediates(const Layout& L, const xtc_problem* pb, const doubl
         }
     }
     for (int sp = 0; sp < L.nspin; ++sp) {
-        hipLaunchKernelGGL(k_intermediates, dim3(blocks), dim3(256), lds, st, rho_rows, K, rows, L.ldP, L.N,
-                           make_occ(pb, sp), at<double>(ws, L.D) + (size_t)sp * 4 * dstride, dstride,
-                           at<double>(ws, L.S) + (size_t)sp * L.cap * 8);
+        if (pad)
+            hipLaunchKernelGGL(k_intermediates<true>, dim3(blocks), dim3(256), lds, st, rho_rows, K, rows, L.ldP, L.N,
+                               make_occ(pb, sp), at<double>(ws, L.D) + (size_t)sp * 4 * dstride, dstride,
+                               at<double>(ws, L.S) + (size_t)sp * L.cap * 8);
+        else
+            hipLaunchKernelGGL(k_intermediates<false>, dim3(blocks), dim3(256), lds, st, rho_rows, K, rows, L.ldP,
+                               L.N, make_occ(pb, sp), at<double>(ws, L.D) + (size_t)sp * 4 * dstride, dstride,
+                               at<double>(ws, L.S) + (size_t)sp * L.cap * 8);
         xtc_status s;
         if ((s = launched("intermediates")) != XTC_OK) return s;
     }
