@@ -446,6 +446,24 @@ def test_loss_homogeneous_quadratic_and_gradient():
         assert abs(fd - g[k]) < 1e-8 * max(1.0, abs(g[k]))
 
 
+def test_loss_weights_select_the_outputs():
+    """The loss E0 + <h1, D> + <V2, G>: with zero weights it is E0, a unit
+    weight on one h1 (or V2) entry adds exactly that entry of the tier-B
+    outputs."""
+    p = inputs.make_problem(8, 2, 300, 2, "pair", "power16", seed=9, aux_seed=19)
+    c = np.array(p.jastrow.coef[:5])
+    V2, h1, E0 = fb.closed_shell(p.xyz, p.w, p.phi, p.occ, og.PowerJastrow("power", 0.0, tuple(float(x) for x in c)))
+    D0, G0 = np.zeros((8, 8)), np.zeros((8,) * 4)
+    L0 = og.loss(p.xyz, p.w, p.phi, p.occ, c, D0, G0)
+    assert L0 == E0
+    D = D0.copy()
+    D[1, 5] = 1.0
+    assert abs(og.loss(p.xyz, p.w, p.phi, p.occ, c, D, G0) - L0 - h1[1, 5]) < 1e-14 * max(1.0, abs(L0))
+    G = G0.copy()
+    G[0, 3, 6, 2] = 1.0
+    assert abs(og.loss(p.xyz, p.w, p.phi, p.occ, c, D0, G) - L0 - V2[0, 3, 6, 2]) < 1e-14 * max(1.0, abs(L0))
+
+
 def test_open_shell_loss_gradient_pins():
     """The open-shell loss is a homogeneous quadratic in c (Euler identity,
     L(2c) = 4 L(c)); with equal spin densities and seeds split evenly over
