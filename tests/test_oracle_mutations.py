@@ -162,3 +162,68 @@ def test_unmodified_copies_pass_every_pin_group(monkeypatch, tiny, tierA):
                        pins.test_lowdin_two_function_closed_form])
     monkeypatch.setattr(pins, "og", mutant("gradient", "import numpy as np", "import numpy as np"))
     assert not caught([pins.test_loss_homogeneous_quadratic_and_gradient, pins.test_loss_weights_select_the_outputs])
+
+
+# --------------------------------------------------- tier A (explicit L) --
+EXPLICIT = [
+    ("L without its electron-2-centred term", "L = L1 + L2 + L3", "L = L1 + L3", 0),
+    ("eq. dU with a wrong sign", '- np.einsum("prtqus,tu->prqs", L, g, optimize=True)',
+     '+ np.einsum("prtqus,tu->prqs", L, g, optimize=True)', 0),
+    ("eq. dU with an exchanged index", 'np.einsum("prtusq,tu->prqs", L, g, optimize=True))',
+     'np.einsum("prtuqs,tu->prqs", L, g, optimize=True))', 0),
+    ("grid intermediate without the weight", "pw = phi * w                                   # [N][j]",
+     "pw = phi                                       # [N][j]", 0),
+]
+
+
+@pytest.mark.parametrize("why,old,new,nth", EXPLICIT, ids=[c[0] for c in EXPLICIT])
+def test_tier_a_mistake_is_caught(monkeypatch, tiny, why, old, new, nth):
+    ex = mutant("explicit", old, new, nth)
+    monkeypatch.setattr(pins, "ex", ex)
+    A = ex.tier_a(tiny.xyz, tiny.w, tiny.phi, tiny.occ, tiny.jastrow)
+    checks = [lambda: pins.test_tier_a_equals_tier_b(tiny, A),
+              lambda: pins.test_determinant_brute_force(tiny, A),
+              lambda: pins.test_K_two_point_closed_form()]
+    assert caught(checks), why
+
+
+# ------------------------------------------------------ the TC integrals --
+TC2 = [
+    ("without the electron-swap term of B", "return (A + B + B.T).reshape(N, N, N, N)",
+     "return (A + 2.0 * B).reshape(N, N, N, N)", 0),
+    ("gradient term without its factor 2", 't2 = 2.0 * np.einsum("pg,xqg,xgh,rh,sh->pqrs"',
+     't2 = 1.0 * np.einsum("pg,xqg,xgh,rh,sh->pqrs"', 0),
+    ("definition without its 1/2", "return 0.5 * (t1 + t2 + t3 + t4)", "return (t1 + t2 + t3 + t4)", 0),
+    ("quadratic part without the weights", "rho = ((phi * w)[:, None, :] * phi[None, :, :]).reshape(phi.shape[0] ** 2, -1)",
+     "rho = ((phi)[:, None, :] * phi[None, :, :]).reshape(phi.shape[0] ** 2, -1)", 0),
+]
+
+
+@pytest.mark.parametrize("why,old,new,nth", TC2, ids=[c[0] for c in TC2])
+def test_tc_integral_mistake_is_caught(monkeypatch, why, old, new, nth):
+    import sys
+    tc2 = mutant("tc2", old, new, nth)
+    monkeypatch.setitem(sys.modules, "oracle.tc2", tc2)
+    monkeypatch.setattr(oracle, "tc2", tc2, raising=False)
+    p = inputs.make_problem(8, 2, 80, 2, "pair", "power16", seed=13)
+    case = (p, inputs.orbital_gradients(p))
+    checks = [lambda: pins.test_tc_two_body_factorised_equals_definition(case),
+              lambda: pins.test_tc_two_body_linear_and_quadratic_parts(case)]
+    assert caught(checks), why
+
+
+def test_unmodified_tier_a_and_tc_copies_pass_their_pins(monkeypatch, tiny):
+    import sys
+    ex = mutant("explicit", "import numpy as np", "import numpy as np")
+    monkeypatch.setattr(pins, "ex", ex)
+    A = ex.tier_a(tiny.xyz, tiny.w, tiny.phi, tiny.occ, tiny.jastrow)
+    assert not caught([lambda: pins.test_tier_a_equals_tier_b(tiny, A),
+                       lambda: pins.test_determinant_brute_force(tiny, A),
+                       lambda: pins.test_K_two_point_closed_form()])
+    tc2 = mutant("tc2", "import numpy as np", "import numpy as np")
+    monkeypatch.setitem(sys.modules, "oracle.tc2", tc2)
+    monkeypatch.setattr(oracle, "tc2", tc2, raising=False)
+    p = inputs.make_problem(8, 2, 80, 2, "pair", "power16", seed=13)
+    case = (p, inputs.orbital_gradients(p))
+    assert not caught([lambda: pins.test_tc_two_body_factorised_equals_definition(case),
+                       lambda: pins.test_tc_two_body_linear_and_quadratic_parts(case)])
