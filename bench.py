@@ -43,7 +43,8 @@ def kernel_sources_hash():
     profiles/ are only reported while it matches)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("xtc_device.h", "kernels_build_k.h", "kernels_lp.h", "kernels_prepare.h", "xtc_api.hip"):
+    for f in ("xtc_device.h", "kernels_build_k.h", "kernels_lp.h", "kernels_prepare.h", "kernels_occ_i8.h",
+              "occ_i8.hip", "xtc_api.hip"):
         with open(os.path.join(ROOT, "paper_2304_07006_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -62,7 +63,7 @@ def traffic_record(prec, workload, chunk):
     return e
 
 
-KBUILD_KERNELS = ("k_build_K_lp", "k_reduce_K", "k_build_K_occ", "k_reduce_occ", "k_build_K_f64")
+KBUILD_KERNELS = ("k_build_K_lp", "k_reduce_K", "k_build_K_occ_i8", "k_build_K_occ", "k_reduce_occ", "k_build_K_f64")
 
 
 def traffic_from(fetch_dir, write_dir, workload, prec, chunk, path=None):
@@ -209,15 +210,31 @@ def profile_kernels(fn):
     return out
 
 
+I8_PEAK = 5000.0        # TOP/s, dense int8 MFMA
+I8_PRODUCTS = 21        # digit products per useful one in the integer occupied block
+
+
+def occ_i8_columns(nocc):
+    """Pair columns the integer occupied block multiplies (16-pair tiles in
+    groups of at most 9)."""
+    nct = -(-(nocc * (nocc + 1) // 2) // 16)
+    groups = -(-nct // 9)
+    return 16 * groups * (-(-nct // groups))
+
+
 def kernel_rooflines(times, N, nocc, Ng, prec):
     """Per-kernel algorithmic rate and fraction of the relevant peak for the
     contraction kernels of one step: the kernel's algorithmic flops per step
-    (K build 6 Ng^2 Npair, FP64 occupied block 6 Ng^2 nOP, two-body GEMM
-    8 Ng Npair^2) over its summed device time in that step."""
+    (K build 6 Ng^2 Npair, occupied block 6 Ng^2 nOP, two-body GEMM
+    8 Ng Npair^2) over its summed device time in that step.  The integer
+    occupied block is rated by its executed int8 operations (21 digit
+    products per useful one over its padded columns) against the int8 peak,
+    and its useful rate is given beside it as an FP64-class rate."""
     P = N * (N + 1) // 2
     nOP = nocc * (nocc + 1) // 2
     table = {"k_build_K_lp": (6 * Ng * Ng * P, PEAK[prec]), "k_build_K_f64": (6 * Ng * Ng * P, PEAK["fp64"]),
              "k_build_K_occ": (6 * Ng * Ng * nOP, PEAK["fp64"]),
+             "k_build_K_occ_i8": (6 * Ng * Ng * occ_i8_columns(nocc) * I8_PRODUCTS, I8_PEAK),
              "k_gemm_tn_lds": (8 * Ng * P * P, PEAK[prec]), "k_gemm_tn_lp": (8 * Ng * P * P, PEAK[prec]),
              "k_gemm2b_f64": (8 * Ng * P * P, PEAK["fp64"])}
     out = {}
@@ -226,6 +243,8 @@ def kernel_rooflines(times, N, nocc, Ng, prec):
         if k in table:
             f, peak = table[k]
             e.update(flop_per_step=f, tflops=f / t / 1e12, peak_tflops=peak, frac=f / t / 1e12 / peak)
+        if k == "k_build_K_occ_i8":
+            e.update(useful_flop_per_step=6 * Ng * Ng * nOP, useful_tflops=6 * Ng * Ng * nOP / t / 1e12)
         out[k] = e
     tot = sum(t for _, t in times.values())
     for k in out:
@@ -233,7 +252,7 @@ def kernel_rooflines(times, N, nocc, Ng, prec):
     return out
 
 
-def run_gpu(problem, prec, steps, warmup, chunk, profile=False):
+def run_gpu(problem, prec, steps, warmup, chunk, profile=False, kflags=0):
     import torch
     from paper_2304_07006_amd import xtc
     dp = xtc.device_problem(problem.xyz, problem.w, problem.phi, problem.occ,
@@ -254,7 +273,7 @@ def run_gpu(problem, prec, steps, warmup, chunk, profile=False):
             if record:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-            xtc.xtc_build_K(dp, jas, g0, g1, ps.prec, K, ps.ws)
+            xtc.xtc_build_K(dp, jas, g0, g1, ps.prec | kflags, K, ps.ws)
             if record:
                 e1.record(stream)
                 kev.append((e0, e1, g1 - g0))
@@ -501,6 +520,9 @@ def main():
     ap.add_argument("--backward", action="store_true",
                     help="time forward + adjoint (xtc_backward) on a power-Jastrow workload "
                          "(default workload then N96-occ12-Ng100k)")
+    ap.add_argument("--occ-fp64", action="store_true",
+                    help="compute the reduced forms' occupied-occupied block of K with FP64 MFMA "
+                         "(XTC_K_OCC_FP64) instead of the integer-sliced products")
     ap.add_argument("--probe", action="store_true",
                     help="counter pass: one 1 GiB device copy (calibration) and one K-build launch, no JSON")
     ap.add_argument("--gemm-calibration", action="store_true",
@@ -582,7 +604,9 @@ def main():
         return
     print(f"[bench] {args.workload} prec={args.prec} chunk={chunk} warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
-    r = run_gpu(problem, args.prec, args.steps, args.warmup, chunk, profile=True)
+    from paper_2304_07006_amd import xtc
+    kflags = xtc.XTC_K_OCC_FP64 if args.occ_fp64 else 0
+    r = run_gpu(problem, args.prec, args.steps, args.warmup, chunk, profile=True, kflags=kflags)
     nspin = 2 if getattr(problem, "occ_n_beta", None) is not None else 1
     F = f_alg(wl.N, nref, wl.Ng, nspin)
     def form_rates(sec):
@@ -610,7 +634,7 @@ def main():
         ref = ref_sec = ref_name = None
         for form in cmp:
             print(f"[bench] comparison form {form}: one step", file=sys.stderr, flush=True)
-            rc = run_gpu(problem, form, 1, 0, default_chunk(wl.Ng, form), profile=form == "fp64")
+            rc = run_gpu(problem, form, 1, 0, default_chunk(wl.Ng, form), profile=form == "fp64", kflags=kflags)
             if rc.get("kernel_times"):
                 forms[form + "_kernels"] = kernel_rooflines(rc["kernel_times"], wl.N, nref, wl.Ng, form)
             outs = rc.pop("outputs")
@@ -660,7 +684,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "N": wl.N, "nocc": nref, "Ng": wl.Ng, "prec": args.prec,
                    "chunk_rows": chunk, "jastrow": wl.jastrow_kind, "density": density, "F_alg_flop": F,
-                   "workspace_bytes": r["ws_bytes"]},
+                   "workspace_bytes": r["ws_bytes"], "occupied_block": "fp64" if args.occ_fp64 else "int8-sliced"},
         "roofline": {"bound": "mfma", "kernel": "xtc_build_K", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": (tr["bytes_per_launch"] if (tr := traffic_record(args.prec, args.workload, chunk))

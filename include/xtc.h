@@ -64,8 +64,14 @@ typedef enum {
  *              within blocks, FP64 across blocks.
  * XTC_BF16X6 : three-way split a = a0 + a1 + a2; the six products of total
  *              order <= 2 (a0b0, a0b1, a1b0, a0b2, a1b1, a2b0).
- * In every form the occupied-occupied block of K, the intermediates and the
- * one- and zero-body reductions are computed in FP64. */
+ * In every form the intermediates and the one- and zero-body reductions are
+ * computed in FP64, and the occupied-occupied block of K to near-FP64
+ * accuracy: by default from exact integer products of the operands written
+ * as six base-128 digits against power-of-two scales (int8 MFMA, int32 sums;
+ * each operand within 2^-43 of its scale, the digit products of order 8 and
+ * up left out: about sqrt(Ng) 2^-44 of the scales' product per entry, with
+ * random sign), or in FP64 arithmetic (XTC_K_OCC_FP64 on xtc_build_K, and
+ * for grids above 2^21 points). */
 typedef enum { XTC_FP64 = 0, XTC_FP32 = 1, XTC_BF16X3 = 2, XTC_BF16X6 = 3 } xtc_prec;
 
 /* OR-ed into prec: lay the workspace out for xtc_backward as well (extra
@@ -80,6 +86,12 @@ enum { XTC_WITH_BACKWARD = 0x10, XTC_WITH_TC2 = 0x20 };
  * accuracy the reduced form sets anyway; an E0 computed from such K carries
  * the reduced form's error.  No effect in XTC_FP64. */
 enum { XTC_K_REDUCED_OCC = 0x40 };
+
+/* OR-ed into the prec of xtc_build_K only (other calls reject it; not
+ * together with XTC_K_REDUCED_OCC): compute the occupied-occupied pairs of K
+ * of the reduced forms with FP64 MFMA instead of the integer-sliced products,
+ * e.g. to compare the two.  No effect in XTC_FP64. */
+enum { XTC_K_OCC_FP64 = 0x80 };
 
 /* flags of the contraction calls */
 enum {
@@ -175,7 +187,8 @@ xtc_status xtc_prepare(const xtc_problem *pb, int32_t prec, int32_t chunk_rows,
  * K: device [3][g1-g0][ldP] FP64 (columns >= Npair written as 0).
  * The gradient is taken with respect to the first argument of u (the
  * electron sitting on grid point g).  In the reduced forms the occupied-
- * occupied pairs are recomputed in FP64 (unless prec has XTC_K_REDUCED_OCC).
+ * occupied pairs are recomputed to FP64 accuracy (unless prec has
+ * XTC_K_REDUCED_OCC).
  * Errors: XTC_E_ARG for !(0 <= g0 < g1 <= Ng), g1-g0 > chunk_rows of the
  * workspace, bad Jastrow, NULL K. */
 xtc_status xtc_build_K(const xtc_problem *pb, const xtc_jastrow *jas,

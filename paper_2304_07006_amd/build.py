@@ -8,16 +8,21 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libxtc.so")
-SOURCES = [os.path.join(HERE, "csrc", "xtc_api.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-shared", "-fPIC",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
     "-Wall", "-Wno-unused-function",
-    # MFMA accumulators in ordinary VGPRs (no per-iteration AGPR copies)
-    "-mllvm", "-amdgpu-mfma-vgpr-form",
+]
+# Translation units and their own flags.  xtc_api.hip: MFMA accumulators in
+# ordinary VGPRs (no per-iteration AGPR copies).  occ_i8.hip: the integer
+# occupied block keeps 216 accumulator registers per lane, beyond the 256
+# ordinary VGPRs, so its accumulators stay in the AGPRs.
+UNITS = [
+    (os.path.join(HERE, "csrc", "xtc_api.hip"), ["-mllvm", "-amdgpu-mfma-vgpr-form"]),
+    (os.path.join(HERE, "csrc", "occ_i8.hip"), []),
 ]
 
 
@@ -33,15 +38,36 @@ def build(verbose: bool = False, out: str | None = None, sanitize: bool = False)
     sanitizers (a checking build, not the product library)."""
     lib = out or LIB
     tmp = lib + ".tmp"
-    cmd = [HIPCC, *FLAGS, *(SANITIZE_FLAGS if sanitize else ()), *SOURCES, "-o", tmp]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    out = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in l)
-    if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{out}")
-    if verbose and out.strip():
-        print(out, file=sys.stderr)
+    extra = SANITIZE_FLAGS if sanitize else []
+    objs, log = [], []
+    jobs = []   # the units compile side by side
+    for src, own in UNITS:
+        obj = f"{tmp}.{os.path.splitext(os.path.basename(src))[0]}.o"
+        objs.append(obj)
+        cmd = [HIPCC, *FLAGS, *own, *extra, "-c", src, "-o", obj]
+        jobs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    for cmd, job in jobs:
+        _check(job.communicate()[0], job.returncode, log)
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *extra, *objs, "-o", tmp], log)
+    for obj in objs:
+        os.remove(obj)
+    if verbose and log:
+        print("\n".join(log), file=sys.stderr)
     os.replace(tmp, lib)
     return lib
+
+
+def _run(cmd, log):
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    _check(res.stdout + res.stderr, res.returncode, log)
+
+
+def _check(text, rc, log):
+    out = "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l)
+    if rc != 0:
+        raise RuntimeError(f"hipcc failed ({rc}):\n{out}")
+    if out.strip():
+        log.append(out)
 
 
 if __name__ == "__main__":

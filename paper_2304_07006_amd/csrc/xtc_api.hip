@@ -8,6 +8,8 @@
 //   rho_lp [NS][ngp/8][ldL][8]        reduced-precision rho (k8-packed), prec != FP64
 //   rho_occ[ldO/tw][ngp][tw], colmap[ldO]  FP64 rho of the occupied-occupied pairs
 //                                     (column tiles of tw = 16 occNB pairs)
+//   stg, amax                         digit stage blocks and per-pair largest |rho|
+//                                     of the integer occupied block (occ_i8.h)
 //   M      [ldP][ldP] doubles         FP64 accumulator of the two-body term
 //   h1acc  [ldP] doubles              FP64 accumulator of the one-body term
 //   T1     [kT1Split][ldP] doubles    per-split partials (one-body, term 1)
@@ -54,6 +56,7 @@
 #include "kernels_bwd.h"
 #include "kernels_lowdin.h"
 #include "kernels_prepare.h"
+#include "occ_i8.h"
 
 using namespace xtc;
 
@@ -110,9 +113,12 @@ struct Layout {
     int N, Ng, nocc, ldP, ngp, Npair, prec;
     int form, ns, es, ldL, ldO, nOP, occNB, nsegK, nspin, ldN, segK, segM;
     int nY;              // adjoint Y slots: Cbar (3), then Abar, Bbar (4) per spin channel
+    OccI8Plan i8;        // column tiling of the integer occupied block
+    bool i8ok;           // the grid fits its int32 segments (else the FP64 block serves)
+    int ldK8;            // row stride of its segment partials (16 i8.nct8)
     bool tc2;
     bool bwd;
-    size_t pos, rho, rho_lp, rho_occ, colmap, M, h1acc, T1, E, gacc, occw, kidx, rhoR, GsL, Atc, Btc, GT;
+    size_t pos, rho, rho_lp, rho_occ, colmap, stg, amax, M, h1acc, T1, E, gacc, occw, kidx, rhoR, GsL, Atc, Btc, GT;
     size_t fixed;        // bytes of everything that does not scale with the chunk rows (plus reserves)
     size_t chunk0;       // offset of the first chunk buffer (S)
     size_t per_row;      // bytes per chunk row (without the K-build partials)
@@ -165,6 +171,9 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.nOP = pb->nocc * (pb->nocc + 1) / 2;
     L.occNB = occ_blocks(L.nOP);
     L.ldO = (int)align_up((size_t)L.nOP, (size_t)16 * L.occNB);
+    L.i8 = occ_i8_plan(L.nOP);
+    L.i8ok = L.ngp <= occ_i8_max_points(kOccSegMax);
+    L.ldK8 = 16 * L.i8.nct8;
     L.segK = L.form == 1 ? kSegKF32 : kSegK;
     L.segM = L.form == 1 ? kSegMF32 : kSegM;
     L.nsegK = (L.ngp + L.segK - 1) / L.segK;
@@ -179,6 +188,9 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.rho_lp = off;  off = align_up(off + (lp ? (size_t)L.ns * L.ngp * L.ldL * L.es : 0), kAlign);
     L.rho_occ = off; off = align_up(off + (lp ? (size_t)L.ngp * L.ldO * sizeof(double) : 0), kAlign);
     L.colmap = off;  off = align_up(off + (lp ? (size_t)L.ldO * sizeof(int) : 0), kAlign);
+    const bool i8 = lp && L.i8ok;
+    L.stg = off;     off = align_up(off + (i8 ? occ_i8_stage_bytes(L.i8, L.ngp) : 0), kAlign);
+    L.amax = off;    off = align_up(off + (i8 ? (size_t)L.ldK8 * sizeof(double) : 0), kAlign);
     L.M = off;       off = align_up(off + (size_t)L.nspin * L.ldP * L.ldP * sizeof(double), kAlign);
     L.h1acc = off;   off = align_up(off + (size_t)L.nspin * L.ldP * sizeof(double), kAlign);
     L.T1 = off;      off = align_up(off + (size_t)kT1Split * L.ldP * sizeof(double), kAlign);
@@ -207,7 +219,7 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.chunk0 = off;
     L.fixed = off + (size_t)kMSegGroup * mslab + (L.bwd ? gslab : 0) + 16 * kAlign;
     L.per_row = (size_t)L.nspin * (8 * sizeof(double) + (size_t)4 * L.ldP * sizeof(double));
-    if (lp) L.per_row += (size_t)kOccSegMax * 3 * L.ldO * sizeof(double);
+    if (lp) L.per_row += (size_t)kOccSegMax * 3 * std::max(L.ldO, L.ldK8) * sizeof(double);
     if (lp) L.per_row += L.cdw * L.ns * L.es;
     L.kpart_row = lp ? (size_t)L.nsegK * 3 * L.ldL * sizeof(float) : 0;
     L.kcap_max = lp ? (int)std::max<size_t>(kKpartQuant, kKpartBudget / L.kpart_row / kKpartQuant * kKpartQuant) : 0;
@@ -247,7 +259,8 @@ void place_chunk(Layout& L, size_t bytes) {
     L.Kpart = off;   off = align_up(off + (lp ? (size_t)L.kcap * L.kpart_row : 0), kAlign);
     L.CDlp = off;    off = align_up(off + (lp ? L.cdw * L.ns * cap * L.es : 0), kAlign);
     L.Mpart = off;   off = align_up(off + (size_t)kMSegGroup * L.mslab, kAlign);
-    L.Kocc = off;    off = align_up(off + (lp ? (size_t)kOccSegMax * 3 * cap * L.ldO * sizeof(double) : 0), kAlign);
+    L.Kocc = off;    off = align_up(off + (lp ? (size_t)kOccSegMax * 3 * cap * std::max(L.ldO, L.ldK8) * sizeof(double) : 0),
+                                    kAlign);
     const bool b = L.bwd;
     L.Kc = off;      off = align_up(off + (b ? (size_t)3 * cap * L.ldP * sizeof(double) : 0), kAlign);
     L.Y = off;       off = align_up(off + (b ? (size_t)L.nY * cap * L.ldP * sizeof(double) : 0), kAlign);
@@ -452,24 +465,12 @@ void launch_build_lp(const Layout& L, int g0, int rows, const JasDev& J, void* w
                        L.segK, J, at<float>(ws, L.Kpart), L.kcap, L.ldP, n_ct, L.nsegK);
 }
 
-// Segments of the g' sum for a grid of `tiles` workgroups per segment: the
-// fewest, from 4, whose last round of workgroups keeps at least 90% of the
-// `slots` resident workgroups busy (equal-work workgroups finish in rounds,
-// and a short last round idles the rest of the chip), else the best found.
-int occ_segments(long tiles, long slots) {
-    int best = 4;
-    double best_eff = 0.0;
-    for (int ns = 4; ns <= kOccSegMax; ++ns) {
-        const long t = tiles * ns;
-        const double eff = (double)t / (double)(((t + slots - 1) / slots) * slots);
-        if (eff >= 0.9) return ns;
-        if (eff > best_eff) {
-            best_eff = eff;
-            best = ns;
-        }
-    }
-    return best;
-}
+// Segments of the g' sum of the FP64 occupied block for a grid of `tiles`
+// workgroups per segment: the fewest, from 4, whose last round of workgroups
+// keeps at least 90% of the `slots` resident workgroups busy (equal-work
+// workgroups finish in rounds, and a short last round idles the rest of the
+// chip), else the best found.
+int occ_segments(long tiles, long slots) { return balanced_segments(tiles, slots, 4, kOccSegMax); }
 
 // Launch the FP64 occupied block with the segment count from the kernel's
 // occupancy on the current device; returns that count (0 on a HIP error).
@@ -537,23 +538,39 @@ xtc_status build_lp_pieces(const Layout& L, int g0, int rows, const JasDev& J, d
     return XTC_OK;
 }
 
-xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double* K, bool occ64, void* ws,
+// How the occupied-occupied pairs of K are computed in the reduced forms.
+enum OccMode {
+    kOccReduced = 0,   // left in the reduced arithmetic (XTC_K_REDUCED_OCC)
+    kOccExact = 1,     // integer-sliced block if the grid fits it, else FP64 MFMA
+    kOccFP64 = 2       // FP64 MFMA block (XTC_K_OCC_FP64)
+};
+
+xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double* K, int occ, void* ws,
                       hipStream_t st) {
     xtc_status s;
     if ((s = build_lp_pieces<3>(L, g0, rows, J, K, ws, st)) != XTC_OK) return s;
-    if (!occ64) return XTC_OK;
-    // occupied-occupied pairs in FP64, written over the reduced-precision values:
+    if (occ == kOccReduced) return XTC_OK;
+    // occupied-occupied pairs, written over the reduced-precision values:
     // segments of the sum over g' (enough, and evenly enough, to fill the chip),
     // FP64 partials, then a fixed-order reduction scattered into K
-    const int n_rt = (rows + kKRows - 1) / kKRows;
-    const int nseg = J.kind == 0 ? launch_build_occ<0>(L, g0, rows, n_rt, J, ws, st)
-                                 : launch_build_occ<1>(L, g0, rows, n_rt, J, ws, st);
-    if (nseg == 0) return fail(XTC_E_HIP, "occupancy query of the occupied-block kernel failed");
-    if ((s = launched("build_K_occ_f64")) != XTC_OK) return s;
     double* part = at<double>(ws, L.Kocc);
+    int nseg = 0, ldK = L.ldO;
+    if (occ == kOccExact && L.i8ok) {
+        ldK = L.ldK8;
+        nseg = occ_i8_build(at<d4>(ws, L.pos), at<void>(ws, L.stg), L.i8, L.ngp, g0, rows, J,
+                            at<unsigned long long>(ws, L.amax), part, ldK, kOccSegMax, st);
+        if (nseg == 0) return fail(XTC_E_HIP, "integer occupied block: %s", hipGetErrorString(hipGetLastError()));
+        if ((s = launched("build_K_occ_i8")) != XTC_OK) return s;
+    } else {
+        const int n_rt = (rows + kKRows - 1) / kKRows;
+        nseg = J.kind == 0 ? launch_build_occ<0>(L, g0, rows, n_rt, J, ws, st)
+                           : launch_build_occ<1>(L, g0, rows, n_rt, J, ws, st);
+        if (nseg == 0) return fail(XTC_E_HIP, "occupancy query of the occupied-block kernel failed");
+        if ((s = launched("build_K_occ_f64")) != XTC_OK) return s;
+    }
     const size_t nel = (size_t)3 * rows * L.nOP;
     hipLaunchKernelGGL(k_reduce_occ, dim3((unsigned)std::min<size_t>((nel + 255) / 256, 8192)), dim3(256), 0, st, part,
-                       nseg, rows, L.ldO, at<int>(ws, L.colmap), L.nOP, L.ldP, K);
+                       nseg, rows, ldK, at<int>(ws, L.colmap), L.nOP, L.ldP, K);
     return launched("reduce_occ");
 }
 
@@ -690,9 +707,9 @@ xtc_status xg_group(const __bf16* X, size_t a_comp, size_t a_split, int rows, co
     return launched("gemm_xg_bf16");
 }
 
-xtc_status build_K_any(const Layout& L, const JasDev& J, int g0, int rows, double* K, bool occ64, void* ws,
+xtc_status build_K_any(const Layout& L, const JasDev& J, int g0, int rows, double* K, int occ, void* ws,
                        hipStream_t st) {
-    if (L.form != 0) return build_K_lp(L, g0, rows, J, K, occ64, ws, st);
+    if (L.form != 0) return build_K_lp(L, g0, rows, J, K, occ, ws, st);
     const int n_rt = (rows + kKRows - 1) / kKRows;
     const int n_ct = L.ldP / 128;
     const dim3 grid(n_rt * n_ct);
@@ -752,6 +769,12 @@ xtc_status xtc_prepare(const xtc_problem* pb, int32_t prec, int32_t chunk_rows, 
         hipLaunchKernelGGL(k_gather_occ, dim3(4096), dim3(256), 0, st, at<double>(ws, L.rho), L.ldP, L.ngp,
                            at<int>(ws, L.colmap), L.ldO, 16 * L.occNB, at<double>(ws, L.rho_occ));
         if ((s = launched("gather_occ")) != XTC_OK) return s;
+        if (L.i8ok) {
+            if ((s = fill(at<double>(ws, L.amax), (size_t)L.ldK8, st)) != XTC_OK) return s;
+            if (occ_i8_prepare(at<double>(ws, L.rho_occ), at<d4>(ws, L.pos), L.ngp, 16 * L.occNB, L.nOP, L.i8,
+                               at<unsigned long long>(ws, L.amax), at<void>(ws, L.stg), st) != hipSuccess)
+                return fail(XTC_E_HIP, "occ_i8_prepare: %s", hipGetErrorString(hipGetLastError()));
+        }
         // the adjoint's Pi operand: k-packed splits of rho (FP32: row-major)
         if (L.bwd && L.form == 1 &&
             (s = split_rows_any(L.form, at<double>(ws, L.rho), (size_t)L.ngp * L.ldP, at<void>(ws, L.rhoR),
@@ -779,8 +802,10 @@ xtc_status xtc_build_K(const xtc_problem* pb, const xtc_jastrow* jas, int32_t g0
                        double* K, void* ws, size_t ws_bytes, void* stream) {
     xtc_status s;
     JasDev J;
-    const bool occ64 = !(prec & XTC_K_REDUCED_OCC);
-    prec &= ~XTC_K_REDUCED_OCC;
+    if ((prec & XTC_K_REDUCED_OCC) && (prec & XTC_K_OCC_FP64))
+        return fail(XTC_E_ARG, "prec: XTC_K_REDUCED_OCC and XTC_K_OCC_FP64 together");
+    const int occ = (prec & XTC_K_REDUCED_OCC) ? kOccReduced : (prec & XTC_K_OCC_FP64) ? kOccFP64 : kOccExact;
+    prec &= ~(XTC_K_REDUCED_OCC | XTC_K_OCC_FP64);
     if ((s = check_problem(pb)) != XTC_OK) return s;
     if ((s = check_prec(prec)) != XTC_OK) return s;
     if ((s = check_jastrow(jas, &J)) != XTC_OK) return s;
@@ -790,7 +815,7 @@ xtc_status xtc_build_K(const xtc_problem* pb, const xtc_jastrow* jas, int32_t g0
     place_chunk(L, ws_bytes);
     if ((s = check_ws(L, ws, ws_bytes)) != XTC_OK) return s;
     if ((s = check_range(L, g0, g1)) != XTC_OK) return s;
-    return build_K_any(L, J, g0, g1 - g0, K, occ64, ws, (hipStream_t)stream);
+    return build_K_any(L, J, g0, g1 - g0, K, occ, ws, (hipStream_t)stream);
 }
 
 xtc_status xtc_contract_2body(const xtc_problem* pb, const double* K, int32_t g0, int32_t g1, int32_t prec,
@@ -962,7 +987,7 @@ xtc_status xtc_backward(const xtc_problem* pb, const xtc_jastrow* jas, int32_t p
     for (int g0 = 0; g0 < L.Ng; g0 += L.cap) {
         const int rows = std::min(L.cap, L.Ng - g0);
         const bool last = g0 + rows >= L.Ng;
-        if ((s = build_K_any(L, J, g0, rows, Kc, true, ws, st)) != XTC_OK) return s;
+        if ((s = build_K_any(L, J, g0, rows, Kc, kOccExact, ws, st)) != XTC_OK) return s;
         if ((s = run_intermediates(L, pb, Kc, g0, g0 + rows, ws, st)) != XTC_OK) return s;
         const double* rho_rows = at<double>(ws, L.rho) + (size_t)g0 * L.ldP;
         const size_t kstride = (size_t)rows * L.ldP;

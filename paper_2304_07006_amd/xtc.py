@@ -22,6 +22,7 @@ XTC_RESET, XTC_FINALIZE, XTC_REUSE_INTERMEDIATES = 1, 2, 4
 XTC_WITH_BACKWARD = 0x10
 XTC_WITH_TC2 = 0x20
 XTC_K_REDUCED_OCC = 0x40
+XTC_K_OCC_FP64 = 0x80
 PRECISIONS = {"fp64": XTC_FP64, "fp32": XTC_FP32, "bf16x3": XTC_BF16X3, "bf16x6": XTC_BF16X6}
 
 

@@ -216,6 +216,27 @@ def test_reduced_occ_flag_only_for_build_K(lib):
     assert st == xtc.XTC_E_ARG and "rows" in xtc.last_error()
 
 
+def test_occ_fp64_flag_only_for_build_K(lib):
+    """XTC_K_OCC_FP64 (the FP64 occupied block instead of the integer one) is
+    a per-call option of xtc_build_K like XTC_K_REDUCED_OCC, and the two
+    exclude each other."""
+    c, keep = _problem()
+    assert lib.xtc_workspace_size(ctypes.byref(c), xtc.XTC_BF16X3 | xtc.XTC_K_OCC_FP64, 50) == 0
+    n = lib.xtc_workspace_size(ctypes.byref(c), xtc.XTC_BF16X3, 50)
+    st = lib.xtc_contract_1body_0body(ctypes.byref(c), ctypes.c_void_p(0x2000), 0, 10,
+                                      xtc.XTC_BF16X3 | xtc.XTC_K_OCC_FP64, 0, None, None,
+                                      ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG
+    j = _jas(kind=0)
+    st = lib.xtc_build_K(ctypes.byref(c), ctypes.byref(j), 5, 5, xtc.XTC_BF16X3 | xtc.XTC_K_OCC_FP64,
+                         ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG and "rows" in xtc.last_error()
+    st = lib.xtc_build_K(ctypes.byref(c), ctypes.byref(j), 0, 10,
+                         xtc.XTC_BF16X3 | xtc.XTC_K_OCC_FP64 | xtc.XTC_K_REDUCED_OCC,
+                         ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000), n, None)
+    assert st == xtc.XTC_E_ARG and "together" in xtc.last_error()
+
+
 def test_workspace_grows_with_chunk(lib):
     c, keep = _problem(N=16, Ng=1000, occ=(0, 3, 5))
     a = lib.xtc_workspace_size(ctypes.byref(c), 0, 100)

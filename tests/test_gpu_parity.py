@@ -83,22 +83,28 @@ def test_tiny_K_entries(torch_cuda):
 
 
 def test_reduced_occ_option(torch_cuda):
-    """xtc_build_K in split BF16 with and without XTC_K_REDUCED_OCC: the pairs
-    outside the occupied-occupied block are bitwise the same, the block itself
-    is FP64 (= the FP64 build to summation noise) only without the option."""
+    """xtc_build_K in split BF16 with XTC_K_REDUCED_OCC, XTC_K_OCC_FP64 and
+    neither: the pairs outside the occupied-occupied block are bitwise the
+    same; the block is the FP64 build to summation noise with XTC_K_OCC_FP64,
+    within the integer block's 2^-30 of max|K| by default (its own tests
+    hold it there against exact sums), and in the reduced arithmetic only
+    with XTC_K_REDUCED_OCC."""
     from paper_2304_07006_amd import xtc
     p = inputs.make_workload("N64-occ8-Ng50k", Ng=3001)
-    _note("case: N64-occ8-Ng3001 K rows [500,1800) bf16x3 with / without XTC_K_REDUCED_OCC")
+    _note("case: N64-occ8-Ng3001 K rows [500,1800) bf16x3 default / XTC_K_OCC_FP64 / XTC_K_REDUCED_OCC")
     K64 = _K(p, 500, 1800)
     Kf = _K(p, 500, 1800, prec="bf16x3")
+    K8 = _K(p, 500, 1800, prec="bf16x3", kflags=xtc.XTC_K_OCC_FP64)
     Kr = _K(p, 500, 1800, prec="bf16x3", kflags=xtc.XTC_K_REDUCED_OCC)
     N = p.N
     occ = sorted(int(k) for k in p.occ)
     cols = [a * N - a * (a - 1) // 2 + (b - a) for i, a in enumerate(occ) for b in occ[i:]]
     other = np.setdiff1d(np.arange(K64.shape[2]), cols)
     assert np.array_equal(Kf[:, :, other], Kr[:, :, other])
+    assert np.array_equal(K8[:, :, other], Kr[:, :, other])
     scale = np.abs(K64).max()
-    assert np.abs(Kf[:, :, cols] - K64[:, :, cols]).max() < 1e-13 * scale
+    assert np.abs(K8[:, :, cols] - K64[:, :, cols]).max() < 1e-13 * scale
+    assert np.abs(Kf[:, :, cols] - K64[:, :, cols]).max() < 2.0**-30 * scale
     er = np.abs(Kr[:, :, cols] - K64[:, :, cols]).max()
     _note(f"  reduced occupied block: max |dK| {er:.2e} (max |K| {scale:.2e})")
     assert 0 < er < 2.0**-16 * scale
