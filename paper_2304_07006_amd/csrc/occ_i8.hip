@@ -19,8 +19,20 @@ long occ_i8_max_points(int max_seg) { return (long)max_seg * kI8SegMax; }
 
 double occ_i8_dscale(const JasDev& J) {
     if (J.kind == 0) return 1.0;
-    double u = 0.0;
-    for (int k = 0; k < 16; ++k) u += std::fabs(J.dcoef[k]);
+    // u'(r) = g(t) = p(t) (1 - t)^2 with t = r/(1+r) in [0, 1) and
+    // p(t) = sum_k dcoef[k] t^k.  |g| is bounded by its largest value on a
+    // grid of spacing h = 1/4096 plus h/2 times a Lipschitz bound of g on
+    // [0, 1]: |g'| = |p' (1-t)^2 - 2 p (1-t)| <= sum_k (k + 2) |dcoef[k]|.
+    constexpr int kGrid = 4096;
+    double lip = 0.0, gmax = 0.0;
+    for (int k = 0; k < 16; ++k) lip += (k + 2) * std::fabs(J.dcoef[k]);
+    for (int i = 0; i <= kGrid; ++i) {
+        const double t = (double)i / kGrid;
+        double p = J.dcoef[15];
+        for (int k = 14; k >= 0; --k) p = p * t + J.dcoef[k];
+        gmax = std::max(gmax, std::fabs(p) * (1.0 - t) * (1.0 - t));
+    }
+    const double u = (gmax + 0.5 * lip / kGrid) * (1.0 + 1e-12);   // + the rounding of this evaluation
     if (!(u > 0.0)) return 1.0;
     int e = 0;
     const double f = std::frexp(2.0 * u, &e);   // 2u = f 2^e, f in [0.5, 1)

@@ -87,7 +87,9 @@ def _pair(a, b, N):
 
 def test_full_size_K_entries(torch_cuda, problem):
     """One bench-sized chunk of K in FP64 and split BF16 x3 against exact grid
-    sums (math.fsum over all 150 000 g') of sampled entries."""
+    sums (math.fsum over all 150 000 g') of sampled entries: FP64 to summation
+    noise, the split form's BF16 pairs to 2^-15 of the sum of |terms|, its
+    occupied-occupied pairs to the integer-sliced block's worst-case bound."""
     from oracle import explicit as ex
     from paper_2304_07006_amd import xtc
     p = problem
@@ -112,17 +114,29 @@ def test_full_size_K_entries(torch_cuda, problem):
     samples = [(int(rng.integers(0, g1 - g0)), *sorted(int(x) for x in rng.integers(0, N, 2))) for _ in range(20)]
     samples += [(int(rng.integers(0, g1 - g0)), *sorted(int(x) for x in rng.choice(occ, 2))) for _ in range(8)]
     worst = {"fp64": 0.0, "bf16x3": 0.0}
+    assert p.jastrow.kind == "pade"     # |d^x| <= |u'| <= 1/2: the integer block's d scale is 1
     for g, a, b in samples:
         e = ex.exact_K_entry(p.xyz, p.w, p.phi, p.jastrow, g0 + g, a, b)
         d = ex.grad1(p.xyz[g0 + g:g0 + g + 1], p.xyz, p.jastrow)[:, 0, :]
-        bound = np.abs(d * (p.w * p.phi[a] * p.phi[b])).sum(axis=1)        # sum of |terms|
+        rho = p.w * p.phi[a] * p.phi[b]
+        bound = np.abs(d * rho).sum(axis=1)        # sum of |terms|
         P = _pair(a, b, N)
         both_occ = a in occ and b in occ
         for prec, K in Ks.items():
             err = np.abs(K[:, g, P] - e)
-            # FP64 (and the FP64 occupied block of the split form): summation
-            # noise; split BF16 x3: 2^-16 per product, bounded by 2^-15 sum|terms|
-            tol = 1e-13 * (1.0 + bound) if (prec == "fp64" or both_occ) else 2.0**-15 * bound + 1e-15
+            if prec == "fp64":                     # summation noise
+                tol = 1e-13 * (1.0 + bound)
+            elif both_occ:
+                # integer-sliced block: d and rho as six digits against the scales
+                # S_d = 1 and S_P = the power of two above 2 max|rho_P|, each
+                # within 2^-43 of its scale, and the left-out digit products
+                # (order >= 8, digits <= 64 in magnitude) below 2.87e-13 S_d S_P
+                # per point; plus summation noise
+                S_P = np.ldexp(1.0, np.frexp(np.abs(rho).max())[1] + 1)
+                tol = (1e-13 * (1.0 + bound) + 2.0**-43 * (np.abs(rho).sum() + S_P * np.abs(d).sum(axis=1))
+                       + 2.87e-13 * S_P * np.count_nonzero(rho))
+            else:                                  # split BF16 x3: 2^-16 per product
+                tol = 2.0**-15 * bound + 1e-15
             assert np.all(err <= tol), (prec, g, a, b, err, tol)
             worst[prec] = max(worst[prec], float((err / (bound + 1e-300)).max()))
     _note(f"  max |dK| / sum|terms|: fp64 {worst['fp64']:.2e}, bf16x3 {worst['bf16x3']:.2e}")
