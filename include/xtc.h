@@ -71,7 +71,8 @@ typedef enum {
  * each operand within 2^-43 of its scale, the digit products of order 8 and
  * up left out: about sqrt(Ng) 2^-44 of the scales' product per entry, with
  * random sign), or in FP64 arithmetic (XTC_K_OCC_FP64 on xtc_build_K, and
- * for grids above 2^21 points). */
+ * for more than 144 occupied pairs, i.e. more than 16 occupied orbitals, or
+ * grids above 2^21 points). */
 typedef enum { XTC_FP64 = 0, XTC_FP32 = 1, XTC_BF16X3 = 2, XTC_BF16X6 = 3 } xtc_prec;
 
 /* OR-ed into prec: lay the workspace out for xtc_backward as well (extra

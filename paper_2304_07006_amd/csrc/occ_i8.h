@@ -9,7 +9,9 @@
 namespace xtc {
 
 // Column tiling of nOP occupied pairs: groups of ct 16-pair tiles (ct <= 9,
-// the accumulators one wave holds), nct8 = groups x ct tiles in all.
+// the accumulators one wave holds), nct8 = groups x ct tiles in all.  The
+// library uses the block for one group only (more regenerate d's digits
+// once per group and measured slower than the FP64 block).
 struct OccI8Plan {
     int ct, groups, nct8;
 };

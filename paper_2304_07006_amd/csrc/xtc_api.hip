@@ -114,7 +114,7 @@ struct Layout {
     int form, ns, es, ldL, ldO, nOP, occNB, nsegK, nspin, ldN, segK, segM;
     int nY;              // adjoint Y slots: Cbar (3), then Abar, Bbar (4) per spin channel
     OccI8Plan i8;        // column tiling of the integer occupied block
-    bool i8ok;           // the grid fits its int32 segments (else the FP64 block serves)
+    bool i8ok;           // one column group and the grid fits its int32 segments (else the FP64 block serves)
     int ldK8;            // row stride of its segment partials (16 i8.nct8)
     bool tc2;
     bool bwd;
@@ -172,7 +172,10 @@ Layout make_layout(const xtc_problem* pb, int prec) {
     L.occNB = occ_blocks(L.nOP);
     L.ldO = (int)align_up((size_t)L.nOP, (size_t)16 * L.occNB);
     L.i8 = occ_i8_plan(L.nOP);
-    L.i8ok = L.ngp <= occ_i8_max_points(kOccSegMax);
+    // the integer block serves one column group (at most 144 occupied pairs):
+    // with two, each of them regenerates d's digits, and at N=160 with 20
+    // occupied orbitals it measured slower than the FP64 block
+    L.i8ok = L.ngp <= occ_i8_max_points(kOccSegMax) && L.i8.groups == 1;
     L.ldK8 = 16 * L.i8.nct8;
     L.segK = L.form == 1 ? kSegKF32 : kSegK;
     L.segM = L.form == 1 ? kSegMF32 : kSegM;

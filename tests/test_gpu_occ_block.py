@@ -1,8 +1,9 @@
 """The occupied-occupied block of K in the reduced forms, computed by default
 from exact integer products of six-digit fixed-point operands (int8 MFMA,
-int32 sums): against the FP64 MFMA block (XTC_K_OCC_FP64), the FP64 build
-and exact sums of the definition, over one and several column groups, one
-and many int32 segments, ragged row ranges and both Jastrow forms.
+int32 sums; up to 144 occupied pairs, one column group): against the FP64
+MFMA block (XTC_K_OCC_FP64), the FP64 build and exact sums of the
+definition, over one to nine column tiles, one and many int32 segments,
+ragged row ranges and both Jastrow forms; above 144 pairs the FP64 block.
 
 Tolerance: each operand is within 2^-43 of its power-of-two scale, and the
 digit products left out (order 8 and up) add about 2^-44 S_d S_P per grid
@@ -52,19 +53,19 @@ def _occ_cols(p):
     return [a * N - a * (a - 1) // 2 + (b - a) for i, a in enumerate(occ) for b in occ[i:]]
 
 
-# (N, nocc, Ng, centres, Jastrow, g0, g1): 36 pairs in 3 tiles (one group);
-# 153 pairs in 2 groups of 5 tiles (power Jastrow); 210 pairs in 2 groups of
-# 7 tiles (the N=160, 20-occupied tiling); 10 pairs on 300 000 points
-# (5 int32 segments of at most 65 536 points)
+# (N, nocc, Ng, centres, Jastrow, g0, g1): 36 pairs in 3 tiles; 91 pairs in
+# 6 tiles (power Jastrow; an even tile count: stage blocks padded to 4 KB);
+# 136 pairs in 9 tiles (the most one group holds, the N=128 tiling); 10 pairs
+# on 300 000 points (5 int32 segments of at most 65 536 points)
 CASES = [
     (64, 8, 3001, 8, "pade", 500, 1800),
-    (24, 17, 2501, 6, "power16", 37, 1190),
-    (40, 20, 2048, 5, "pade", 0, 2048),
+    (24, 13, 2501, 6, "power16", 37, 1190),
+    (40, 16, 2048, 5, "pade", 0, 2048),
     (16, 4, 300000, 4, "pade", 123457, 123532),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=["N64-occ8", "N24-occ17-power", "N40-occ20", "N16-occ4-Ng300k"])
+@pytest.mark.parametrize("case", CASES, ids=["N64-occ8", "N24-occ13-power", "N40-occ16", "N16-occ4-Ng300k"])
 def test_integer_block_against_fp64_block(torch_cuda, case):
     from paper_2304_07006_amd import xtc
     N, nocc, Ng, nc, jk, g0, g1 = case
@@ -80,6 +81,18 @@ def test_integer_block_against_fp64_block(torch_cuda, case):
     _note(f"  max |dK| {e:.2e} = {e / scale:.2e} of max |K_occ| {scale:.2e}")
     assert np.all(np.isfinite(Ki))
     assert e < TOL_REL * scale
+
+
+def test_more_than_one_column_group_uses_the_fp64_block(torch_cuda):
+    """Above 144 occupied pairs (17 occupied orbitals: 153) the reduced forms'
+    occupied block is the FP64 one: the default K equals the XTC_K_OCC_FP64 K
+    bitwise."""
+    from paper_2304_07006_amd import xtc
+    p = inputs.make_problem(24, 17, 1500, 6, "chain", "power16", seed=63)
+    _note("case: N24 occ17 Ng1500 power: default occupied block = FP64 block")
+    Ki = _K(p, 100, 900, "bf16x3")
+    Kf = _K(p, 100, 900, "bf16x3", kflags=xtc.XTC_K_OCC_FP64)
+    assert np.array_equal(Ki, Kf)
 
 
 def test_integer_block_against_fp64_build_and_exact_sums(torch_cuda):
