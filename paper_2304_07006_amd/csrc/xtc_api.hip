@@ -562,7 +562,11 @@ xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double
         ldK = L.ldK8;
         nseg = occ_i8_build(at<d4>(ws, L.pos), at<void>(ws, L.stg), L.i8, L.ngp, g0, rows, J,
                             at<unsigned long long>(ws, L.amax), part, ldK, kOccSegMax, st);
-        if (nseg == 0) return fail(XTC_E_HIP, "integer occupied block: %s", hipGetErrorString(hipGetLastError()));
+        if (nseg == 0) {
+            const hipError_t e = hipGetLastError();   // 0 segments without a HIP error: a layout check failed
+            return e != hipSuccess ? fail(XTC_E_HIP, "integer occupied block: %s", hipGetErrorString(e))
+                                   : fail(XTC_E_UNSUPPORTED, "integer occupied block: grid or rows outside its range");
+        }
         if ((s = launched("build_K_occ_i8")) != XTC_OK) return s;
     } else {
         const int n_rt = (rows + kKRows - 1) / kKRows;
