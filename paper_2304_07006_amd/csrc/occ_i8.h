@@ -24,7 +24,8 @@ long occ_i8_max_points(int max_seg);
 // Power-of-two scale S_d >= 2 max|d^x| for the Jastrow (|d^x| <= |u'(r)|):
 // 1 for Pade (u' = 1/(2 (1 + b r)^2) <= 1/2), else the power of two at or
 // above twice a bound of |u'| = |p(t)| (1-t)^2 over t = r/(1+r) in [0, 1)
-// (its largest value on a fine grid plus a Lipschitz margin).
+// (its largest value on a fine grid plus a Lipschitz margin); 0 when that
+// bound is not finite (the FP64 block then serves).
 double occ_i8_dscale(const JasDev& J);
 
 // The fewest segments in [lo, hi] whose last round of `tiles` equal-work

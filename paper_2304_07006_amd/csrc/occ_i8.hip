@@ -33,6 +33,7 @@ double occ_i8_dscale(const JasDev& J) {
         gmax = std::max(gmax, std::fabs(p) * (1.0 - t) * (1.0 - t));
     }
     const double u = (gmax + 0.5 * lip / kGrid) * (1.0 + 1e-12);   // + the rounding of this evaluation
+    if (!(u < 1e300)) return 0.0;   // no usable bound (coefficients near the FP64 range)
     if (!(u > 0.0)) return 1.0;
     int e = 0;
     const double f = std::frexp(2.0 * u, &e);   // 2u = f 2^e, f in [0.5, 1)

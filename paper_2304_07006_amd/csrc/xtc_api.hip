@@ -558,7 +558,7 @@ xtc_status build_K_lp(const Layout& L, int g0, int rows, const JasDev& J, double
     // FP64 partials, then a fixed-order reduction scattered into K
     double* part = at<double>(ws, L.Kocc);
     int nseg = 0, ldK = L.ldO;
-    if (occ == kOccExact && L.i8ok) {
+    if (occ == kOccExact && L.i8ok && occ_i8_dscale(J) > 0.0) {
         ldK = L.ldK8;
         nseg = occ_i8_build(at<d4>(ws, L.pos), at<void>(ws, L.stg), L.i8, L.ngp, g0, rows, J,
                             at<unsigned long long>(ws, L.amax), part, ldK, kOccSegMax, st);

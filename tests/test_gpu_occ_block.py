@@ -95,6 +95,20 @@ def test_more_than_one_column_group_uses_the_fp64_block(torch_cuda):
     assert np.array_equal(Ki, Kf)
 
 
+def test_power_jastrow_without_a_finite_scale_uses_the_fp64_block(torch_cuda):
+    """A power Jastrow whose |u'| bound is not finite in FP64 (a coefficient
+    of 1e300) gets no integer scale: its occupied pairs come from the FP64
+    block, bitwise equal to the XTC_K_OCC_FP64 build."""
+    from paper_2304_07006_amd import xtc
+    p = inputs.make_problem(24, 4, 1200, 6, "chain", "power16", seed=64)
+    p.jastrow = inputs.Jastrow("power", coef=(1e300,) + (0.0,) * 15)
+    _note("case: N24 occ4 Ng1200 power Jastrow with a 1e300 coefficient: FP64 occupied block")
+    cols = _occ_cols(p)
+    Ki = _K(p, 0, 600, "bf16x3")[:, :, cols]
+    Kf = _K(p, 0, 600, "bf16x3", kflags=xtc.XTC_K_OCC_FP64)[:, :, cols]
+    assert np.all(np.isfinite(Kf)) and np.array_equal(Ki, Kf)
+
+
 def test_integer_block_against_fp64_build_and_exact_sums(torch_cuda):
     """The block against the FP64 path's K (a separate kernel) and against
     exact (math.fsum) sums of the definition at sampled rows and pairs."""
