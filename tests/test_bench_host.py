@@ -81,3 +81,17 @@ def test_kernel_rooflines_from_per_step_totals():
     assert r["k_build_K_occ"]["peak_tflops"] == 78.6 and "frac" not in r["k_reduce_K"]
     assert abs(sum(e["share_of_step"] for e in r.values()) - 1.0) < 1e-12
     assert abs(r["k_build_K_lp"]["avg_ms"] - t_lp / 40 * 1e3) < 1e-9
+
+
+def test_integer_occupied_block_roofline():
+    """The integer occupied block is rated by its executed int8 work (21 digit
+    products per useful one over its 16-pair tiles) against the int8 peak,
+    with its useful FP64-class rate beside it."""
+    assert bench.occ_i8_columns(16) == 144          # 136 pairs: nine tiles
+    assert bench.occ_i8_columns(8) == 48            # 36 pairs: three tiles
+    assert bench.occ_i8_columns(17) == 160          # 153 pairs: two groups of five tiles
+    t = 0.27                                        # seconds per step
+    r = bench.kernel_rooflines({"k_build_K_occ_i8": (20, t)}, 128, 16, 150000, "bf16x3")["k_build_K_occ_i8"]
+    executed = 6 * 150000 ** 2 * 144 * 21
+    assert abs(r["tflops"] - executed / t / 1e12) < 1e-9 and r["peak_tflops"] == 5000.0
+    assert abs(r["useful_tflops"] - 6 * 150000 ** 2 * 136 / t / 1e12) < 1e-9
