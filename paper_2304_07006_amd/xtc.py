@@ -341,13 +341,15 @@ class Pass:
         n = 3 * (g1 - g0) * self.ldP
         return self.K.view(-1)[:n].view(3, g1 - g0, self.ldP)
 
-    def run(self, jas: XtcJastrow, two_body=True, one_body=True, stream=None):
+    def run(self, jas: XtcJastrow, two_body=True, one_body=True, stream=None, kflags=0):
+        """The pass over all chunks; kflags: options of xtc_build_K only
+        (XTC_K_OCC_FP64)."""
         xtc_prepare(self.dp, self.prec, self.chunk, self.ws, stream)
         ch = self.chunks()
         for i, (g0, g1) in enumerate(ch):
             flags = (XTC_RESET if i == 0 else 0) | (XTC_FINALIZE if i == len(ch) - 1 else 0)
             K = self.K_view(g0, g1)
-            xtc_build_K(self.dp, jas, g0, g1, self.prec, K, self.ws, stream)
+            xtc_build_K(self.dp, jas, g0, g1, self.prec | kflags, K, self.ws, stream)
             if two_body:
                 xtc_contract_2body(self.dp, K, g0, g1, self.prec, flags, self.V2, self.ws, stream)
             if one_body:
@@ -357,12 +359,14 @@ class Pass:
         return self.V2, self.h1, self.E0
 
 
-def forward(problem, prec="fp64", chunk_rows=None, device="cuda", jastrow=None):
-    """V2, h1, E0 (torch tensors on the device) for an inputs.Problem."""
+def forward(problem, prec="fp64", chunk_rows=None, device="cuda", jastrow=None, occ_fp64=False):
+    """V2, h1, E0 (torch tensors on the device) for an inputs.Problem.
+    occ_fp64: in the reduced forms, the occupied-occupied block of K with
+    FP64 MFMA (XTC_K_OCC_FP64) instead of the integer-sliced products."""
     dp = device_problem(problem.xyz, problem.w, problem.phi, problem.occ, device,
                         getattr(problem, "occ_n", None), getattr(problem, "occ_n_beta", None))
     ps = Pass(dp, PRECISIONS[prec] if isinstance(prec, str) else prec, chunk_rows, device)
-    V2, h1, E0 = ps.run(make_jastrow(jastrow or problem.jastrow))
+    V2, h1, E0 = ps.run(make_jastrow(jastrow or problem.jastrow), kflags=XTC_K_OCC_FP64 if occ_fp64 else 0)
     return V2, h1, E0
 
 

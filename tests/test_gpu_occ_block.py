@@ -145,3 +145,23 @@ def test_integer_block_is_the_same_in_every_reduced_form(torch_cuda):
     cols = _occ_cols(p)
     Ks = [_K(p, 100, 1333, f)[:, :, cols] for f in ("fp32", "bf16x3", "bf16x6")]
     assert np.array_equal(Ks[0], Ks[1]) and np.array_equal(Ks[1], Ks[2])
+
+
+def test_forward_with_either_occupied_block(torch_cuda):
+    """xtc.forward in split BF16 x3 with the integer (default) and the FP64
+    occupied block: both within the bars of the oracle, and within FP64-class
+    noise of each other (only the occupied block differs between them)."""
+    from oracle import factorised as fb
+    from paper_2304_07006_amd import xtc
+    p = inputs.make_problem(24, 5, 1500, 6, "chain", "pade", seed=65)
+    _note("case: N24 occ5 Ng1500 forward bf16x3 with the integer and the FP64 occupied block")
+    V2o, h1o, E0o = fb.closed_shell(p.xyz, p.w, p.phi, p.occ, p.jastrow)
+    outs = []
+    for occ_fp64 in (False, True):
+        V2, h1, E0 = (t.cpu().numpy() for t in xtc.forward(p, prec="bf16x3", chunk_rows=600, occ_fp64=occ_fp64))
+        assert np.abs(V2 - V2o).max() < 1e-6 and np.abs(h1 - h1o).max() < 1e-6 and abs(E0[0] - E0o) < 1e-8
+        outs.append((V2, h1, float(E0[0])))
+    (Vi, hi, Ei), (Vf, hf, Ef) = outs
+    _note(f"  integer vs FP64 block: |dV2| {np.abs(Vi - Vf).max():.2e} |dh1| {np.abs(hi - hf).max():.2e} "
+          f"|dE0| {abs(Ei - Ef):.2e}")
+    assert np.abs(Vi - Vf).max() < 1e-9 and np.abs(hi - hf).max() < 1e-10 and abs(Ei - Ef) < 1e-10
