@@ -1128,15 +1128,75 @@ __global__ __launch_bounds__(kPiThreads) void k_nt_bf16(const __bf16* __restrict
         }
         storeA(W);
     };
-    loadA(0);
-    loadB(0);
-    storeA(sA0);
-    __syncthreads();
-    for (int k = 0; k < ldk; k += 2 * kLpK) {
-        step(k, sA0, sA1);
+    if constexpr (FORM == 3 && NC == 3) {
+        // one barrier per two k-steps (four components have no registers for
+        // the second B operand): a stage multiplies the two LDS tiles
+        // of steps k and k + 1 while the tiles of k + 2 and k + 3 are written
+        // to the other two buffers (four statically named buffers, two stages
+        // per loop iteration); B of step k + 1 is loaded at the stage's start,
+        // B of step k + 2 (the next stage's first) between its two halves
+        __shared__ __attribute__((aligned(16))) ATile sA2;
+        __shared__ __attribute__((aligned(16))) ATile sA3;
+        bf8 aQ[kAPer], bQ[NB][NS];
+        auto loadA_to = [&](int k, bf8 (&dst)[kAPer]) {
+#pragma unroll
+            for (int i = 0; i < kAPer; ++i)
+                if (aon[i]) dst[i] = *(const bf8*)(asrc[i] + (size_t)min(k, ldk - kLpK) * rows);
+        };
+        auto storeA_from = [&](ATile& W, const bf8 (&src)[kAPer]) {
+#pragma unroll
+            for (int i = 0; i < kAPer; ++i)
+                if (aon[i]) *(bf8*)(&W[0][0][0][0] + adst[i]) = src[i];
+        };
+        auto loadB_to = [&](int k, bf8 (&dst)[NB][NS]) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+                    dst[b][s] = *(const bf8*)(bsrc[b] + s * b_split + (size_t)min(k, ldk - kLpK) * nB);
+        };
+        // stage over steps k, k + 1 from tiles R0, R1; tiles of k + 2, k + 3
+        // into W0, W1; bnext holds B of step k on entry and of step k + 2 on exit
+        auto stage2 = [&](int k, const ATile& R0, const ATile& R1, ATile& W0, ATile& W1) {
+            loadA_to(k + 2 * kLpK, apre);
+            loadA_to(k + 3 * kLpK, aQ);
+            bf8 bv[NB][NS];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) bv[b][s] = bnext[b][s];
+            loadB_to(k + kLpK, bQ);
+            multiply(R0, bv);
+            loadB_to(k + 2 * kLpK, bnext);
+            multiply(R1, bQ);
+            storeA_from(W0, apre);
+            storeA_from(W1, aQ);
+        };
+        loadA_to(0, apre);
+        loadA_to(kLpK, aQ);
+        loadB_to(0, bnext);
+        storeA_from(sA0, apre);
+        storeA_from(sA1, aQ);
         __syncthreads();
-        step(k + kLpK, sA1, sA0);
+        int k = 0;
+        for (; k + 4 * kLpK <= ldk; k += 4 * kLpK) {
+            stage2(k, sA0, sA1, sA2, sA3);
+            __syncthreads();
+            stage2(k + 2 * kLpK, sA2, sA3, sA0, sA1);
+            __syncthreads();
+        }
+        if (k < ldk) stage2(k, sA0, sA1, sA2, sA3);   // ldk = 64 mod 128: one more stage
+    } else {
+        loadA(0);
+        loadB(0);
+        storeA(sA0);
         __syncthreads();
+        for (int k = 0; k < ldk; k += 2 * kLpK) {
+            step(k, sA0, sA1);
+            __syncthreads();
+            step(k + kLpK, sA1, sA0);
+            __syncthreads();
+        }
     }
 
     if constexpr (!GRAD) {
