@@ -10,10 +10,11 @@
 // largest |rho_P(g')| of pair P.  With v = d / S_d (or rho / S_P) in
 // [-1/2, 1/2]:
 //   v = sum_{i=1..6} a_i 2^(-7 i) + e,   |e| <= 2^-43,
-// a_1 in [-64, 64], a_2..a_6 in [-64, 63] (digits centred on zero, so that
-// rounding and dropped terms carry no sign bias).  The digit products a_i b_j
-// with i + j <= 7 (21 of the 36) are summed exactly in int32, one
-// accumulator per order i + j; each dropped product is below 2^-49 S_d S_P.
+// a_1 and a_4 in [-64, 64], the others in [-64, 63] (digits centred on zero,
+// so that rounding and dropped terms carry no sign bias).  The digit products
+// a_i b_j with i + j <= 7 (21 of the 36) are summed exactly in int32, one
+// accumulator per order i + j; each dropped product is at most 2^-44 S_d S_P
+// and all of them together below 2.87e-13 S_d S_P.
 // The orders are combined in FP64 per segment of at most kI8SegMax grid
 // points (|an accumulator| <= 6 x 64 x 64 per point, < 2^31 over a segment),
 // and the segments are summed in FP64 afterwards.
